@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark of the smooth-convex rasterizer on one MI355X.
+
+A step is one training pass of the whole hot path over one synthetic view:
+forward render (preprocess, depth sort, binning, tile sort, ranges, per-tile
+compositing), the L1 loss gradient, and the backward render (per-tile reverse
+compositing, per-convex chain rule) to gradients for points, delta, sigma,
+opacity and SH.  Inputs are resident in HBM before the timed region.
+
+Default workload: 1M convexes (K=6, SH degree 3, 64-component mixture) at
+1920x1080, the paper-scale scene.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# VALU issue: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-operations/s for
+# full-rate ops (FP32 and FP64 FMA alike on this chip); a transcendental costs 4.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def workload(name):
+    from paper_2411_14974_amd import scenes
+    if name == "c3":
+        scene, cam, target = scenes.config3()
+        desc = "1M convexes K=6 SH3, 64-cluster mixture, 1920x1080, fwd+bwd (L1)"
+    elif name == "c2":
+        scene, cam, target = scenes.config2()
+        desc = "100k convexes K=6 SH3, uniform cube, 1297x840, fwd+bwd (L1)"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return scene, cam, target, desc
+
+
+def stage_work(stage, n, m, K, T_mean, deg, stats, npix):
+    """Algorithmic bytes (or VALU lane-ops) of one launch of a stage."""
+    nc = (deg + 1) ** 2
+    rec = 64 + 24 * T_mean
+    if stage == "preprocess":  # read points, delta, sigma, opacity, SH; write record, key, id, rect, count, hull
+        return "hbm", n * (12 * K + 12 + 12 * nc + rec + 4 + 4 + 8 + 4 + 4)
+    if stage == "depth_sort":  # 4 passes x (histogram read 4 B + scatter read 8 B + write 8 B)
+        return "hbm", n * 4 * 20
+    if stage == "bin_scan":  # gather: id 4 + count 4 + write 4; scan: read twice 8 + write 4
+        return "hbm", n * 24
+    if stage == "emit":  # per convex: id, offset, rect 16 B; per pair: write 8 B
+        return "hbm", n * 16 + m * 8
+    if stage == "tile_sort":  # 2 passes of 8-bit digits over the tile id
+        return "hbm", m * 2 * 20
+    if stage == "ranges":
+        return "hbm", m * 4
+    if stage == "render_fwd":  # per tested pair: 2T DFMA + (T-1) max + 4; full pairs: 7T + 24 (4 per transcendental)
+        ev, full = stats["evaluated"], stats["full"]
+        return "alu", ev * (3 * T_mean + 4) + full * (7 * T_mean + 24)
+    if stage == "render_bwd":  # same evaluation plus the gradient (12T + 30) on the full pairs
+        ev, full = stats["evaluated"], stats["full"]
+        return "alu", ev * (3 * T_mean + 4) + full * (7 * T_mean + 24 + 12 * T_mean + 30)
+    if stage == "preprocess_bwd":  # read accumulators, points, delta, sigma, SH, hull; write gradients
+        acc = 4 * (3 * K + 6)
+        return "hbm", n * (acc + 12 * K + 8 + 12 * nc + 4 + 12 * K + 12 + 12 * nc)
+    return "hbm", 0
+
+
+def cpu_baseline(scene, cam, target, sample):
+    """The FP64 oracle, as it stands, on a seeded pixel sample of the workload."""
+    import oracle
+    W, H = cam.width, cam.height
+    rng = np.random.default_rng(2024)
+    sel = rng.choice(W * H, sample, replace=False)
+    pix = np.stack([sel % W, sel // W], 1).astype(np.int32)
+    t0 = time.perf_counter()
+    oracle.preprocess(scene, cam)
+    t_pre = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rgb, _, _ = oracle.render(scene, cam, mode=oracle.MODE_MATCHED, pixels=pix)
+    t_fwd = time.perf_counter() - t0
+    dl = np.sign(rgb - target.reshape(-1, 3)[sel]) / (3.0 * W * H)
+    t0 = time.perf_counter()
+    oracle.backward(scene, cam, dl, mode=oracle.MODE_MATCHED, pixels=pix)
+    t_bwd = time.perf_counter() - t0
+    # each oracle call runs its own per-convex preprocess once; the rest scales with pixels
+    per_pixel = max(t_fwd + t_bwd - 2 * t_pre, 1e-12) / sample
+    full = 2 * t_pre + W * H * per_pixel
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": W * H / full / 1e6, "unit": "Mpixels/s", "cores": cores, "kind": "oracle",
+        "sample": (f"{sample} seeded pixels of the same frame, fwd+bwd, matched mode; full-frame time "
+                   f"extrapolated as 2 x per-convex pass ({t_pre:.2f} s) + W*H x per-pixel cost "
+                   f"({per_pixel * 1e3:.3f} ms); measured {t_pre + t_fwd + t_bwd:.1f} s of CPU work"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (views shard across GPUs with no "
+              "exchange; see the sharding design). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2411_14974_amd.binding import FLAG_TIMING, DeviceScene, Renderer, make_params
+
+    scene, cam, target, desc = workload(args.workload)
+    W, H = cam.width, cam.height
+    dev = torch.device("cuda:0")
+    R = Renderer(0)
+    ds = DeviceScene.from_scene(scene, dev)
+    tgt = torch.from_numpy(target).to(dev)
+    rgb = torch.empty((H, W, 3), device=dev)
+    dl = torch.empty_like(rgb)
+    grads = {k: torch.empty_like(getattr(ds, k)) for k in ("points", "delta", "sigma", "opacity", "sh")}
+    params = make_params(flags=FLAG_TIMING)
+
+    def step():
+        out, st = R.forward(ds, cam, params, want_state=True, out=rgb)
+        R.l1_loss_grad(out, tgt, grad=dl)
+        R.backward(st, dl, grads=grads)
+        return st
+
+    for _ in range(args.warmup):
+        step().release()
+    torch.cuda.synchronize()
+    R.timing(reset=True)
+    states = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = step()
+        states.append(st)
+        if len(states) > 2:
+            states.pop(0).release()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    stats = states[-1].stats()
+    for s in states:
+        s.release()
+    timing = R.timing(reset=True)
+
+    n, K, deg = scene.n, scene.k, scene.deg
+    T_mean = 4.92 if K == 6 else float(K)
+    avg = {s: (t / c if c else 0.0) for s, (t, c) in timing.items()}
+    dom = max(avg, key=avg.get)
+    bound, work = stage_work(dom, n, stats["pairs"], K, T_mean, deg, stats, W * H)
+    sec = avg[dom] / 1e3
+    if bound == "hbm":
+        achieved, peak, unit = work / sec / 1e9, HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved, peak, unit = work / sec / 1e12, VALU_PEAK_TOPS, "TOP/s"
+    if args.stages:
+        for s in avg:
+            print(f"  {s:15s} {avg[s]:8.3f} ms", file=sys.stderr)
+        print(f"  pairs {stats['pairs']}, evaluated {stats['evaluated']}, full {stats['full']}", file=sys.stderr)
+
+    line = {
+        "metric": "Mpixels/s fwd+bwd @1M convexes 1080p vs plain; p50/p99 served frame latency",
+        "value": W * H / (ms / 1e3) / 1e6,
+        "unit": "Mpixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "convexes": n, "k": K, "sh_degree": deg, "width": W, "height": H,
+                   "form": "plain (one view per launch)", "tile": 16},
+        "stages_ms": {s: round(v, 4) for s, v in avg.items()},
+        "work": {"pairs": stats["pairs"], "evaluated": stats["evaluated"], "full": stats["full"]},
+        "roofline": {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                     "frac": achieved / peak, "traffic": None},
+    }
+    R.close()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(scene, cam, target, args.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

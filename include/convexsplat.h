@@ -1,0 +1,184 @@
+/*
+ * convexsplat.h — C ABI of the MI355X (gfx950) differentiable rasterizer for
+ * smooth 3D convexes, after "3D Convex Splatting" (Held et al., CVPR 2025).
+ *
+ * Conventions for every entry point
+ *   - Pointers to scene, image and gradient arrays are DEVICE pointers (HBM of
+ *     the context's GPU); structs (cs_scene, cs_camera, cs_params, cs_grads)
+ *     themselves live in host memory and are read during the call only.
+ *   - All arrays are dense, row-major, float32, with the shapes stated below.
+ *   - The caller owns every scene, image and gradient buffer; the library never
+ *     frees them.  The library owns cs_ctx, cs_fwd_state and their workspace.
+ *   - Work is enqueued on `hip_stream` (a hipStream_t; NULL = the null stream)
+ *     in stream order.  cs_render_forward makes one host synchronisation: a
+ *     4-byte read of the number of (convex, tile) pairs to size its buffers.
+ *   - A context is used by one host thread and one stream at a time; separate
+ *     contexts are independent.
+ *   - Return value 0 = success, a negative CS_E* code otherwise; no exception
+ *     crosses the ABI; cs_last_error() describes the last failure of the
+ *     calling thread.
+ *
+ * Parameter conventions (paper, Sec. 3.2 and 3.3): a convex is K points p_k;
+ * delta (smoothness), sigma (sharpness) and opacity are the ACTIVATED values
+ * (delta > 0, sigma > 0, 0 <= opacity <= 1); colour is real spherical harmonics
+ * of degree D <= 3, coefficients ordered (l, m) with m ascending.
+ */
+#ifndef CONVEXSPLAT_H
+#define CONVEXSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CS_OK 0
+#define CS_EINVAL (-1)    /* bad shape, K, degree, camera, null pointer */
+#define CS_ENOMEM (-2)    /* device allocation failed or HBM budget exceeded */
+#define CS_EOVERFLOW (-3) /* a fixed-capacity buffer was too small */
+#define CS_EHIP (-4)      /* HIP runtime error (message in cs_last_error) */
+#define CS_EBUSY (-5)     /* serving queue full */
+#define CS_ENODEV (-6)    /* no usable gfx950 device */
+
+#define CS_MAX_K 8
+#define CS_MAX_SH_DEGREE 3
+
+typedef struct cs_ctx cs_ctx;             /* device, workspace, tuning and serving state */
+typedef struct cs_fwd_state cs_fwd_state; /* what the backward pass needs from a forward pass */
+
+/* Pinhole camera (paper Sec. 3.2, Eq. projection q = K (R p + t) with the
+ * homogeneous divide): R row-major world->camera, camera axes x right, y down,
+ * z forward; fx, fy, cx, cy in pixels; pixel (u, v) is sampled at
+ * (u + 0.5, v + 0.5).  A convex with any point at depth <= znear is dropped. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    float znear;
+} cs_camera;
+
+/* Scene (paper Sec. 3.2 point-set convexes; Sec. 3.3 optimised parameters). */
+typedef struct {
+    int32_t n;          /* number of convexes, >= 0 */
+    int32_t k;          /* points per convex, 3 <= k <= 8 */
+    int32_t sh_degree;  /* 0 <= sh_degree <= 3 */
+    const float *points;  /* [n][k][3] world space */
+    const float *delta;   /* [n] smoothness, activated, > 0 */
+    const float *sigma;   /* [n] sharpness, activated, > 0 */
+    const float *opacity; /* [n] in [0, 1] */
+    const float *sh;      /* [n][(sh_degree+1)^2][3] */
+} cs_scene;
+
+/* Gradients, same shapes as the scene arrays; OVERWRITTEN by the backward call. */
+typedef struct {
+    float *points, *delta, *sigma, *opacity, *sh;
+} cs_grads;
+
+/* cs_params.flags bits */
+#define CS_FLAG_TIMING 1 /* record hipEvents around each stage on the call's stream (see cs_timing_read) */
+
+/* Stages timed under CS_FLAG_TIMING */
+enum {
+    CS_STAGE_PREPROCESS = 0, /* per-convex projection, hull, lines, colour, key, tile rectangle */
+    CS_STAGE_DEPTH_SORT,     /* radix sort of the convexes by depth key */
+    CS_STAGE_BIN_SCAN,       /* tile counts in depth order and their exclusive scan */
+    CS_STAGE_EMIT,           /* (tile, convex) pair emission */
+    CS_STAGE_TILE_SORT,      /* stable radix sort of the pairs by tile */
+    CS_STAGE_RANGES,         /* per-tile list ranges */
+    CS_STAGE_RENDER_FWD,     /* per-tile forward compositing */
+    CS_STAGE_RENDER_BWD,     /* per-tile backward compositing */
+    CS_STAGE_PREPROCESS_BWD, /* per-convex backward chain rule */
+    CS_NUM_STAGES
+};
+
+/* Render parameters.  eps_alpha and t_min are part of the result's definition:
+ * a (pixel, convex) pair with alpha < eps_alpha is skipped, and a pixel stops
+ * after the convex that brings its transmittance below t_min.  tile = 0 picks
+ * the default (16); supported: 16.  NULL = {1e-6, 1e-5, black, 0, 0}. */
+typedef struct {
+    float eps_alpha, t_min;
+    float background[3];
+    int32_t tile;
+    int32_t flags;
+} cs_params;
+
+/* Library version as major*10000 + minor*100 + patch. */
+int cs_version(void);
+
+/* Thread-local description of the last failure of this thread ("" if none). */
+const char *cs_last_error(void);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes = 0 means no
+ * limit; otherwise workspace growth beyond it fails with CS_ENOMEM. */
+int cs_create(int device, size_t hbm_budget_bytes, cs_ctx **out);
+
+/* Wait for the context's work, free its workspace and the context. */
+int cs_destroy(cs_ctx *ctx);
+
+/* Forward render (paper Sec. 3.2: projection, 2D hull, hull lines, distance-
+ * scaled smooth indicator of Supp. B, SH colour, front-to-back compositing of
+ * the compositing equation, convexes ordered by increasing depth).
+ *   out_rgb: [height][width][3] device, written.
+ *   state:   if non-NULL receives a new cs_fwd_state for cs_render_backward;
+ *            release it with cs_state_release.  NULL = forward only.
+ * The scene arrays must stay unchanged until the matching backward call. */
+int cs_render_forward(cs_ctx *ctx, const cs_scene *scene, const cs_camera *cam, const cs_params *params,
+                      float *out_rgb, cs_fwd_state **state, void *hip_stream);
+
+/* Backward render: gradient of sum(dl_drgb * rgb) with respect to points,
+ * delta, sigma, opacity and SH (paper Sec. 3.3 optimised parameters), through
+ * every step of the forward pass ("fully differentiable", Sec. 3.2).
+ *   dl_drgb: [height][width][3] device.  grads: overwritten device arrays.
+ * scene, cam and params must be those of the forward call that made state. */
+int cs_render_backward(cs_ctx *ctx, const cs_scene *scene, const cs_camera *cam, const cs_params *params,
+                       const cs_fwd_state *state, const float *dl_drgb, cs_grads *grads, void *hip_stream);
+
+/* Release a forward state (stream-ordered after the work that uses it). */
+int cs_state_release(cs_ctx *ctx, cs_fwd_state *state);
+
+/* Work counters of a forward state, copied to host (synchronises the stream):
+ * n_pairs = (convex, tile) pairs binned; n_evaluated = (pixel, list entry)
+ * pairs the forward walk tested; n_full = those that passed the max-line test
+ * and evaluated the full indicator. */
+int cs_state_stats(cs_ctx *ctx, const cs_fwd_state *state, int64_t *n_pairs, int64_t *n_evaluated,
+                   int64_t *n_full);
+
+/* Debug/parity: per-convex preprocess results copied to host memory `out`,
+ * an array of n cs_debug_convex records (synchronises the stream). */
+typedef struct {
+    int32_t status;     /* 0 visible, 1 culled (near plane), 2 culled (hull < 3), 3 never visible (opacity <= eps) */
+    int32_t T;          /* hull size */
+    int32_t hull[CS_MAX_K]; /* hull point indices, positive orientation, from min (y, x) */
+    uint32_t depth_key; /* bits of the float32 depth key */
+    int32_t clampmask;  /* bit c: colour channel c clamped at 0 */
+    double A[CS_MAX_K], B[CS_MAX_K], C[CS_MAX_K]; /* L_j(q) = A_j qx + B_j qy + C_j, pixels, unit normal */
+    double d, delta_p, sigma_p; /* depth, delta' = d delta, sigma' = d sigma */
+    float rgb[3];
+    int32_t tile_rect[4]; /* tx0, ty0, tx1, ty1 (inclusive); empty when tx0 > tx1 */
+} cs_debug_convex;
+
+int cs_debug_preprocess(cs_ctx *ctx, const cs_scene *scene, const cs_camera *cam, const cs_params *params,
+                        cs_debug_convex *out, void *hip_stream);
+
+/* Debug/parity: the depth-ordered per-tile convex lists of a forward state,
+ * copied to host.  ranges: [n_tiles][2] (start, end); ids: [n_pairs]. */
+int cs_debug_tile_lists(cs_ctx *ctx, const cs_fwd_state *state, int32_t *ranges, int64_t ranges_len,
+                        int32_t *ids, int64_t ids_len);
+
+/* Accumulated GPU time per stage (ms) and number of timed launches of it, over
+ * the calls made with CS_FLAG_TIMING since the last reset; waits for the
+ * pending events.  ms and count are host arrays of CS_NUM_STAGES (nullable). */
+int cs_timing_read(cs_ctx *ctx, double *ms, int64_t *count, int reset);
+
+/* Mean-absolute-error loss helper for a training step: writes
+ * dl_drgb = sign(rgb - target) / (3 * height * width) and, if loss is
+ * non-NULL (device, one float), accumulates the mean |rgb - target| into it. */
+int cs_l1_loss_grad(cs_ctx *ctx, const float *rgb, const float *target, int32_t width, int32_t height,
+                    float *dl_drgb, float *loss, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

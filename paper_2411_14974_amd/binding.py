@@ -1,0 +1,266 @@
+"""ctypes binding of libconvexsplat.so (include/convexsplat.h).
+
+Argument marshalling only: every step of the rasterizer runs in the library's
+HIP kernels.  PyTorch provides device memory and the current stream.  Loading
+fails loudly when the library is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libconvexsplat.so")
+
+CS_OK, CS_EINVAL, CS_ENOMEM, CS_EOVERFLOW, CS_EHIP, CS_EBUSY, CS_ENODEV = 0, -1, -2, -3, -4, -5, -6
+MAX_K = 8
+
+# Every symbol include/convexsplat.h declares.
+EXPORTED = (
+    "cs_version", "cs_last_error", "cs_create", "cs_destroy", "cs_render_forward", "cs_render_backward",
+    "cs_state_release", "cs_state_stats", "cs_debug_preprocess", "cs_debug_tile_lists", "cs_l1_loss_grad",
+    "cs_timing_read",
+)
+FLAG_TIMING = 1
+STAGES = ("preprocess", "depth_sort", "bin_scan", "emit", "tile_sort", "ranges", "render_fwd", "render_bwd",
+          "preprocess_bwd")
+
+
+class CSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"convexsplat error {code}: {msg}")
+        self.code = code
+
+
+class Camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("R", C.c_float * 9), ("t", C.c_float * 3),
+                ("znear", C.c_float)]
+
+
+class SceneS(C.Structure):
+    _fields_ = [("n", C.c_int32), ("k", C.c_int32), ("sh_degree", C.c_int32), ("points", C.c_void_p),
+                ("delta", C.c_void_p), ("sigma", C.c_void_p), ("opacity", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class GradsS(C.Structure):
+    _fields_ = [("points", C.c_void_p), ("delta", C.c_void_p), ("sigma", C.c_void_p), ("opacity", C.c_void_p),
+                ("sh", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("eps_alpha", C.c_float), ("t_min", C.c_float), ("background", C.c_float * 3),
+                ("tile", C.c_int32), ("flags", C.c_int32)]
+
+
+class DebugConvex(C.Structure):
+    _fields_ = [("status", C.c_int32), ("T", C.c_int32), ("hull", C.c_int32 * MAX_K), ("depth_key", C.c_uint32),
+                ("clampmask", C.c_int32), ("A", C.c_double * MAX_K), ("B", C.c_double * MAX_K),
+                ("C", C.c_double * MAX_K), ("d", C.c_double), ("delta_p", C.c_double), ("sigma_p", C.c_double),
+                ("rgb", C.c_float * 3), ("tile_rect", C.c_int32 * 4)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libconvexsplat.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2411_14974_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        L.cs_version.restype = C.c_int
+        L.cs_last_error.restype = C.c_char_p
+        L.cs_create.argtypes = [C.c_int, sz, C.POINTER(vp)]
+        L.cs_destroy.argtypes = [vp]
+        L.cs_render_forward.argtypes = [vp, vp, vp, vp, vp, C.POINTER(vp), vp]
+        L.cs_render_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.cs_state_release.argtypes = [vp, vp]
+        L.cs_state_stats.argtypes = [vp, vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+        L.cs_timing_read.argtypes = [vp, vp, vp, C.c_int]
+        L.cs_debug_preprocess.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.cs_debug_tile_lists.argtypes = [vp, vp, vp, i64, vp, i64]
+        L.cs_l1_loss_grad.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != CS_OK:
+        raise CSError(code, lib().cs_last_error().decode())
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def make_camera(cam) -> Camera:
+    """cs_camera from an object with width, height, fx, fy, cx, cy, R (3x3), t (3), znear."""
+    c = Camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    R = np.asarray(cam.R, np.float32).ravel()
+    t = np.asarray(cam.t, np.float32).ravel()
+    for i in range(9):
+        c.R[i] = float(R[i])
+    for i in range(3):
+        c.t[i] = float(t[i])
+    c.znear = float(getattr(cam, "znear", 0.1))
+    return c
+
+
+def make_params(eps_alpha=1e-6, t_min=1e-5, background=(0.0, 0.0, 0.0), tile=0, flags=0) -> Params:
+    p = Params()
+    p.eps_alpha, p.t_min = eps_alpha, t_min
+    for i in range(3):
+        p.background[i] = float(background[i])
+    p.tile, p.flags = tile, flags
+    return p
+
+
+class DeviceScene:
+    """Scene arrays resident on the GPU (float32, contiguous)."""
+
+    def __init__(self, points, delta, sigma, opacity, sh, device="cuda"):
+        t = lambda a: (a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a))).to(
+            device=device, dtype=torch.float32).contiguous()
+        self.points, self.delta, self.sigma, self.opacity, self.sh = t(points), t(delta), t(sigma), t(opacity), t(sh)
+        self._validate()
+
+    @classmethod
+    def from_scene(cls, scene, device="cuda"):
+        return cls(scene.points, scene.delta, scene.sigma, scene.opacity, scene.sh, device)
+
+    def _validate(self):
+        n, k = self.points.shape[:2]
+        if self.points.dim() != 3 or self.points.shape[2] != 3:
+            raise ValueError("points must be [N][K][3]")
+        nc = self.sh.shape[1]
+        deg = int(round(nc ** 0.5)) - 1
+        if (deg + 1) ** 2 != nc or self.sh.shape != (n, nc, 3):
+            raise ValueError("sh must be [N][(D+1)^2][3]")
+        for a in (self.delta, self.sigma, self.opacity):
+            if a.shape != (n,):
+                raise ValueError("delta, sigma, opacity must be [N]")
+
+    @property
+    def n(self):
+        return int(self.points.shape[0])
+
+    @property
+    def k(self):
+        return int(self.points.shape[1])
+
+    @property
+    def deg(self):
+        return int(round(self.sh.shape[1] ** 0.5)) - 1
+
+    def struct(self) -> SceneS:
+        return SceneS(self.n, self.k, self.deg, self.points.data_ptr(), self.delta.data_ptr(),
+                      self.sigma.data_ptr(), self.opacity.data_ptr(), self.sh.data_ptr())
+
+
+class FwdState:
+    """Owns a cs_fwd_state; released when garbage-collected or released explicitly."""
+
+    def __init__(self, renderer: "Renderer", handle: int, scene: DeviceScene, cam: Camera, params: Params):
+        self.renderer, self.handle, self.scene, self.cam, self.params = renderer, handle, scene, cam, params
+
+    def stats(self):
+        pairs, evals, full = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().cs_state_stats(self.renderer.ctx, self.handle, C.byref(pairs), C.byref(evals), C.byref(full)))
+        return {"pairs": pairs.value, "evaluated": evals.value, "full": full.value}
+
+    def tile_lists(self):
+        cam = self.cam
+        ntiles = ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
+        npairs = self.stats()["pairs"]
+        ranges = np.zeros((ntiles, 2), np.int32)
+        ids = np.zeros(max(npairs, 1), np.int32)
+        _check(lib().cs_debug_tile_lists(self.renderer.ctx, self.handle, ranges.ctypes.data, ranges.size,
+                                         ids.ctypes.data, ids.size))
+        return ranges, ids[:npairs]
+
+    def release(self):
+        if self.handle:
+            lib().cs_state_release(self.renderer.ctx, self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+class Renderer:
+    """A library context on one GPU."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        _check(lib().cs_create(device, hbm_budget_bytes, C.byref(h)))
+        self.ctx = h
+
+    def close(self):
+        if self.ctx:
+            lib().cs_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, scene: DeviceScene, cam, params: Params | None = None, want_state=False, out=None):
+        camS = cam if isinstance(cam, Camera) else make_camera(cam)
+        params = params or make_params()
+        dev = scene.points.device
+        if out is None:
+            out = torch.empty((camS.height, camS.width, 3), device=dev, dtype=torch.float32)
+        st = C.c_void_p()
+        sS = scene.struct()
+        _check(lib().cs_render_forward(self.ctx, C.byref(sS), C.byref(camS), C.byref(params), out.data_ptr(),
+                                       C.byref(st) if want_state else None, _stream_handle(dev)))
+        state = FwdState(self, st.value, scene, camS, params) if want_state else None
+        return out, state
+
+    def backward(self, state: FwdState, dl_drgb: torch.Tensor, grads=None):
+        scene = state.scene
+        dl = dl_drgb.contiguous()
+        if grads is None:
+            grads = {k: torch.empty_like(getattr(scene, k)) for k in ("points", "delta", "sigma", "opacity", "sh")}
+        gS = GradsS(grads["points"].data_ptr(), grads["delta"].data_ptr(), grads["sigma"].data_ptr(),
+                    grads["opacity"].data_ptr(), grads["sh"].data_ptr())
+        sS = scene.struct()
+        _check(lib().cs_render_backward(self.ctx, C.byref(sS), C.byref(state.cam), C.byref(state.params),
+                                        state.handle, dl.data_ptr(), C.byref(gS), _stream_handle(dl.device)))
+        return grads
+
+    def debug_preprocess(self, scene: DeviceScene, cam, params: Params | None = None):
+        camS = cam if isinstance(cam, Camera) else make_camera(cam)
+        out = (DebugConvex * max(scene.n, 1))()
+        sS = scene.struct()
+        _check(lib().cs_debug_preprocess(self.ctx, C.byref(sS), C.byref(camS), C.byref(params or make_params()),
+                                         out, _stream_handle(scene.points.device)))
+        return out
+
+    def timing(self, reset=True):
+        """{stage: (total ms, launches)} of the calls made with FLAG_TIMING."""
+        ms = (C.c_double * len(STAGES))()
+        cnt = (C.c_int64 * len(STAGES))()
+        _check(lib().cs_timing_read(self.ctx, ms, cnt, int(reset)))
+        return {s: (ms[i], cnt[i]) for i, s in enumerate(STAGES)}
+
+    def l1_loss_grad(self, rgb: torch.Tensor, target: torch.Tensor, grad=None, loss=None):
+        H, W = rgb.shape[:2]
+        grad = torch.empty_like(rgb) if grad is None else grad
+        _check(lib().cs_l1_loss_grad(self.ctx, rgb.data_ptr(), target.data_ptr(), W, H, grad.data_ptr(),
+                                     loss.data_ptr() if loss is not None else None, _stream_handle(rgb.device)))
+        return grad

@@ -1,0 +1,69 @@
+"""The C-ABI library: it loads, exports every symbol the header declares, and
+returns its documented error codes on bad arguments (no compute call is made,
+so these run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2411_14974_amd import binding
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "convexsplat.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(cs_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    syms = declared_symbols()
+    for s in ("cs_create", "cs_destroy", "cs_render_forward", "cs_render_backward", "cs_state_release",
+              "cs_debug_preprocess", "cs_last_error"):
+        assert s in syms
+    assert set(syms) == set(binding.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = binding.lib()
+    for s in declared_symbols():
+        assert hasattr(L, s), s
+    assert L.cs_version() >= 100
+
+
+def test_null_and_shape_errors_without_a_gpu():
+    L = binding.lib()
+    cam = binding.Camera()
+    cam.width, cam.height, cam.fx, cam.fy, cam.znear = 64, 64, 50.0, 50.0, 0.1
+    sc = binding.SceneS(10, 6, 3, 0, 0, 0, 0, 0)
+    out = C.c_void_p()
+    # NULL context
+    assert L.cs_render_forward(None, C.byref(sc), C.byref(cam), None, 1, None, None) == binding.CS_EINVAL
+    assert b"ctx" in L.cs_last_error()
+    # a context-sized dummy: argument checks run before any device call
+    dummy = (C.c_char * 64)()
+    bad_k = binding.SceneS(10, 9, 3, 1, 1, 1, 1, 1)
+    assert L.cs_render_forward(dummy, C.byref(bad_k), C.byref(cam), None, 1, None, None) == binding.CS_EINVAL
+    assert b"k" in L.cs_last_error()
+    bad_deg = binding.SceneS(10, 6, 4, 1, 1, 1, 1, 1)
+    assert L.cs_render_forward(dummy, C.byref(bad_deg), C.byref(cam), None, 1, None, None) == binding.CS_EINVAL
+    null_arr = binding.SceneS(10, 6, 3, 1, 0, 1, 1, 1)
+    assert L.cs_render_forward(dummy, C.byref(null_arr), C.byref(cam), None, 1, None, None) == binding.CS_EINVAL
+    bad_cam = binding.Camera()
+    bad_cam.width, bad_cam.height, bad_cam.fx, bad_cam.fy, bad_cam.znear = 0, 64, 50.0, 50.0, 0.1
+    good = binding.SceneS(10, 6, 3, 1, 1, 1, 1, 1)
+    assert L.cs_render_forward(dummy, C.byref(good), C.byref(bad_cam), None, 1, None, None) == binding.CS_EINVAL
+    p = binding.make_params(tile=8)
+    assert L.cs_render_forward(dummy, C.byref(good), C.byref(cam), C.byref(p), 1, None, None) == binding.CS_EINVAL
+    assert L.cs_render_backward(dummy, C.byref(good), C.byref(cam), None, None, 1, 1, None) == binding.CS_EINVAL
+
+
+@pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),
+                    reason="a GPU is present: cs_create would succeed")
+def test_create_without_device_reports_enodev():
+    L = binding.lib()
+    h = C.c_void_p()
+    rc = L.cs_create(0, 0, C.byref(h))
+    assert rc == binding.CS_ENODEV
+    assert not h.value

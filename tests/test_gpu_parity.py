@@ -1,0 +1,320 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: hull index sequences and depth keys bit-exact; per-tile lists hold every
+convex the oracle finds with alpha >= eps_alpha in the tile, in depth order;
+pixels within 1e-4 absolute of the oracle's matched mode; gradients (the same
+dL/dC fed to both) within 1e-3 relative per tensor (L2) and per element
+(floor 1e-2 rms).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2411_14974_amd import scenes  # noqa: E402
+from paper_2411_14974_amd.scenes import Camera, Scene  # noqa: E402
+
+PIX_TOL = 1e-4
+GRAD_TOL = 1e-3
+NAMES = ("points", "delta", "sigma", "opacity", "sh")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2411_14974_amd.binding import Renderer
+    r = Renderer(0)
+    yield r
+    r.close()
+
+
+def dev(scene):
+    from paper_2411_14974_amd.binding import DeviceScene
+    return DeviceScene.from_scene(scene, "cuda:0")
+
+
+def render_gpu(R, scene, cam, want_state=False, **kw):
+    from paper_2411_14974_amd.binding import make_params
+    ds = dev(scene)
+    rgb, st = R.forward(ds, cam, make_params(**kw), want_state=want_state)
+    torch.cuda.synchronize()
+    return ds, rgb, st
+
+
+def grad_check(g_gpu, g_ref, label):
+    worst = {}
+    for k in NAMES:
+        a = g_gpu[k].detach().cpu().numpy().astype(np.float64).ravel()
+        b = np.asarray(g_ref[k], np.float64).ravel()
+        nb = np.linalg.norm(b)
+        rel = np.linalg.norm(a - b) / max(nb, 1e-300)
+        rms = np.sqrt(np.mean(b * b)) if b.size else 0.0
+        elem = np.abs(a - b) / np.maximum(np.abs(b), 1e-2 * rms + 1e-300)
+        worst[k] = (float(rel), float(elem.max()) if b.size else 0.0)
+    say(f"[{label}] grad rel-L2 / worst element: " + ", ".join(f"{k} {v[0]:.1e}/{v[1]:.1e}" for k, v in worst.items()))
+    for k, (rel, el) in worst.items():
+        assert rel <= GRAD_TOL, (label, k, rel)
+        assert el <= GRAD_TOL, (label, k, el)
+
+
+# ------------------------------------------------------------ preprocess ----
+
+STATUS_MAP = {0: 0, 1: 1, 2: 2, 3: 0}  # GPU "faint" (opacity <= eps) is visible to the oracle
+
+
+def check_preprocess(R, scene, cam, label):
+    import oracle
+    g = R.debug_preprocess(dev(scene), cam)
+    o = oracle.preprocess(scene, cam)
+    degenerate = 0
+    ntiles_x = (cam.width + 15) // 16
+    for i in range(scene.n):
+        a, b = g[i], o[i]
+        if b.status & 256:
+            degenerate += 1
+            continue
+        assert STATUS_MAP[a.status] == (b.status & 0xFF), (label, i, a.status, b.status)
+        if a.status == 1:
+            continue
+        assert a.T == b.T, (label, i)
+        assert list(a.hull)[:a.T] == list(b.hull)[:b.T], (label, i)
+        if a.status in (0, 3):
+            assert a.depth_key == b.key, (label, i, hex(a.depth_key), hex(b.key))
+            for j in range(a.T):
+                assert abs(a.A[j] - b.nx[j]) < 1e-12 and abs(a.B[j] - b.ny[j]) < 1e-12, (label, i, j)
+                assert abs(a.C[j] - b.off[j]) < 1e-9 * (1 + abs(b.off[j])), (label, i, j)
+            assert abs(a.d - b.d) <= 1e-12 * b.d and abs(a.delta_p - b.dp) <= 1e-12 * b.dp
+            assert abs(a.sigma_p - b.sp) <= 1e-12 * b.sp
+            np.testing.assert_allclose(list(a.rgb), list(b.rgb), atol=2e-6)
+            assert a.clampmask == b.clampmask or np.min(np.abs(list(b.rgb))) < 1e-6
+        if a.status == 0:
+            # the oracle's alpha >= eps region must lie inside the GPU's tile rectangle
+            x0, y0, x1, y1 = b.rect
+            u0, u1 = max(0, int(np.ceil(x0 - 0.5))), min(cam.width - 1, int(np.floor(x1 - 0.5)))
+            v0, v1 = max(0, int(np.ceil(y0 - 0.5))), min(cam.height - 1, int(np.floor(y1 - 0.5)))
+            if u0 <= u1 and v0 <= v1:
+                tx0, ty0, tx1, ty1 = list(a.tile_rect)
+                assert tx0 <= u0 // 16 and u1 // 16 <= tx1 and ty0 <= v0 // 16 and v1 // 16 <= ty1, (label, i)
+    say(f"[{label}] preprocess parity over {scene.n} convexes, {degenerate} degenerate excluded")
+    assert degenerate <= max(1, scene.n // 10000)
+
+
+def test_preprocess_parity_config1(R):
+    scene, cam = scenes.config1()
+    check_preprocess(R, scene, cam, "C1")
+
+
+def test_preprocess_parity_config2_subset(R):
+    scene, cam, _ = scenes.config2(n=20000)
+    check_preprocess(R, scene, cam, "C2-20k")
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 7, 8])
+def test_preprocess_parity_other_k(R, k):
+    rng = np.random.default_rng(100 + k)
+    centres = scenes.uniform_centres(rng, 2000)
+    scene = scenes.convexes_around(rng, centres, k, 2)
+    cam = scenes.orbit_camera(rng, 320, 200)
+    check_preprocess(R, scene, cam, f"K={k}")
+
+
+# ------------------------------------------------------------- tile lists ---
+
+def test_tile_lists_hold_oracle_candidates_in_depth_order(R):
+    import oracle
+    scene, cam, _ = scenes.config2(n=4000, width=200, height=150)
+    ds, rgb, st = render_gpu(R, scene, cam, want_state=True)
+    ranges, ids = st.tile_lists()
+    pre = oracle.preprocess(scene, cam)
+    keys = np.array([c.key for c in pre], np.uint64)
+    tx_n = (cam.width + 15) // 16
+    rng = np.random.default_rng(0)
+    tiles = rng.choice(ranges.shape[0], 25, replace=False)
+    for t in tiles:
+        s, e = ranges[t]
+        lst = ids[s:e]
+        assert len(set(lst.tolist())) == len(lst)
+        order = np.lexsort((lst, keys[lst]))
+        assert np.all(order == np.arange(len(lst))), "list not in (depth key, index) order"
+        cand = oracle.tile_candidates(scene, cam, 16, int(t % tx_n), int(t // tx_n))
+        assert set(cand.tolist()) <= set(lst.tolist()), (t, sorted(set(cand) - set(lst)))
+    say(f"[lists] {len(tiles)} tiles checked, {len(ids)} pairs")
+    st.release()
+
+
+# --------------------------------------------------------------- forward ----
+
+def forward_parity(R, scene, cam, label, bg=(0.0, 0.0, 0.0)):
+    import oracle
+    _, rgb, _ = render_gpu(R, scene, cam, background=bg)
+    ref, _, _ = oracle.render(scene, cam, mode=oracle.MODE_MATCHED, bg=bg)
+    refx, _, _ = oracle.render(scene, cam, mode=oracle.MODE_EXACT, bg=bg)
+    a = rgb.cpu().numpy().astype(np.float64)
+    err, errx = np.abs(a - ref).max(), np.abs(a - refx).max()
+    say(f"[{label}] max |gpu - oracle| matched {err:.2e}, exact {errx:.2e}")
+    assert err <= PIX_TOL
+    return a
+
+
+def test_forward_config1(R):
+    scene, cam = scenes.config1()
+    forward_parity(R, scene, cam, "C1")
+
+
+def test_forward_ragged_background(R):
+    # 211 x 157: neither side a multiple of the 16-pixel tile
+    scene, cam, _ = scenes.config2(n=15000, width=211, height=157)
+    forward_parity(R, scene, cam, "C2-ragged", bg=(0.2, 0.5, 0.9))
+
+
+def test_forward_mixture_small(R):
+    scene, cam, _ = scenes.config3(n=40000, width=240, height=135)
+    forward_parity(R, scene, cam, "C3-small")
+
+
+@pytest.mark.parametrize("k,deg", [(3, 0), (4, 1), (5, 2), (8, 3)])
+def test_forward_k_and_degree(R, k, deg):
+    rng = np.random.default_rng(200 + k)
+    centres = scenes.uniform_centres(rng, 3000)
+    scene = scenes.convexes_around(rng, centres, k, deg)
+    cam = scenes.orbit_camera(rng, 160, 96)
+    forward_parity(R, scene, cam, f"K={k},D={deg}")
+
+
+def test_forward_edge_cases(R):
+    import oracle
+    from paper_2411_14974_amd.binding import make_params
+    # empty scene: background only
+    empty = Scene(np.zeros((0, 6, 3), np.float32), np.zeros(0, np.float32), np.zeros(0, np.float32),
+                  np.zeros(0, np.float32), np.zeros((0, 16, 3), np.float32))
+    cam = scenes.origin_camera(40, 24)
+    _, rgb, _ = render_gpu(R, empty, cam, background=(0.1, 0.2, 0.3))
+    assert np.allclose(rgb.cpu().numpy(), [0.1, 0.2, 0.3])
+    # every convex behind the camera
+    scene, cam = scenes.config1(n=200)
+    behind = Scene(scene.points * np.array([1, 1, -1], np.float32), scene.delta, scene.sigma, scene.opacity, scene.sh)
+    _, rgb, _ = render_gpu(R, behind, cam)
+    assert np.abs(rgb.cpu().numpy()).max() == 0.0
+    # 1 x 1 image and a convex larger than the screen
+    big = Scene(np.array([[[-5, -5, 2], [5, -5, 2], [0, 5, 2.5]]], np.float32), np.array([1.0], np.float32),
+                np.array([1.0], np.float32), np.array([0.7], np.float32), np.full((1, 1, 3), 0.5, np.float32))
+    for w, h in ((1, 1), (33, 17)):
+        c = scenes.origin_camera(w, h, focal=50.0)
+        _, rgb, _ = render_gpu(R, big, c)
+        ref, _, _ = oracle.render(big, c, mode=oracle.MODE_MATCHED)
+        assert np.abs(rgb.cpu().numpy() - ref).max() <= PIX_TOL
+    # opaque convexes drive T below t_min quickly (early termination path)
+    scene, cam = scenes.config1(n=800)
+    opaque = Scene(scene.points, scene.delta * 5, scene.sigma * 5, np.ones_like(scene.opacity), scene.sh)
+    forward_parity(R, opaque, cam, "opaque")
+
+
+# -------------------------------------------------------------- backward ----
+
+def backward_parity(R, scene, cam, label, dl=None, bg=(0.0, 0.0, 0.0), seed=0):
+    import oracle
+    ds, rgb, st = render_gpu(R, scene, cam, want_state=True, background=bg)
+    if dl is None:
+        rng = np.random.default_rng(seed)
+        dl = rng.normal(size=(cam.height, cam.width, 3)).astype(np.float32)
+    g = R.backward(st, torch.from_numpy(dl).cuda())
+    torch.cuda.synchronize()
+    ref = oracle.backward(scene, cam, dl.reshape(-1, 3), mode=oracle.MODE_MATCHED, bg=bg)
+    grad_check(g, ref, label)
+    st.release()
+
+
+def test_backward_config1(R):
+    scene, cam = scenes.config1()
+    backward_parity(R, scene, cam, "C1")
+
+
+def test_backward_l1_target_small_c2(R):
+    # the training-step loss: mean |C - target|, its gradient computed on the GPU
+    scene, cam, target = scenes.config2(n=10000, width=180, height=117)
+    ds, rgb, st = render_gpu(R, scene, cam, want_state=True)
+    dl = R.l1_loss_grad(rgb, torch.from_numpy(target).cuda())
+    torch.cuda.synchronize()
+    dl_np = dl.cpu().numpy()
+    d = rgb.cpu().numpy() - target
+    np.testing.assert_array_equal(dl_np, np.sign(d).astype(np.float32) / np.float32(d.size))
+    backward_parity(R, scene, cam, "C2-L1", dl=dl_np)
+    st.release()
+
+
+def test_backward_mixture_background(R):
+    scene, cam, _ = scenes.config3(n=20000, width=160, height=90)
+    backward_parity(R, scene, cam, "C3-small", bg=(0.3, 0.6, 0.1), seed=3)
+
+
+@pytest.mark.parametrize("k,deg", [(3, 0), (5, 1), (8, 3)])
+def test_backward_k_and_degree(R, k, deg):
+    rng = np.random.default_rng(300 + k)
+    centres = scenes.uniform_centres(rng, 2000)
+    scene = scenes.convexes_around(rng, centres, k, deg)
+    cam = scenes.orbit_camera(rng, 128, 80)
+    backward_parity(R, scene, cam, f"K={k},D={deg}", seed=k)
+
+
+# ------------------------------------------------ full size, sampled -------
+
+def sampled_parity(R, scene, cam, label, npix=400, seed=0):
+    """Forward on sampled pixels and backward through a dL/dC that is zero
+    outside them, at the full workload size and the benchmark's launch shape."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    W, H = cam.width, cam.height
+    sel = rng.choice(W * H, npix, replace=False)
+    pix = np.stack([sel % W, sel // W], 1)
+    say(f"[{label}] render N={scene.n} {W}x{H}")
+    ds, rgb, st = render_gpu(R, scene, cam, want_state=True)
+    stats = st.stats()
+    a = rgb.cpu().numpy().reshape(-1, 3)[sel].astype(np.float64)
+    say(f"[{label}] oracle on {npix} pixels; pairs {stats['pairs']}")
+    ref, _, _ = oracle.render(scene, cam, mode=oracle.MODE_MATCHED, pixels=pix)
+    err = np.abs(a - ref).max()
+    say(f"[{label}] sampled max |gpu - oracle| {err:.2e}")
+    assert err <= PIX_TOL
+    dl = np.zeros((H * W, 3), np.float32)
+    dl[sel] = rng.normal(size=(npix, 3)).astype(np.float32)
+    g = R.backward(st, torch.from_numpy(dl.reshape(H, W, 3)).cuda())
+    torch.cuda.synchronize()
+    gref = oracle.backward(scene, cam, dl[sel], mode=oracle.MODE_MATCHED, pixels=pix)
+    grad_check(g, gref, label)
+    st.release()
+
+
+def test_full_size_config2_sampled(R):
+    scene, cam, _ = scenes.config2()
+    sampled_parity(R, scene, cam, "C2-full")
+
+
+def test_full_size_config3_sampled(R):
+    scene, cam, _ = scenes.config3()
+    sampled_parity(R, scene, cam, "C3-full", npix=200)
+
+
+# ------------------------------------------------------------- autograd ----
+
+def test_autograd_matches_direct_call(R):
+    from paper_2411_14974_amd.autograd import render
+    scene, cam, _ = scenes.config2(n=3000, width=96, height=64)
+    t = {k: torch.from_numpy(getattr(scene, k)).cuda().requires_grad_(True) for k in NAMES}
+    rgb = render(t["points"], t["delta"], t["sigma"], t["opacity"], t["sh"], R, cam)
+    w = torch.randn_like(rgb)
+    (rgb * w).sum().backward()
+    ds, rgb2, st = render_gpu(R, scene, cam, want_state=True)
+    g = R.backward(st, w)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb.detach(), rgb2)
+    for k in NAMES:
+        torch.testing.assert_close(t[k].grad, g[k], rtol=1e-5, atol=1e-7)
+    st.release()
