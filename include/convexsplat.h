@@ -77,7 +77,11 @@ typedef struct {
 } cs_grads;
 
 /* cs_params.flags bits */
-#define CS_FLAG_TIMING 1 /* record hipEvents around each stage on the call's stream (see cs_timing_read) */
+#define CS_FLAG_TIMING 1         /* record hipEvents around each stage on the call's stream (see cs_timing_read) */
+#define CS_FLAG_LONGEST_FIRST 2  /* compositing takes tiles in order of decreasing list length (else natural) */
+#define CS_FLAG_GRAPH 4          /* batched calls: capture into a hipGraph and replay (see cs_render_forward_batch) */
+#define CS_FLAG_AUTOTUNE 8       /* batched calls with tile = 0: take tile, schedule and sort digits from the tuner */
+#define CS_FLAG_DIGITS(b) (((b)&15) << 8) /* radix digit width of the pair sort, 4..8 (0 = 8) */
 
 /* Stages timed under CS_FLAG_TIMING */
 enum {
@@ -90,13 +94,16 @@ enum {
     CS_STAGE_RENDER_FWD,     /* per-tile forward compositing */
     CS_STAGE_RENDER_BWD,     /* per-tile backward compositing */
     CS_STAGE_PREPROCESS_BWD, /* per-convex backward chain rule */
+    CS_STAGE_ORDER,          /* longest-first tile order */
+    CS_STAGE_GRAPH_FWD,      /* a replayed forward graph, whole */
+    CS_STAGE_GRAPH_BWD,      /* a replayed backward graph, whole */
     CS_NUM_STAGES
 };
 
 /* Render parameters.  eps_alpha and t_min are part of the result's definition:
  * a (pixel, convex) pair with alpha < eps_alpha is skipped, and a pixel stops
  * after the convex that brings its transmittance below t_min.  tile = 0 picks
- * the default (16); supported: 16.  NULL = {1e-6, 1e-5, black, 0, 0}. */
+ * the default (16); supported: 8, 16, 32.  NULL = {1e-6, 1e-5, black, 0, 0}. */
 typedef struct {
     float eps_alpha, t_min;
     float background[3];
@@ -137,6 +144,49 @@ int cs_render_backward(cs_ctx *ctx, const cs_scene *scene, const cs_camera *cam,
 
 /* Release a forward state (stream-ordered after the work that uses it). */
 int cs_state_release(cs_ctx *ctx, cs_fwd_state *state);
+
+/* Batched multi-view render: n_views (1..256) views of one scene in one pass
+ * (paper Sec. 3.2 for each view).  All (view, convex) instances are
+ * preprocessed in one grid and depth-sorted together; their (tile, instance)
+ * pairs live in one global tile space and one persistent compositing grid
+ * takes the tiles of every view from per-XCD work queues.
+ *   cams:    host array of n_views cameras (resolutions may differ).
+ *   out_rgb: host array of n_views DEVICE pointers, each [h_v][w_v][3].
+ *   state:   as for cs_render_forward (required for the backward).
+ * With CS_FLAG_GRAPH the context keeps the batch's buffers (sized from the
+ * first frame's pair count plus a margin) and, from the second call on,
+ * replays one captured hipGraph; cameras, resolutions (within the first
+ * frame's tile and pixel totals) and output pointers may change between
+ * replays, the scene arrays, n_views, K and the tuning may not (a change
+ * re-captures).  A graph replay makes no host synchronisation; a frame whose
+ * pairs exceed the capacity is reported by cs_batch_check or the backward call
+ * as CS_EOVERFLOW (the buffers have then grown: render the frame again).  In
+ * graph mode a context holds one batch state at a time: the next batched
+ * forward invalidates the previous one. */
+int cs_render_forward_batch(cs_ctx *ctx, const cs_scene *scene, int32_t n_views, const cs_camera *cams,
+                            const cs_params *params, float *const *out_rgb, cs_fwd_state **state, void *hip_stream);
+
+/* Backward of a batched forward: gradients summed over the views.
+ *   dl_drgb: host array of n_views DEVICE pointers, each [h_v][w_v][3]. */
+int cs_render_backward_batch(cs_ctx *ctx, const cs_scene *scene, int32_t n_views, const cs_camera *cams,
+                             const cs_params *params, const cs_fwd_state *state, const float *const *dl_drgb,
+                             cs_grads *grads, void *hip_stream);
+
+/* Waits for a forward state's work; CS_EOVERFLOW if its pair buffer overflowed. */
+int cs_batch_check(cs_ctx *ctx, const cs_fwd_state *state);
+
+/* Autotuner: times the batched forward + backward for tile sizes {8, 16, 32},
+ * tile schedules {natural, longest-first} and pair-sort digit widths {6, 8} on
+ * the given scene and cameras, keeps the fastest in the context (keyed by
+ * K, SH degree, views and the log2 buckets of convex and pixel counts) and
+ * returns it.  Batched calls with tile = 0 and CS_FLAG_AUTOTUNE use it. */
+typedef struct {
+    int32_t tile, longest_first, digit_bits;
+    float ms;          /* fwd + bwd time of the winner */
+    float ms_default;  /* fwd + bwd time of tile 16, natural order, 8-bit digits */
+} cs_tuning;
+int cs_autotune(cs_ctx *ctx, const cs_scene *scene, int32_t n_views, const cs_camera *cams,
+                const cs_params *params, cs_tuning *out, void *hip_stream);
 
 /* Work counters of a forward state, copied to host (synchronises the stream):
  * n_pairs = (convex, tile) pairs binned; n_evaluated = (pixel, list entry)

@@ -22,11 +22,20 @@ MAX_K = 8
 EXPORTED = (
     "cs_version", "cs_last_error", "cs_create", "cs_destroy", "cs_render_forward", "cs_render_backward",
     "cs_state_release", "cs_state_stats", "cs_debug_preprocess", "cs_debug_tile_lists", "cs_l1_loss_grad",
-    "cs_timing_read",
+    "cs_timing_read", "cs_render_forward_batch", "cs_render_backward_batch", "cs_batch_check", "cs_autotune",
 )
 FLAG_TIMING = 1
+FLAG_LONGEST_FIRST = 2
+FLAG_GRAPH = 4
+FLAG_AUTOTUNE = 8
+
+
+def FLAG_DIGITS(b):
+    return (b & 15) << 8
+
+
 STAGES = ("preprocess", "depth_sort", "bin_scan", "emit", "tile_sort", "ranges", "render_fwd", "render_bwd",
-          "preprocess_bwd")
+          "preprocess_bwd", "order", "graph_fwd", "graph_bwd")
 
 
 class CSError(RuntimeError):
@@ -54,6 +63,11 @@ class GradsS(C.Structure):
 class Params(C.Structure):
     _fields_ = [("eps_alpha", C.c_float), ("t_min", C.c_float), ("background", C.c_float * 3),
                 ("tile", C.c_int32), ("flags", C.c_int32)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("longest_first", C.c_int32), ("digit_bits", C.c_int32), ("ms", C.c_float),
+                ("ms_default", C.c_float)]
 
 
 class DebugConvex(C.Structure):
@@ -86,6 +100,10 @@ def lib():
         L.cs_debug_preprocess.argtypes = [vp, vp, vp, vp, vp, vp]
         L.cs_debug_tile_lists.argtypes = [vp, vp, vp, i64, vp, i64]
         L.cs_l1_loss_grad.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
+        L.cs_render_forward_batch.argtypes = [vp, vp, i32, vp, vp, vp, C.POINTER(vp), vp]
+        L.cs_render_backward_batch.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp]
+        L.cs_batch_check.argtypes = [vp, vp]
+        L.cs_autotune.argtypes = [vp, vp, i32, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -177,8 +195,9 @@ class FwdState:
         return {"pairs": pairs.value, "evaluated": evals.value, "full": full.value}
 
     def tile_lists(self):
-        cam = self.cam
-        ntiles = ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
+        cams = self.cam if isinstance(self.cam, (list, tuple)) else [self.cam]
+        t = self.params.tile or 16
+        ntiles = sum(((c.width + t - 1) // t) * ((c.height + t - 1) // t) for c in cams)
         npairs = self.stats()["pairs"]
         ranges = np.zeros((ntiles, 2), np.int32)
         ids = np.zeros(max(npairs, 1), np.int32)
@@ -250,6 +269,51 @@ class Renderer:
         _check(lib().cs_debug_preprocess(self.ctx, C.byref(sS), C.byref(camS), C.byref(params or make_params()),
                                          out, _stream_handle(scene.points.device)))
         return out
+
+    def forward_batch(self, scene: DeviceScene, cams, params: Params | None = None, want_state=False, outs=None):
+        """Render several views of one scene in one pass; returns (list of images, state)."""
+        camS = [c if isinstance(c, Camera) else make_camera(c) for c in cams]
+        arr = (Camera * len(camS))(*camS)
+        params = params or make_params()
+        dev = scene.points.device
+        if outs is None:
+            outs = [torch.empty((c.height, c.width, 3), device=dev, dtype=torch.float32) for c in camS]
+        ptrs = (C.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        st = C.c_void_p()
+        sS = scene.struct()
+        _check(lib().cs_render_forward_batch(self.ctx, C.byref(sS), len(camS), arr, C.byref(params), ptrs,
+                                             C.byref(st) if want_state else None, _stream_handle(dev)))
+        state = FwdState(self, st.value, scene, camS, params) if want_state else None
+        return outs, state
+
+    def backward_batch(self, state: FwdState, dl_drgb_list, grads=None):
+        scene = state.scene
+        camS = state.cam
+        arr = (Camera * len(camS))(*camS)
+        dls = [d.contiguous() for d in dl_drgb_list]
+        ptrs = (C.c_void_p * len(dls))(*[d.data_ptr() for d in dls])
+        if grads is None:
+            grads = {k: torch.empty_like(getattr(scene, k)) for k in ("points", "delta", "sigma", "opacity", "sh")}
+        gS = GradsS(grads["points"].data_ptr(), grads["delta"].data_ptr(), grads["sigma"].data_ptr(),
+                    grads["opacity"].data_ptr(), grads["sh"].data_ptr())
+        sS = scene.struct()
+        _check(lib().cs_render_backward_batch(self.ctx, C.byref(sS), len(camS), arr, C.byref(state.params),
+                                              state.handle, ptrs, C.byref(gS), _stream_handle(dls[0].device)))
+        return grads
+
+    def batch_check(self, state: FwdState) -> int:
+        """0, or CS_EOVERFLOW when the state's pair buffer overflowed (render again)."""
+        return lib().cs_batch_check(self.ctx, state.handle)
+
+    def autotune(self, scene: DeviceScene, cams, params: Params | None = None) -> dict:
+        camS = [c if isinstance(c, Camera) else make_camera(c) for c in cams]
+        arr = (Camera * len(camS))(*camS)
+        t = Tuning()
+        sS = scene.struct()
+        _check(lib().cs_autotune(self.ctx, C.byref(sS), len(camS), arr, C.byref(params or make_params()),
+                                 C.byref(t), _stream_handle(scene.points.device)))
+        return {"tile": t.tile, "longest_first": t.longest_first, "digit_bits": t.digit_bits, "ms": t.ms,
+                "ms_default": t.ms_default}
 
     def timing(self, reset=True):
         """{stage: (total ms, launches)} of the calls made with FLAG_TIMING."""

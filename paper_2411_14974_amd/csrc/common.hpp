@@ -51,8 +51,35 @@ struct CamArgs {
 struct RenderArgs {
     float eps_alpha, t_min;
     float bg[3];
-    int32_t tile, tiles_x, tiles_y;
+    int32_t tile;
 };
+
+// One view of a (possibly batched) render, as the kernels read it from device
+// memory.  Tiles of all views share one global index space: view v owns
+// [tile_off, tile_off + tiles_x * tiles_y); its per-pixel state starts at pix_off.
+struct ViewDesc {
+    CamArgs cam;
+    int32_t tiles_x, tiles_y, tile_off, pad;
+    int64_t pix_off;
+    float *out_rgb;        // [H][W][3]
+    const float *dl_drgb;  // [H][W][3], backward only
+};
+
+// Header of the device view table; the ViewDesc array follows it.  Kernels
+// read the view count and the tile total from here, so a captured graph can be
+// replayed with other cameras and resolutions.
+struct FrameHeader {
+    uint32_t nviews, total_tiles;
+    int64_t total_pix;
+    uint32_t pad[12];
+};
+static_assert(sizeof(FrameHeader) == 64, "frame header is 64 bytes");
+
+constexpr int MAX_VIEWS = 256;
+constexpr int NUM_QUEUES = 8; // one work queue per XCD
+
+// Device counters of one frame (u32 words).
+enum : int { CNT_PAIRS = 0, CNT_PAIRS_EFF = 1, CNT_OVERFLOW = 2, CNT_QUEUE = 4 /* .. 4 + 2*NUM_QUEUES */, CNT_WORDS = 32 };
 
 // Host-visible debug record (mirrors cs_debug_convex of the public header).
 struct DebugConvex {

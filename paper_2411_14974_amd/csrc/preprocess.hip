@@ -41,14 +41,17 @@ __device__ __forceinline__ void pixel_span(double a, double b, int n, int &lo, i
 template <int K>
 __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
     int n, int deg, const float *__restrict__ points, const float *__restrict__ delta,
-    const float *__restrict__ sigma, const float *__restrict__ opacity, const float *__restrict__ sh, CamArgs cam,
-    RenderArgs ra, uint8_t *__restrict__ records, uint32_t *__restrict__ keys, uint32_t *__restrict__ ids,
-    uint2 *__restrict__ rects, uint32_t *__restrict__ counts, uint32_t *__restrict__ hullpk,
-    DebugConvex *__restrict__ dbg)
+    const float *__restrict__ sigma, const float *__restrict__ opacity, const float *__restrict__ sh,
+    const FrameHeader *__restrict__ frame, RenderArgs ra, uint8_t *__restrict__ records, uint32_t *__restrict__ keys,
+    uint32_t *__restrict__ ids, uint2 *__restrict__ rects, uint32_t *__restrict__ counts,
+    uint32_t *__restrict__ hullpk, DebugConvex *__restrict__ dbg)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    ids[i] = (uint32_t)i;
+    // one (view, convex) instance per thread; all outputs are indexed by the instance
+    const CamArgs cam = reinterpret_cast<const ViewDesc *>(frame + 1)[blockIdx.y].cam;
+    const size_t inst = (size_t)blockIdx.y * n + i;
+    ids[inst] = (uint32_t)inst;
 
     const float *p = points + (size_t)i * K * 3;
     float px[K], py[K], pz[K];
@@ -111,7 +114,7 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
 
         const double ox = rint(sx), oy = rint(sy);
         const double s2 = dp * LOG2E;
-        uint8_t *rec = records + (size_t)i * rec_stride(K);
+        uint8_t *rec = records + inst * rec_stride(K);
         double *lines = reinterpret_cast<double *>(rec + 64);
 
         // cut-off radius: outside { L_j <= r for all j } alpha < eps_alpha
@@ -214,7 +217,7 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
             h.opacity = (float)o;
             h.rgb[0] = rgb[0]; h.rgb[1] = rgb[1]; h.rgb[2] = rgb[2];
             h.T = T;
-            h.id = i;
+            h.id = (int32_t)inst;
 #pragma unroll
             for (int q = 0; q < 6; ++q) h.pad[q] = 0;
             const uint4 *hs = reinterpret_cast<const uint4 *>(&h);
@@ -251,14 +254,14 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
     }
 
     const bool has_tiles = status == ST_VISIBLE && tx0 <= tx1 && ty0 <= ty1;
-    keys[i] = status == ST_VISIBLE ? key : KEY_CULLED;
-    counts[i] = has_tiles ? (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1)) : 0u;
-    rects[i] = has_tiles ? make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16))
+    keys[inst] = status == ST_VISIBLE ? key : KEY_CULLED;
+    counts[inst] = has_tiles ? (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1)) : 0u;
+    rects[inst] = has_tiles ? make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16))
                          : make_uint2(1u, 0u);
-    hullpk[i] = (status == ST_VISIBLE || status == ST_FAINT) ? (packed | ((uint32_t)T << 28)) : 0u;
+    hullpk[inst] = (status == ST_VISIBLE || status == ST_FAINT) ? (packed | ((uint32_t)T << 28)) : 0u;
 
     if (dbg) {
-        DebugConvex &o = dbg[i];
+        DebugConvex &o = dbg[inst];
         o.status = status;
         o.T = (status == ST_NEAR) ? 0 : T;
         for (int j = 0; j < MAXK; ++j) {
@@ -281,40 +284,21 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
     }
 }
 
-// Backward, one thread per convex: chain the per-convex accumulators of the
-// compositing backward (base-2 line coefficients, sigma', opacity, colour)
-// through lines -> hull vertices -> projection -> points, delta' and sigma'
-// -> (delta, sigma, d), d -> every point, colour -> SH and view direction.
+// Backward, one thread per convex, summed over the views of the frame: chain
+// each instance's accumulators of the compositing backward (base-2 line
+// coefficients, sigma', opacity, colour, x2-weighted sum) through lines -> hull
+// vertices -> projection -> points, delta' and sigma' -> (delta, sigma, d),
+// d -> every point, colour -> SH and view direction.  The geometry is
+// recomputed from the points and the stored hull indices, bit-identically to
+// the forward pass.
 template <int K>
-__global__ __launch_bounds__(256) void preprocess_bwd_kernel(
-    int n, int deg, const float *__restrict__ points, const float *__restrict__ delta,
-    const float *__restrict__ sigma, const float *__restrict__ sh, CamArgs cam, const uint32_t *__restrict__ hullpk,
-    const float *__restrict__ acc, float *__restrict__ g_points,
-    float *__restrict__ g_delta, float *__restrict__ g_sigma, float *__restrict__ g_opacity,
-    float *__restrict__ g_sh)
+__device__ __forceinline__ void view_backward(int deg, const float *px, const float *py, const float *pz, double dl,
+                                              double sg, const float *f, const CamArgs &cam, uint32_t hp,
+                                              const float *__restrict__ A, float *gp, float &gdelta, float &gsigma,
+                                              float &gopac, float *gsh)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int nc = (deg + 1) * (deg + 1);
-    float *gp = g_points + (size_t)i * K * 3;
-    float *gs = g_sh + (size_t)i * nc * 3;
-    const uint32_t hp = hullpk[i];
     const int T = (int)(hp >> 28);
-    if (T < 3) { // dropped convex: no gradient
-#pragma unroll
-        for (int k = 0; k < 3 * K; ++k) gp[k] = 0.0f;
-        for (int c = 0; c < 3 * nc; ++c) gs[c] = 0.0f;
-        g_delta[i] = 0.0f;
-        g_sigma[i] = 0.0f;
-        g_opacity[i] = 0.0f;
-        return;
-    }
-    const float *A = acc + (size_t)i * acc_stride(K);
-
-    const float *p = points + (size_t)i * K * 3;
-    float px[K], py[K], pz[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) { px[k] = p[3 * k]; py[k] = p[3 * k + 1]; pz[k] = p[3 * k + 2]; }
+    const int nc = (deg + 1) * (deg + 1);
     double X[K], Y[K], Z[K], qx[K], qy[K];
     const double r0 = cam.R[0], r1 = cam.R[1], r2 = cam.R[2], r3 = cam.R[3], r4 = cam.R[4], r5 = cam.R[5];
     const double r6 = cam.R[6], r7 = cam.R[7], r8 = cam.R[8];
@@ -330,7 +314,6 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
         zs += Z[k];
     }
     const double dd = zs / K;
-    const double dl = (double)delta[i], sg = (double)sigma[i];
     const double dp = dd * dl;
     const double s2 = dp * LOG2E;
 
@@ -339,7 +322,8 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const int v = (hp >> (3 * j)) & 7;
-        vx[j] = 0.0; vy[j] = 0.0;
+        vx[j] = 0.0;
+        vy[j] = 0.0;
 #pragma unroll
         for (int k = 0; k < K; ++k)
             if (k == v) { vx[j] = qx[k]; vy[j] = qy[k]; }
@@ -363,10 +347,8 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
         const double tx = ex / len, ty = ey / len;
         const double nA = ty, nB = -tx;
         const double ax = vx[j] - ox, ay = vy[j] - oy;
-        // stored (a, b, c) = s2 * (A, B, C')
-        const double ga = (double)A[j], gb = (double)A[K + j], gc = (double)A[2 * K + j];
-        const double gA = s2 * ga, gB = s2 * gb, gC = s2 * gc;
-        // C' = -(A ax + B ay)
+        // stored (a, b, c) = s2 * (A, B, C'), C' = -(A ax + B ay)
+        const double gA = s2 * (double)A[j], gB = s2 * (double)A[K + j], gC = s2 * (double)A[2 * K + j];
         const double gAt = gA - gC * ax, gBt = gB - gC * ay;
         gvx[j] -= gC * nA;
         gvy[j] -= gC * nB;
@@ -382,9 +364,9 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     // x2_j = delta' log2(e) L_j  =>  dx2_j / ddelta' = x2_j / delta'
     const double gdp = (double)A[3 * K + 5] / dp;
     const double gsp = (double)A[3 * K];
-    g_delta[i] = (float)(dd * gdp);
-    g_sigma[i] = (float)(dd * gsp);
-    g_opacity[i] = A[3 * K + 1];
+    gdelta += (float)(dd * gdp);
+    gsigma += (float)(dd * gsp);
+    gopac += A[3 * K + 1];
     const double gd = dl * gdp + sg * gsp;
 
     // hull vertices -> projected points
@@ -409,7 +391,6 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     const float dx = (float)(wx / dist), dy = (float)(wy / dist), dz = (float)(wz / dist);
     float Yb[16];
     sh_eval(deg, dx, dy, dz, Yb);
-    const float *f = sh + (size_t)i * nc * 3;
     float raw[3] = {0.5f, 0.5f, 0.5f};
     for (int c = 0; c < nc; ++c) {
         raw[0] = fmaf(Yb[c], f[3 * c + 0], raw[0]);
@@ -421,9 +402,9 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     for (int c = 0; c < 3; ++c) graw[c] = raw[c] > 0.0f ? A[3 * K + 2 + c] : 0.0f;
     float wsum[16];
     for (int c = 0; c < nc; ++c) {
-        gs[3 * c + 0] = graw[0] * Yb[c];
-        gs[3 * c + 1] = graw[1] * Yb[c];
-        gs[3 * c + 2] = graw[2] * Yb[c];
+        gsh[3 * c + 0] += graw[0] * Yb[c];
+        gsh[3 * c + 1] += graw[1] * Yb[c];
+        gsh[3 * c + 2] += graw[2] * Yb[c];
         wsum[c] = graw[0] * f[3 * c + 0] + graw[1] * f[3 * c + 1] + graw[2] * f[3 * c + 2];
     }
     float gdx = 0.f, gdy = 0.f, gdz = 0.f;
@@ -441,10 +422,52 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
         const double iz = 1.0 / Z[k];
         const double gX = gqx[k] * fx * iz, gY = gqy[k] * fy * iz;
         const double gZ = -(gqx[k] * fx * X[k] + gqy[k] * fy * Y[k]) * iz * iz + gd / K;
-        gp[3 * k + 0] = (float)(r0 * gX + r3 * gY + r6 * gZ + gcx);
-        gp[3 * k + 1] = (float)(r1 * gX + r4 * gY + r7 * gZ + gcy);
-        gp[3 * k + 2] = (float)(r2 * gX + r5 * gY + r8 * gZ + gcz);
+        gp[3 * k + 0] += (float)(r0 * gX + r3 * gY + r6 * gZ + gcx);
+        gp[3 * k + 1] += (float)(r1 * gX + r4 * gY + r7 * gZ + gcy);
+        gp[3 * k + 2] += (float)(r2 * gX + r5 * gY + r8 * gZ + gcz);
     }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void preprocess_bwd_kernel(
+    int n, int nviews, int deg, const float *__restrict__ points, const float *__restrict__ delta,
+    const float *__restrict__ sigma, const float *__restrict__ sh, const FrameHeader *__restrict__ frame,
+    const uint32_t *__restrict__ hullpk, const float *__restrict__ acc, float *__restrict__ g_points,
+    float *__restrict__ g_delta, float *__restrict__ g_sigma, float *__restrict__ g_opacity,
+    float *__restrict__ g_sh)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int nc = (deg + 1) * (deg + 1);
+    float gp[3 * K], gsh[48];
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) gp[k] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 48; ++c) gsh[c] = 0.0f;
+    float gdelta = 0.0f, gsigma = 0.0f, gopac = 0.0f;
+
+    const float *p = points + (size_t)i * K * 3;
+    float px[K], py[K], pz[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) { px[k] = p[3 * k]; py[k] = p[3 * k + 1]; pz[k] = p[3 * k + 2]; }
+    const double dl = (double)delta[i], sg = (double)sigma[i];
+    const float *f = sh + (size_t)i * nc * 3;
+    const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
+    for (int v = 0; v < nviews; ++v) {
+        const size_t inst = (size_t)v * n + i;
+        const uint32_t hp = hullpk[inst];
+        if ((int)(hp >> 28) < 3) continue; // dropped in this view: no gradient
+        view_backward<K>(deg, px, py, pz, dl, sg, f, views[v].cam, hp, acc + inst * acc_stride(K), gp, gdelta,
+                         gsigma, gopac, gsh);
+    }
+    float *gpo = g_points + (size_t)i * K * 3;
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) gpo[k] = gp[k];
+    float *gso = g_sh + (size_t)i * nc * 3;
+    for (int c = 0; c < 3 * nc; ++c) gso[c] = gsh[c];
+    g_delta[i] = gdelta;
+    g_sigma[i] = gsigma;
+    g_opacity[i] = gopac;
 }
 
 // ------------------------------------------------------------- launchers ---
@@ -460,26 +483,26 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     default: break;                                                                                                \
     }
 
-void launch_preprocess_fwd(hipStream_t st, int n, int K, int deg, const float *points, const float *delta,
-                           const float *sigma, const float *opacity, const float *sh, const CamArgs &cam,
-                           const RenderArgs &ra, uint8_t *records, uint32_t *keys, uint32_t *ids, uint2 *rects,
-                           uint32_t *counts, uint32_t *hullpk, DebugConvex *dbg)
+void launch_preprocess_fwd(hipStream_t st, int n, int nviews, int K, int deg, const float *points,
+                           const float *delta, const float *sigma, const float *opacity, const float *sh,
+                           const FrameHeader *views, const RenderArgs &ra, uint8_t *records, uint32_t *keys,
+                           uint32_t *ids, uint2 *rects, uint32_t *counts, uint32_t *hullpk, DebugConvex *dbg)
 {
-    if (n <= 0) return;
-    dim3 grid((n + 255) / 256), block(256);
+    if (n <= 0 || nviews <= 0) return;
+    dim3 grid((n + 255) / 256, nviews), block(256);
     CS_DISPATCH_K(K, hipLaunchKernelGGL(preprocess_fwd_kernel<KK>, grid, block, 0, st, n, deg, points, delta, sigma,
-                                        opacity, sh, cam, ra, records, keys, ids, rects, counts, hullpk, dbg));
+                                        opacity, sh, views, ra, records, keys, ids, rects, counts, hullpk, dbg));
 }
 
-void launch_preprocess_bwd(hipStream_t st, int n, int K, int deg, const float *points, const float *delta,
-                           const float *sigma, const float *sh, const CamArgs &cam, const uint32_t *hullpk,
-                           const float *acc, float *g_points, float *g_delta, float *g_sigma,
-                           float *g_opacity, float *g_sh)
+void launch_preprocess_bwd(hipStream_t st, int n, int nviews, int K, int deg, const float *points,
+                           const float *delta, const float *sigma, const float *sh, const FrameHeader *views,
+                           const uint32_t *hullpk, const float *acc, float *g_points, float *g_delta,
+                           float *g_sigma, float *g_opacity, float *g_sh)
 {
     if (n <= 0) return;
     dim3 grid((n + 255) / 256), block(256);
-    CS_DISPATCH_K(K, hipLaunchKernelGGL(preprocess_bwd_kernel<KK>, grid, block, 0, st, n, deg, points, delta, sigma,
-                                        sh, cam, hullpk, acc, g_points, g_delta, g_sigma, g_opacity, g_sh));
+    CS_DISPATCH_K(K, hipLaunchKernelGGL(preprocess_bwd_kernel<KK>, grid, block, 0, st, n, nviews, deg, points, delta,
+                                        sigma, sh, views, hullpk, acc, g_points, g_delta, g_sigma, g_opacity, g_sh));
 }
 
 } // namespace cs

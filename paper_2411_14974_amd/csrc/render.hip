@@ -1,8 +1,9 @@
 // Per-tile compositing, forward and backward (gfx950).
 //
-// One 256-thread workgroup per 16x16 tile, one pixel per thread.  The tile's
-// depth-ordered convex list is streamed through LDS in batches of records;
-// every thread walks the batch front to back and evaluates, for its pixel,
+// One workgroup per tile (8x8, 16x16 or 32x32 pixels), one pixel per thread,
+// in a persistent grid that pulls tiles of all views from per-XCD work queues.
+// The tile's depth-ordered convex list is streamed through LDS in batches of
+// records; every thread walks the batch front to back and evaluates, for its pixel,
 //   x2_j = log2(e) delta' L_j(q)           (FP64: hull lines, Supp. B scaling)
 //   phi  = LogSumExp of the x_j            (Sec. 3.1 Eq. smoothness, base 2)
 //   I    = Sigmoid(-sigma' phi)            (Sec. 3.1 Eq. sharpness)
@@ -18,6 +19,8 @@
 // decisions), recovering T_n = T_{n+1} / (1 - alpha_n), and reduces the per-pair
 // gradients over the wavefront before one atomic add per convex value.
 #include <algorithm>
+#include <mutex>
+#include <unordered_map>
 #include <utility>
 
 #include "common.hpp"
@@ -25,9 +28,6 @@
 namespace cs {
 
 namespace {
-
-constexpr int TILE = 16;
-constexpr int BLOCK = 256;
 
 template <int K> struct PairEval {
     float I, omI, alpha, oma, phi2, inv_sum;
@@ -80,15 +80,6 @@ __device__ __forceinline__ bool eval_pair(const uint8_t *rec, float pxf, float p
     return true;
 }
 
-// Tiles are dealt to workgroups so that each of the 8 XCDs (which receive
-// workgroups round-robin) owns a contiguous band of tiles: neighbouring tiles
-// share convex records, and they then share an L2.
-__device__ __forceinline__ int xcd_tile(int ntiles)
-{
-    const int per_xcd = (ntiles + 7) / 8;
-    return (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
-}
-
 __device__ __forceinline__ float wave_sum(float x)
 {
     x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, true));  // quad_perm 1,0,3,2
@@ -102,76 +93,128 @@ __device__ __forceinline__ float wave_sum(float x)
     return (a + b) + (c + d);
 }
 
-template <int K, int BATCH>
+template <int K, int NT>
 __device__ __forceinline__ void load_batch(uint4 *lds, const uint32_t *__restrict__ ids,
                                            const uint8_t *__restrict__ records, int base, int cnt)
 {
     constexpr int CH = rec_stride(K) / 16;
-    for (int c = threadIdx.x; c < cnt * CH; c += BLOCK) {
+    for (int c = threadIdx.x; c < cnt * CH; c += NT) {
         const int e = c / CH, part = c - e * CH;
         const uint32_t id = ids[base + e];
         lds[c] = reinterpret_cast<const uint4 *>(records + (size_t)id * rec_stride(K))[part];
     }
 }
 
+// Work distribution of the persistent compositing grid.  Items (tiles of all
+// views, in the order given by `order`, or natural order) are split into one
+// contiguous band per XCD; a workgroup takes items from the queue of its own XCD
+// (workgroups are dealt to the 8 XCDs round-robin), so neighbouring tiles, which
+// share convex records, meet in one L2, and steals from the other queues when
+// its own runs dry.  Every workgroup exits once all queues are empty.
+__device__ __forceinline__ uint32_t next_item(uint32_t *counters, uint32_t total, int &q, int &tried,
+                                              uint32_t *s_item)
+{
+    if (threadIdx.x == 0) {
+        const uint32_t per = (total + NUM_QUEUES - 1) / NUM_QUEUES;
+        uint32_t item = 0xFFFFFFFFu;
+        while (tried < NUM_QUEUES) {
+            const uint32_t lo = q * per, hi = min(total, lo + per);
+            if (lo < hi) {
+                const uint32_t k = atomicAdd(&counters[CNT_QUEUE + 2 * q], 1u);
+                if (lo + k < hi) { item = lo + k; break; }
+            }
+            q = (q + 1) % NUM_QUEUES;
+            ++tried;
+        }
+        *s_item = item;
+    }
+    __syncthreads();
+    const uint32_t item = *s_item;
+    __syncthreads();
+    return item;
+}
+
+__device__ __forceinline__ int find_view(const ViewDesc *__restrict__ views, int nviews, int gt)
+{
+    int lo = 0, hi = nviews - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_off <= gt) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 } // namespace
 
-template <int K, int BATCH>
-__global__ __launch_bounds__(BLOCK) void render_fwd_kernel(const uint2 *__restrict__ ranges,
-                                                          const uint32_t *__restrict__ ids,
-                                                          const uint8_t *__restrict__ records, RenderArgs ra, int W,
-                                                          int H, float *__restrict__ out_rgb,
-                                                          uint2 *__restrict__ pixstate,
-                                                          unsigned long long *__restrict__ evalcount)
+template <int K, int TILE, int BATCH>
+__global__ __launch_bounds__(TILE *TILE) void render_fwd_kernel(
+    const FrameHeader *__restrict__ frame, const uint32_t *__restrict__ order, uint32_t *__restrict__ counters,
+    const uint2 *__restrict__ ranges, const uint32_t *__restrict__ ids,
+    const uint8_t *__restrict__ records, RenderArgs ra, uint2 *__restrict__ pixstate,
+    unsigned long long *__restrict__ evalcount)
 {
+    constexpr int NT = TILE * TILE;
     constexpr int CH = rec_stride(K) / 16;
     __shared__ uint4 lds[BATCH * CH];
-    const int ntiles = ra.tiles_x * ra.tiles_y;
-    const int tile = xcd_tile(ntiles);
-    if (tile >= ntiles) return;
-    const int tx = tile % ra.tiles_x, ty = tile / ra.tiles_x;
-    const int u = tx * TILE + (threadIdx.x & (TILE - 1)), v = ty * TILE + (threadIdx.x / TILE);
-    const bool inside = u < W && v < H;
-    const float pxf = (float)u + 0.5f, pyf = (float)v + 0.5f;
-    const uint2 rg = ranges[tile];
-    const int start = (int)rg.x, end = (int)rg.y;
+    __shared__ uint32_t s_item;
+    const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
+    const int nviews = (int)frame->nviews;
+    const uint32_t total_tiles = frame->total_tiles;
+    int q = blockIdx.x % NUM_QUEUES, tried = 0;
+    uint32_t nevals = 0, nfull = 0; // pairs tested / pairs past the max-line test
+    for (;;) {
+        const uint32_t item = next_item(counters, total_tiles, q, tried, &s_item);
+        if (item == 0xFFFFFFFFu) break;
+        const int gt = order ? (int)order[item] : (int)item;
+        const int v = find_view(views, nviews, gt);
+        const ViewDesc &vd = views[v];
+        const int lt = gt - vd.tile_off;
+        const int tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
+        const int W = vd.cam.W, H = vd.cam.H;
+        const int u = tx * TILE + (threadIdx.x % TILE), y = ty * TILE + (threadIdx.x / TILE);
+        const bool inside = u < W && y < H;
+        const float pxf = (float)u + 0.5f, pyf = (float)y + 0.5f;
+        const uint2 rg = ranges[gt];
+        const int start = (int)rg.x, end = (int)rg.y;
 
-    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, Tlast = 1.0f;
-    int nend = 0;
-    uint32_t nevals = 0, nfull = 0; // pairs evaluated / pairs past the max-line test
-    bool done = !inside;
-    for (int base = start; base < end; base += BATCH) {
-        const int cnt = min(BATCH, end - base);
-        __syncthreads();
-        load_batch<K, BATCH>(lds, ids, records, base, cnt);
-        __syncthreads();
-        if (!done) {
-            for (int e = 0; e < cnt; ++e) {
-                const uint8_t *rec = reinterpret_cast<const uint8_t *>(&lds[e * CH]);
-                PairEval<K> pe;
-                ++nevals;
-                const bool hit = eval_pair<K>(rec, pxf, pyf, ra.eps_alpha, pe);
-                if (evalcount) nfull += pe.inv_sum > 0.0f;
-                if (!hit) continue;
-                const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
-                const float w = T * pe.alpha;
-                C0 = fmaf(w, h.rgb[0], C0);
-                C1 = fmaf(w, h.rgb[1], C1);
-                C2 = fmaf(w, h.rgb[2], C2);
-                Tlast = T;
-                T = T * pe.oma;
-                nend = base - start + e + 1;
-                if (T < ra.t_min) { done = true; break; }
+        float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, Tlast = 1.0f;
+        int nend = 0;
+        bool done = !inside;
+        for (int base = start; base < end; base += BATCH) {
+            const int cnt = min(BATCH, end - base);
+            __syncthreads();
+            load_batch<K, NT>(lds, ids, records, base, cnt);
+            __syncthreads();
+            if (!done) {
+                for (int e = 0; e < cnt; ++e) {
+                    const uint8_t *rec = reinterpret_cast<const uint8_t *>(&lds[e * CH]);
+                    PairEval<K> pe;
+                    ++nevals;
+                    const bool hit = eval_pair<K>(rec, pxf, pyf, ra.eps_alpha, pe);
+                    nfull += pe.inv_sum > 0.0f;
+                    if (!hit) continue;
+                    const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
+                    const float w = T * pe.alpha;
+                    C0 = fmaf(w, h.rgb[0], C0);
+                    C1 = fmaf(w, h.rgb[1], C1);
+                    C2 = fmaf(w, h.rgb[2], C2);
+                    Tlast = T;
+                    T = T * pe.oma;
+                    nend = base - start + e + 1;
+                    if (T < ra.t_min) { done = true; break; }
+                }
             }
+            if (__syncthreads_and(done)) break;
         }
-        if (__syncthreads_and(done)) break;
-    }
-    if (inside) {
-        const size_t pix = (size_t)v * W + u;
-        out_rgb[3 * pix + 0] = fmaf(T, ra.bg[0], C0);
-        out_rgb[3 * pix + 1] = fmaf(T, ra.bg[1], C1);
-        out_rgb[3 * pix + 2] = fmaf(T, ra.bg[2], C2);
-        pixstate[pix] = make_uint2((uint32_t)nend, __float_as_uint(Tlast));
+        if (inside) {
+            const size_t pix = (size_t)y * W + u;
+            float *o = vd.out_rgb + 3 * pix;
+            o[0] = fmaf(T, ra.bg[0], C0);
+            o[1] = fmaf(T, ra.bg[1], C1);
+            o[2] = fmaf(T, ra.bg[2], C2);
+            pixstate[vd.pix_off + pix] = make_uint2((uint32_t)nend, __float_as_uint(Tlast));
+        }
     }
     if (evalcount) {
         unsigned long long c = nevals, f = nfull;
@@ -187,13 +230,14 @@ __global__ __launch_bounds__(BLOCK) void render_fwd_kernel(const uint2 *__restri
     }
 }
 
-template <int K, int BATCH>
-__global__ __launch_bounds__(BLOCK) void render_bwd_kernel(const uint2 *__restrict__ ranges,
-                                                          const uint32_t *__restrict__ ids,
-                                                          const uint8_t *__restrict__ records, RenderArgs ra, int W,
-                                                          int H, const float *__restrict__ dl_drgb,
-                                                          const uint2 *__restrict__ pixstate, float *__restrict__ acc)
+template <int K, int TILE, int BATCH>
+__global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
+    const FrameHeader *__restrict__ frame, const uint32_t *__restrict__ order, uint32_t *__restrict__ counters,
+    const uint2 *__restrict__ ranges, const uint32_t *__restrict__ ids,
+    const uint8_t *__restrict__ records, RenderArgs ra, const uint2 *__restrict__ pixstate,
+    float *__restrict__ acc)
 {
+    constexpr int NT = TILE * TILE;
     constexpr int CH = rec_stride(K) / 16;
     constexpr int NV = acc_values(K); // a[K] b[K] c[K] sigma' o rgb[3] x2-weighted sum
     constexpr int AS = acc_stride(K);
@@ -201,96 +245,107 @@ __global__ __launch_bounds__(BLOCK) void render_bwd_kernel(const uint2 *__restri
     __shared__ uint4 lds[BATCH * CH];
     __shared__ uint32_t s_ids[BATCH];
     __shared__ int s_maxn;
-    const int ntiles = ra.tiles_x * ra.tiles_y;
-    const int tile = xcd_tile(ntiles);
-    if (tile >= ntiles) return;
-    const int tx = tile % ra.tiles_x, ty = tile / ra.tiles_x;
-    const int u = tx * TILE + (threadIdx.x & (TILE - 1)), v = ty * TILE + (threadIdx.x / TILE);
-    const bool inside = u < W && v < H;
-    const float pxf = (float)u + 0.5f, pyf = (float)v + 0.5f;
+    __shared__ uint32_t s_item;
+    const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
+    const int nviews = (int)frame->nviews;
+    const uint32_t total_tiles = frame->total_tiles;
     const int lane = threadIdx.x & 63;
-    const uint2 rg = ranges[tile];
-    const int start = (int)rg.x;
+    int q = blockIdx.x % NUM_QUEUES, tried = 0;
+    for (;;) {
+        const uint32_t item = next_item(counters, total_tiles, q, tried, &s_item);
+        if (item == 0xFFFFFFFFu) break;
+        const int gt = order ? (int)order[item] : (int)item;
+        const int v = find_view(views, nviews, gt);
+        const ViewDesc &vd = views[v];
+        const int lt = gt - vd.tile_off;
+        const int tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
+        const int W = vd.cam.W, H = vd.cam.H;
+        const int u = tx * TILE + (threadIdx.x % TILE), y = ty * TILE + (threadIdx.x / TILE);
+        const bool inside = u < W && y < H;
+        const float pxf = (float)u + 0.5f, pyf = (float)y + 0.5f;
+        const int start = (int)ranges[gt].x;
 
-    float g0 = 0.f, g1 = 0.f, g2 = 0.f, Tlast = 1.f;
-    int nend = 0;
-    if (inside) {
-        const size_t pix = (size_t)v * W + u;
-        g0 = dl_drgb[3 * pix + 0];
-        g1 = dl_drgb[3 * pix + 1];
-        g2 = dl_drgb[3 * pix + 2];
-        const uint2 ps = pixstate[pix];
-        nend = (int)ps.x;
-        Tlast = __uint_as_float(ps.y);
-    }
-    if (threadIdx.x == 0) s_maxn = 0;
-    __syncthreads();
-    if (nend > 0) atomicMax(&s_maxn, nend);
-    __syncthreads();
-    const int maxn = s_maxn;
+        float g0 = 0.f, g1 = 0.f, g2 = 0.f, Tlast = 1.f;
+        int nend = 0;
+        if (inside) {
+            const size_t pix = (size_t)y * W + u;
+            const float *g = vd.dl_drgb + 3 * pix;
+            g0 = g[0];
+            g1 = g[1];
+            g2 = g[2];
+            const uint2 ps = pixstate[vd.pix_off + pix];
+            nend = (int)ps.x;
+            Tlast = __uint_as_float(ps.y);
+        }
+        if (threadIdx.x == 0) s_maxn = 0;
+        __syncthreads();
+        if (nend > 0) atomicMax(&s_maxn, nend);
+        __syncthreads();
+        const int maxn = s_maxn;
 
-    float B0 = ra.bg[0], B1 = ra.bg[1], B2 = ra.bg[2];
-    float Tcur = Tlast;
-    bool first = true;
-    for (int hi = maxn; hi > 0; hi -= BATCH) {
-        const int lo = max(hi - BATCH, 0);
-        const int cnt = hi - lo;
-        __syncthreads();
-        load_batch<K, BATCH>(lds, ids, records, start + lo, cnt);
-        for (int c = threadIdx.x; c < cnt; c += BLOCK) s_ids[c] = ids[start + lo + c];
-        __syncthreads();
-        for (int e = cnt - 1; e >= 0; --e) {
-            const int pos = lo + e;
-            if (!__any(pos < nend)) continue; // wave-uniform
-            const uint8_t *rec = reinterpret_cast<const uint8_t *>(&lds[e * CH]);
-            const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
-            PairEval<K> pe;
-            const bool contrib = (pos < nend) && eval_pair<K>(rec, pxf, pyf, ra.eps_alpha, pe);
-            if (__ballot(contrib) == 0ull) continue; // wave-uniform
-            float val[NV];
+        float B0 = ra.bg[0], B1 = ra.bg[1], B2 = ra.bg[2];
+        float Tcur = Tlast;
+        bool first = true;
+        for (int hi = maxn; hi > 0; hi -= BATCH) {
+            const int lo = max(hi - BATCH, 0);
+            const int cnt = hi - lo;
+            __syncthreads();
+            load_batch<K, NT>(lds, ids, records, start + lo, cnt);
+            for (int c = threadIdx.x; c < cnt; c += NT) s_ids[c] = ids[start + lo + c];
+            __syncthreads();
+            for (int e = cnt - 1; e >= 0; --e) {
+                const int pos = lo + e;
+                if (!__any(pos < nend)) continue; // wave-uniform
+                const uint8_t *rec = reinterpret_cast<const uint8_t *>(&lds[e * CH]);
+                const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
+                PairEval<K> pe;
+                const bool contrib = (pos < nend) && eval_pair<K>(rec, pxf, pyf, ra.eps_alpha, pe);
+                if (__ballot(contrib) == 0ull) continue; // wave-uniform
+                float val[NV];
 #pragma unroll
-            for (int q = 0; q < NV; ++q) val[q] = 0.0f;
-            if (contrib) {
-                const float Tn = first ? Tlast : Tcur / pe.oma;
-                first = false;
-                Tcur = Tn;
-                const float dLda = Tn * (g0 * (h.rgb[0] - B0) + g1 * (h.rgb[1] - B1) + g2 * (h.rgb[2] - B2));
-                const float ta = Tn * pe.alpha;
-                val[3 * K + 2] = g0 * ta;
-                val[3 * K + 3] = g1 * ta;
-                val[3 * K + 4] = g2 * ta;
-                val[3 * K + 1] = dLda * pe.I;
-                const float dLdz = -dLda * h.opacity * pe.I * pe.omI; // I = Sigmoid(-z), z = sigma' phi
-                val[3 * K] = dLdz * pe.phi2 * (float)LN2;
-                const float dLdphi2 = dLdz * h.sigma_p * (float)LN2;
-                const float dxf = pxf - h.ox, dyf = pyf - h.oy;
-                float gdl = 0.0f;
+                for (int qv = 0; qv < NV; ++qv) val[qv] = 0.0f;
+                if (contrib) {
+                    const float Tn = first ? Tlast : Tcur / pe.oma;
+                    first = false;
+                    Tcur = Tn;
+                    const float dLda = Tn * (g0 * (h.rgb[0] - B0) + g1 * (h.rgb[1] - B1) + g2 * (h.rgb[2] - B2));
+                    const float ta = Tn * pe.alpha;
+                    val[3 * K + 2] = g0 * ta;
+                    val[3 * K + 3] = g1 * ta;
+                    val[3 * K + 4] = g2 * ta;
+                    val[3 * K + 1] = dLda * pe.I;
+                    const float dLdz = -dLda * h.opacity * pe.I * pe.omI; // I = Sigmoid(-z), z = sigma' phi
+                    val[3 * K] = dLdz * pe.phi2 * (float)LN2;
+                    const float dLdphi2 = dLdz * h.sigma_p * (float)LN2;
+                    const float dxf = pxf - h.ox, dyf = pyf - h.oy;
+                    float gdl = 0.0f;
 #pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    const float gx = dLdphi2 * pe.e[j] * pe.inv_sum;
-                    val[j] = gx * dxf;
-                    val[K + j] = gx * dyf;
-                    val[2 * K + j] = gx;
-                    gdl = fmaf(gx, pe.x2[j], gdl);
+                    for (int j = 0; j < K; ++j) {
+                        const float gx = dLdphi2 * pe.e[j] * pe.inv_sum;
+                        val[j] = gx * dxf;
+                        val[K + j] = gx * dyf;
+                        val[2 * K + j] = gx;
+                        gdl = fmaf(gx, pe.x2[j], gdl);
+                    }
+                    val[3 * K + 5] = gdl;
+                    B0 = fmaf(pe.alpha, h.rgb[0], pe.oma * B0);
+                    B1 = fmaf(pe.alpha, h.rgb[1], pe.oma * B1);
+                    B2 = fmaf(pe.alpha, h.rgb[2], pe.oma * B2);
                 }
-                val[3 * K + 5] = gdl;
-                B0 = fmaf(pe.alpha, h.rgb[0], pe.oma * B0);
-                B1 = fmaf(pe.alpha, h.rgb[1], pe.oma * B1);
-                B2 = fmaf(pe.alpha, h.rgb[2], pe.oma * B2);
-            }
-            const int T = h.T;
-            float mine = 0.0f;
+                const int T = h.T;
+                float mine = 0.0f;
 #pragma unroll
-            for (int q = 0; q < NV; ++q) {
-                const int j = q < 3 * K ? q % K : 0;
-                if (j < T) { // uniform
-                    const float s = wave_sum(val[q]);
-                    if (lane == q) mine = s;
+                for (int qv = 0; qv < NV; ++qv) {
+                    const int j = qv < 3 * K ? qv % K : 0;
+                    if (j < T) { // uniform
+                        const float s = wave_sum(val[qv]);
+                        if (lane == qv) mine = s;
+                    }
                 }
+                const int jl = lane < 3 * K ? lane % K : 0;
+                if (lane < NV && jl < T && mine != 0.0f)
+                    unsafeAtomicAdd(&acc[(size_t)s_ids[e] * AS + lane], mine);
             }
-            const int jl = lane < 3 * K ? lane % K : 0;
-            if (lane < NV && jl < T && mine != 0.0f)
-                unsafeAtomicAdd(&acc[(size_t)s_ids[e] * AS + lane], mine);
         }
     }
 }
@@ -308,29 +363,59 @@ __global__ __launch_bounds__(BLOCK) void render_bwd_kernel(const uint2 *__restri
     default: break;                                                                                                \
     }
 
-constexpr int FWD_BATCH = 64;
-constexpr int BWD_BATCH = 64;
+#define CS_DISPATCH_TILE(TILEV, ...)                                                                               \
+    switch (TILEV) {                                                                                               \
+    case 8: { constexpr int TT = 8; constexpr int BB = 32; __VA_ARGS__; } break;                                   \
+    case 16: { constexpr int TT = 16; constexpr int BB = 64; __VA_ARGS__; } break;                                 \
+    case 32: { constexpr int TT = 32; constexpr int BB = 64; __VA_ARGS__; } break;                                 \
+    default: break;                                                                                                \
+    }
 
-int render_grid(int ntiles) { return ((ntiles + 7) / 8) * 8; }
-
-void launch_render_fwd(hipStream_t st, int K, int ntiles, const uint2 *ranges, const uint32_t *ids,
-                       const uint8_t *records, const RenderArgs &ra, int W, int H, float *out_rgb, uint2 *pixstate,
-                       unsigned long long *evalcount)
+namespace {
+// Resident workgroups of a kernel on the whole device, cached per kernel.
+template <class F> int persistent_grid(F kernel, int threads)
 {
-    if (ntiles <= 0) return;
-    dim3 grid(render_grid(ntiles)), block(BLOCK);
-    CS_DISPATCH_K(K, hipLaunchKernelGGL((render_fwd_kernel<KK, FWD_BATCH>), grid, block, 0, st, ranges, ids, records,
-                                        ra, W, H, out_rgb, pixstate, evalcount));
+    static std::mutex mu;
+    static std::unordered_map<const void *, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    const void *key = reinterpret_cast<const void *>(kernel);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int dev = 0, cus = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0);
+    const int g = std::max(1, cus) * std::max(1, per);
+    cache[key] = g;
+    return g;
+}
+} // namespace
+
+// max_items bounds the grid (a persistent grid larger than the work only idles).
+void launch_render_fwd(hipStream_t st, int K, int tile, const FrameHeader *frame, const uint32_t *order,
+                       uint32_t max_items, uint32_t *counters, const uint2 *ranges, const uint32_t *ids,
+                       const uint8_t *records, const RenderArgs &ra, uint2 *pixstate, unsigned long long *evalcount)
+{
+    if (max_items == 0) return;
+    CS_DISPATCH_K(K, CS_DISPATCH_TILE(tile, {
+        auto kern = render_fwd_kernel<KK, TT, BB>;
+        const int grid = std::min<int>(persistent_grid(kern, TT * TT), (int)max_items);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(TT * TT), 0, st, frame, order, counters, ranges, ids, records, ra,
+                           pixstate, evalcount);
+    }));
 }
 
-void launch_render_bwd(hipStream_t st, int K, int ntiles, const uint2 *ranges, const uint32_t *ids,
-                       const uint8_t *records, const RenderArgs &ra, int W, int H, const float *dl_drgb,
-                       const uint2 *pixstate, float *acc)
+void launch_render_bwd(hipStream_t st, int K, int tile, const FrameHeader *frame, const uint32_t *order,
+                       uint32_t max_items, uint32_t *counters, const uint2 *ranges, const uint32_t *ids,
+                       const uint8_t *records, const RenderArgs &ra, const uint2 *pixstate, float *acc)
 {
-    if (ntiles <= 0) return;
-    dim3 grid(render_grid(ntiles)), block(BLOCK);
-    CS_DISPATCH_K(K, hipLaunchKernelGGL((render_bwd_kernel<KK, BWD_BATCH>), grid, block, 0, st, ranges, ids, records,
-                                        ra, W, H, dl_drgb, pixstate, acc));
+    if (max_items == 0) return;
+    CS_DISPATCH_K(K, CS_DISPATCH_TILE(tile, {
+        auto kern = render_bwd_kernel<KK, TT, BB>;
+        const int grid = std::min<int>(persistent_grid(kern, TT * TT), (int)max_items);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(TT * TT), 0, st, frame, order, counters, ranges, ids, records, ra,
+                           pixstate, acc);
+    }));
 }
 
 // ------------------------------------------------------------ L1 loss ----

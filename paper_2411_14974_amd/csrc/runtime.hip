@@ -1,45 +1,54 @@
-// C-ABI runtime of the convex rasterizer: argument checks, stream-ordered
-// buffer management, and the launch sequence of the forward and backward
-// passes.  Every compute step runs in the HIP kernels of this library.
+// C-ABI runtime of the convex rasterizer: argument checks, frame buffers,
+// the launch sequence of the forward and backward passes (eager, or captured
+// into a hipGraph and replayed), the autotuner and the stage timers.  Every
+// compute step runs in the HIP kernels of this library.
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "convexsplat.h"
 #include "common.hpp"
+#include "runtime.hpp"
 
 namespace cs {
-void launch_preprocess_fwd(hipStream_t, int, int, int, const float *, const float *, const float *, const float *,
-                           const float *, const CamArgs &, const RenderArgs &, uint8_t *, uint32_t *, uint32_t *,
-                           uint2 *, uint32_t *, uint32_t *, DebugConvex *);
-void launch_preprocess_bwd(hipStream_t, int, int, int, const float *, const float *, const float *, const float *,
-                           const CamArgs &, const uint32_t *, const float *, float *, float *, float *, float *,
-                           float *);
+void launch_preprocess_fwd(hipStream_t, int, int, int, int, const float *, const float *, const float *,
+                           const float *, const float *, const FrameHeader *, const RenderArgs &, uint8_t *,
+                           uint32_t *, uint32_t *, uint2 *, uint32_t *, uint32_t *, DebugConvex *);
+void launch_preprocess_bwd(hipStream_t, int, int, int, int, const float *, const float *, const float *,
+                           const float *, const FrameHeader *, const uint32_t *, const float *, float *, float *,
+                           float *, float *, float *);
 void radix_sort(hipStream_t, uint32_t **, uint32_t **, uint32_t **, uint32_t **, uint32_t, const uint32_t *, int, int,
-                uint32_t *, uint32_t *);
+                uint32_t *, uint32_t *, int);
 int radix_blocks(uint32_t);
 size_t radix_hist_words(int);
 size_t scan_temp_words(uint32_t);
 void scan_exclusive(hipStream_t, const uint32_t *, uint32_t *, uint32_t, uint32_t *, uint32_t *);
 void launch_fill_u32(hipStream_t, uint32_t *, size_t, uint32_t);
 void launch_gather_counts(hipStream_t, uint32_t, const uint32_t *, const uint32_t *, uint32_t *);
-void launch_emit_pairs(hipStream_t, uint32_t, const uint32_t *, const uint32_t *, const uint2 *, int, uint32_t,
-                       uint32_t *, uint32_t *);
+void launch_emit_pairs(hipStream_t, uint32_t, uint32_t, const uint32_t *, const uint32_t *, const uint2 *,
+                       const FrameHeader *, uint32_t, uint32_t *, uint32_t *);
+void launch_clamp_pairs(hipStream_t, uint32_t *, uint32_t);
+void launch_tile_length_keys(hipStream_t, uint32_t, const uint2 *, uint32_t *, uint32_t *);
 void launch_tile_ranges(hipStream_t, const uint32_t *, uint32_t, const uint32_t *, uint32_t, uint2 *);
-void launch_render_fwd(hipStream_t, int, int, const uint2 *, const uint32_t *, const uint8_t *, const RenderArgs &,
-                       int, int, float *, uint2 *, unsigned long long *);
-void launch_render_bwd(hipStream_t, int, int, const uint2 *, const uint32_t *, const uint8_t *, const RenderArgs &,
-                       int, int, const float *, const uint2 *, float *);
+void launch_render_fwd(hipStream_t, int, int, const FrameHeader *, const uint32_t *, uint32_t, uint32_t *,
+                       const uint2 *, const uint32_t *, const uint8_t *, const RenderArgs &, uint2 *,
+                       unsigned long long *);
+void launch_render_bwd(hipStream_t, int, int, const FrameHeader *, const uint32_t *, uint32_t, uint32_t *,
+                       const uint2 *, const uint32_t *, const uint8_t *, const RenderArgs &, const uint2 *, float *);
 void launch_l1_grad(hipStream_t, const float *, const float *, size_t, float *, float *);
 } // namespace cs
 
 using namespace cs;
 
-namespace {
+// --------------------------------------------------------------- errors ----
 
+namespace cs {
 thread_local std::string g_err;
 
 int fail(int code, const char *fmt, ...)
@@ -52,80 +61,193 @@ int fail(int code, const char *fmt, ...)
     g_err = buf;
     return code;
 }
+} // namespace cs
 
-#define CS_HIP(expr)                                                                                               \
-    do {                                                                                                           \
-        hipError_t e_ = (expr);                                                                                    \
-        if (e_ != hipSuccess) return fail(CS_EHIP, "%s: %s", #expr, hipGetErrorString(e_));                        \
-    } while (0)
+namespace {
 
-#define CS_TRY(expr)                                                                                               \
-    do {                                                                                                           \
-        int r_ = (expr);                                                                                           \
-        if (r_ != CS_OK) return r_;                                                                                \
-    } while (0)
-
-int ilog2_ceil(uint32_t v)
+int ilog2_ceil(uint64_t v)
 {
     int b = 0;
-    while ((1u << b) < v) ++b;
+    while ((1ull << b) < v) ++b;
     return b;
 }
 
-// Stream-ordered allocations of one call; freed (stream-ordered) on scope exit
-// unless released to a longer-lived owner.
-struct Scratch {
-    hipStream_t st;
-    void *ptrs[32];
-    int n = 0;
-    explicit Scratch(hipStream_t s) : st(s) {}
-    ~Scratch()
-    {
-        for (int i = 0; i < n; ++i)
-            if (ptrs[i]) (void)hipFreeAsync(ptrs[i], st);
-    }
-    template <class T> int get(T **out, size_t count)
-    {
-        void *p = nullptr;
-        const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
-        hipError_t e = hipMallocAsync(&p, bytes, st);
-        if (e != hipSuccess) return fail(CS_ENOMEM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
-        ptrs[n++] = p;
-        *out = static_cast<T *>(p);
-        return CS_OK;
-    }
-    // hand one allocation over to a longer-lived owner
-    void keep(const void *p)
-    {
-        for (int i = 0; i < n; ++i)
-            if (ptrs[i] == p) ptrs[i] = nullptr;
-    }
-};
-
 } // namespace
+
+// -------------------------------------------------------- frame buffers ----
+
+namespace cs {
+
+int Frame::alloc(void **p, size_t bytes)
+{
+    bytes = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMallocAsync(p, bytes, st);
+    if (e != hipSuccess) return fail(CS_ENOMEM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    allocs.push_back(*p);
+    bytes_held += bytes;
+    return CS_OK;
+}
+
+void Frame::release_buffer(void *p)
+{
+    for (auto &a : allocs)
+        if (a == p) {
+            (void)hipFreeAsync(a, st);
+            a = nullptr;
+        }
+}
+
+Frame::~Frame()
+{
+    if (gfwd) (void)hipGraphExecDestroy(gfwd);
+    if (gbwd) (void)hipGraphExecDestroy(gbwd);
+    for (void *p : allocs)
+        if (p) (void)hipFreeAsync(p, st);
+    if (counters_ev) (void)hipEventSynchronize(counters_ev), (void)hipEventDestroy(counters_ev);
+    if (h_counters) (void)hipHostFree(h_counters);
+}
+
+static constexpr size_t VIEW_TABLE_BYTES = sizeof(FrameHeader) + sizeof(ViewDesc) * MAX_VIEWS;
+
+int HostRing::init()
+{
+    for (auto &s : slot) {
+        if (hipHostMalloc(&s.host, VIEW_TABLE_BYTES, hipHostMallocDefault) != hipSuccess)
+            return fail(CS_ENOMEM, "pinned staging allocation failed");
+        if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess)
+            return fail(CS_EHIP, "event creation failed");
+    }
+    if (hipHostMalloc((void **)&h_word, 64, hipHostMallocDefault) != hipSuccess)
+        return fail(CS_ENOMEM, "pinned allocation failed");
+    return CS_OK;
+}
+
+HostRing::~HostRing()
+{
+    for (auto &s : slot) {
+        if (s.ev) (void)hipEventSynchronize(s.ev), (void)hipEventDestroy(s.ev);
+        if (s.host) (void)hipHostFree(s.host);
+    }
+    if (h_word) (void)hipHostFree(h_word);
+}
+
+int Frame::init_async_readback()
+{
+    if (h_counters) return CS_OK;
+    if (hipHostMalloc((void **)&h_counters, CNT_WORDS * 4, hipHostMallocDefault) != hipSuccess)
+        return fail(CS_ENOMEM, "pinned counter allocation failed");
+    std::memset(h_counters, 0, CNT_WORDS * 4);
+    if (hipEventCreateWithFlags(&counters_ev, hipEventDisableTiming) != hipSuccess)
+        return fail(CS_EHIP, "event creation failed");
+    return CS_OK;
+}
+
+// Instance-, tile- and pixel-level buffers (pairs come later).
+int Frame::init(int n_, int K_, int deg_, int V_, size_t tiles, size_t pix, hipStream_t s, HostRing *r)
+{
+    n = n_; K = K_; deg = deg_; V = V_; st = s; ring = r;
+    cap_inst = (size_t)n * V;
+    cap_tiles = std::max<size_t>(tiles, 1);
+    cap_pix = std::max<size_t>(pix, 1);
+    const uint32_t ui = (uint32_t)cap_inst;
+    nb_inst = radix_blocks(ui);
+    nb_tiles = radix_blocks((uint32_t)cap_tiles);
+#define CS_A(ptr, bytes) do { int r_ = alloc((void **)&(ptr), (bytes)); if (r_) return r_; } while (0)
+    CS_A(d_frame, VIEW_TABLE_BYTES);
+    CS_A(records, cap_inst * rec_stride(K));
+    CS_A(keys, cap_inst * 4);
+    CS_A(ids, cap_inst * 4);
+    CS_A(keys_alt, cap_inst * 4);
+    CS_A(ids_alt, cap_inst * 4);
+    CS_A(counts, cap_inst * 4);
+    CS_A(counts_sorted, cap_inst * 4);
+    CS_A(offsets, cap_inst * 4);
+    CS_A(hullpk, cap_inst * 4);
+    CS_A(rects, cap_inst * 8);
+    CS_A(ranges, cap_tiles * 8);
+    CS_A(ord_k, cap_tiles * 4);
+    CS_A(ord_v, cap_tiles * 4);
+    CS_A(ord_k_alt, cap_tiles * 4);
+    CS_A(ord_v_alt, cap_tiles * 4);
+    CS_A(pixstate, cap_pix * 8);
+    CS_A(counters, CNT_WORDS * 4);
+    CS_A(evalcount, 16);
+#undef CS_A
+    return CS_OK;
+}
+
+int Frame::ensure_pairs(size_t m)
+{
+    if (m <= cap_pairs && pt) return CS_OK;
+    for (void *p : {(void *)pt, (void *)pi, (void *)pt_alt, (void *)pi_alt, (void *)hist, (void *)scan_tmp})
+        if (p) release_buffer(p);
+    cap_pairs = std::max<size_t>(m, 1);
+    nb_pairs = radix_blocks((uint32_t)cap_pairs);
+    const int nb = std::max(std::max(nb_inst, nb_pairs), nb_tiles);
+    const size_t hw = radix_hist_words(nb);
+    const size_t scan_n = std::max<size_t>(std::max<size_t>(hw, cap_inst), cap_tiles);
+#define CS_A(ptr, bytes) do { int r_ = alloc((void **)&(ptr), (bytes)); if (r_) return r_; } while (0)
+    CS_A(pt, cap_pairs * 4);
+    CS_A(pi, cap_pairs * 4);
+    CS_A(pt_alt, cap_pairs * 4);
+    CS_A(pi_alt, cap_pairs * 4);
+    CS_A(hist, hw * 4);
+    CS_A(scan_tmp, (scan_temp_words((uint32_t)scan_n) + 16) * 4);
+#undef CS_A
+    return CS_OK;
+}
+
+int Frame::ensure_acc()
+{
+    if (acc) return CS_OK;
+    return alloc((void **)&acc, cap_inst * acc_stride(K) * 4);
+}
+
+// Upload the view table through the context's ring of pinned staging buffers.
+int Frame::upload_views(const FrameHeader &hdr, const ViewDesc *views)
+{
+    HostRing::Slot &sg = ring->slot[ring->next];
+    ring->next = (ring->next + 1) % (int)(sizeof(ring->slot) / sizeof(ring->slot[0]));
+    if (sg.used) {
+        hipError_t e = hipEventSynchronize(sg.ev);
+        if (e != hipSuccess) return fail(CS_EHIP, "staging wait: %s", hipGetErrorString(e));
+    }
+    std::memcpy(sg.host, &hdr, sizeof(hdr));
+    std::memcpy((char *)sg.host + sizeof(FrameHeader), views, sizeof(ViewDesc) * hdr.nviews);
+    const size_t bytes = sizeof(FrameHeader) + sizeof(ViewDesc) * hdr.nviews;
+    hipError_t e = hipMemcpyAsync(d_frame, sg.host, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return fail(CS_EHIP, "view table upload: %s", hipGetErrorString(e));
+    (void)hipEventRecord(sg.ev, st);
+    sg.used = true;
+    return CS_OK;
+}
+
+} // namespace cs
+
+// ------------------------------------------------------------- context -----
 
 struct cs_ctx {
     int device = 0;
     size_t budget = 0;
-    uint32_t *h_word = nullptr; // pinned host word for the pair-count read-back
+    HostRing ring;
     // stage timing
     struct Pending { int stage; hipEvent_t a, b; };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> spare;
     double stage_ms[CS_NUM_STAGES] = {};
     int64_t stage_count[CS_NUM_STAGES] = {};
+    // batched graph frame and tuning cache
+    hipStream_t capture_stream = nullptr; // graphs are captured here (the null stream cannot be) and launched on the caller's
+    Frame *batch = nullptr;
+    uint64_t batch_key = 0;
+    std::map<std::tuple<int, int, int, int, int>, cs_tuning> tune;
 };
 
 struct cs_fwd_state {
-    int n = 0, K = 0, deg = 0, W = 0, H = 0, tiles_x = 0, tiles_y = 0;
-    uint32_t npairs = 0;
-    hipStream_t stream = nullptr;
-    uint8_t *records = nullptr;
-    uint32_t *hullpk = nullptr;
-    uint32_t *pair_ids = nullptr;
-    uint2 *ranges = nullptr;
-    uint2 *pixstate = nullptr;
-    unsigned long long *evalcount = nullptr;
+    Frame *frame = nullptr;
+    bool owned = true; // plain states own their frame; batch-graph states borrow the context's
+    int nviews = 1;
+    uint64_t epoch = 0;
 };
 
 namespace {
@@ -136,7 +258,7 @@ struct StageTimer {
     hipStream_t st;
     bool on;
     hipEvent_t a = nullptr;
-    StageTimer(cs_ctx *c, hipStream_t s, const cs_params *p) : ctx(c), st(s), on(p && (p->flags & CS_FLAG_TIMING)) {}
+    StageTimer(cs_ctx *c, hipStream_t s, bool enabled) : ctx(c), st(s), on(enabled) {}
     hipEvent_t take()
     {
         if (!ctx->spare.empty()) {
@@ -187,8 +309,9 @@ int check_camera(const cs_camera *c)
     return CS_OK;
 }
 
-int make_args(const cs_camera *c, const cs_params *p, CamArgs &ca, RenderArgs &ra)
+CamArgs cam_args(const cs_camera *c)
 {
+    CamArgs ca;
     ca.W = c->width;
     ca.H = c->height;
     ca.fx = c->fx; ca.fy = c->fy; ca.cx = c->cx; ca.cy = c->cy;
@@ -197,25 +320,242 @@ int make_args(const cs_camera *c, const cs_params *p, CamArgs &ca, RenderArgs &r
     ca.znear = c->znear;
     for (int r = 0; r < 3; ++r)
         ca.campos[r] = -((double)c->R[r] * c->t[0] + (double)c->R[3 + r] * c->t[1] + (double)c->R[6 + r] * c->t[2]);
+    return ca;
+}
+
+struct Knobs {
+    int tile = 16, longest = 0, digits = 8;
+};
+
+int render_args(const cs_params *p, RenderArgs &ra, Knobs &kn)
+{
     ra.eps_alpha = p ? p->eps_alpha : 1e-6f;
     ra.t_min = p ? p->t_min : 1e-5f;
     for (int i = 0; i < 3; ++i) ra.bg[i] = p ? p->background[i] : 0.0f;
-    int tile = p ? p->tile : 0;
-    if (tile == 0) tile = 16;
-    if (tile != 16) return fail(CS_EINVAL, "tile size %d unsupported (16)", tile);
+    const int flags = p ? p->flags : 0;
+    kn.tile = p ? p->tile : 0;
+    if (kn.tile == 0) kn.tile = 16;
+    if (kn.tile != 8 && kn.tile != 16 && kn.tile != 32) return fail(CS_EINVAL, "tile size %d unsupported (8, 16, 32)", kn.tile);
+    kn.longest = (flags & CS_FLAG_LONGEST_FIRST) ? 1 : 0;
+    kn.digits = (flags >> 8) & 15;
+    if (kn.digits == 0) kn.digits = 8;
+    if (kn.digits < 4 || kn.digits > 8) return fail(CS_EINVAL, "pair-sort digit width %d outside [4, 8]", kn.digits);
     if (!(ra.eps_alpha > 0.0f) || !(ra.eps_alpha < 1.0f)) return fail(CS_EINVAL, "eps_alpha must be in (0, 1)");
     if (!(ra.t_min >= 0.0f) || !(ra.t_min < 1.0f)) return fail(CS_EINVAL, "t_min must be in [0, 1)");
-    ra.tile = tile;
-    ra.tiles_x = (c->width + tile - 1) / tile;
-    ra.tiles_y = (c->height + tile - 1) / tile;
+    ra.tile = kn.tile;
+    return CS_OK;
+}
+
+// Host view table of a call: tile and pixel offsets of every view.
+struct ViewPlan {
+    FrameHeader hdr{};
+    std::vector<ViewDesc> views;
+};
+
+int plan_views(int nviews, const cs_camera *cams, int tile, float *const *out, const float *const *dl, ViewPlan &vp)
+{
+    if (nviews < 1 || nviews > MAX_VIEWS) return fail(CS_EINVAL, "n_views = %d outside [1, %d]", nviews, MAX_VIEWS);
+    if (!cams) return fail(CS_EINVAL, "cameras are NULL");
+    vp.views.resize(nviews);
+    int64_t toff = 0, poff = 0;
+    for (int v = 0; v < nviews; ++v) {
+        int r = check_camera(&cams[v]);
+        if (r) return r;
+        ViewDesc &d = vp.views[v];
+        std::memset(&d, 0, sizeof(d));
+        d.cam = cam_args(&cams[v]);
+        d.tiles_x = (cams[v].width + tile - 1) / tile;
+        d.tiles_y = (cams[v].height + tile - 1) / tile;
+        d.tile_off = (int32_t)toff;
+        d.pix_off = poff;
+        d.out_rgb = out ? out[v] : nullptr;
+        d.dl_drgb = dl ? dl[v] : nullptr;
+        toff += (int64_t)d.tiles_x * d.tiles_y;
+        poff += (int64_t)cams[v].width * cams[v].height;
+    }
+    if (toff >= (1ll << 30)) return fail(CS_EINVAL, "too many tiles in one call");
+    vp.hdr.nviews = (uint32_t)nviews;
+    vp.hdr.total_tiles = (uint32_t)toff;
+    vp.hdr.total_pix = poff;
+    return CS_OK;
+}
+
+// --------------------------------------------------------- launch sequence --
+
+// Forward pass on frame F.  device_count: the pair count stays on the device
+// (fixed capacities, graph capture); otherwise it is read back to size the
+// pair buffers exactly (plus `margin`).
+int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs &ra, const Knobs &kn,
+                    bool device_count, double margin, StageTimer &tm)
+{
+    hipStream_t st = F.st;
+    const int n = sc->n;
+    const uint32_t ninst = (uint32_t)F.cap_inst;
+    F.tile = kn.tile;
+    F.longest = kn.longest;
+    F.digits = kn.digits;
+    launch_fill_u32(st, F.counters, CNT_WORDS, 0u);
+    launch_fill_u32(st, reinterpret_cast<uint32_t *>(F.evalcount), 4, 0u);
+    tm.begin();
+    launch_preprocess_fwd(st, n, F.V, F.K, F.deg, sc->points, sc->delta, sc->sigma, sc->opacity, sc->sh, F.d_frame,
+                          ra, F.records, F.keys, F.ids, F.rects, F.counts, F.hullpk, nullptr);
+    tm.end(CS_STAGE_PREPROCESS);
+
+    uint32_t *keys = F.keys, *ids = F.ids, *keys_alt = F.keys_alt, *ids_alt = F.ids_alt;
+    uint32_t M = 0;
+    if (ninst > 0) {
+        if (!F.pt) { // first sizing: the sort temporaries come with the pair buffers
+            int r = F.ensure_pairs(1);
+            if (r) return r;
+        }
+        tm.begin();
+        radix_sort(st, &keys, &ids, &keys_alt, &ids_alt, ninst, nullptr, F.nb_inst, 32, F.hist, F.scan_tmp, 8);
+        tm.end(CS_STAGE_DEPTH_SORT);
+        tm.begin();
+        launch_gather_counts(st, ninst, ids, F.counts, F.counts_sorted);
+        scan_exclusive(st, F.counts_sorted, F.offsets, ninst, F.counters + CNT_PAIRS, F.scan_tmp);
+        tm.end(CS_STAGE_BIN_SCAN);
+        if (!device_count) {
+            uint32_t *hw = F.ring->h_word;
+            hipError_t e = hipMemcpyAsync(hw, F.counters + CNT_PAIRS, 4, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return fail(CS_EHIP, "pair count read-back: %s", hipGetErrorString(e));
+            M = hw[0];
+            int r = F.ensure_pairs((size_t)std::ceil(M * margin));
+            if (r) return r;
+            F.npairs = M;
+        }
+    }
+    if (!F.pt) {
+        int r = F.ensure_pairs(1);
+        if (r) return r;
+    }
+    launch_clamp_pairs(st, F.counters, (uint32_t)F.cap_pairs);
+    const uint32_t *m_dev = device_count ? F.counters + CNT_PAIRS_EFF : nullptr;
+    launch_fill_u32(st, reinterpret_cast<uint32_t *>(F.ranges), 2 * F.cap_tiles, 0u);
+    uint32_t *pt = F.pt, *pi = F.pi, *pt_alt = F.pt_alt, *pi_alt = F.pi_alt;
+    if (ninst > 0) {
+        tm.begin();
+        launch_emit_pairs(st, ninst, (uint32_t)n, ids, F.offsets, F.rects, F.d_frame, (uint32_t)F.cap_pairs, pt, pi);
+        tm.end(CS_STAGE_EMIT);
+        const int tile_bits = std::max(1, ilog2_ceil(F.cap_tiles));
+        tm.begin();
+        radix_sort(st, &pt, &pi, &pt_alt, &pi_alt, M, m_dev, F.nb_pairs, tile_bits, F.hist, F.scan_tmp, kn.digits);
+        tm.end(CS_STAGE_TILE_SORT);
+        tm.begin();
+        launch_tile_ranges(st, pt, M, m_dev, device_count ? (uint32_t)F.cap_pairs : M, F.ranges);
+        tm.end(CS_STAGE_RANGES);
+    }
+    F.sorted_ids = pi;
+    F.order = nullptr;
+    if (kn.longest) {
+        uint32_t *ok = F.ord_k, *ov = F.ord_v, *ok2 = F.ord_k_alt, *ov2 = F.ord_v_alt;
+        tm.begin();
+        launch_tile_length_keys(st, (uint32_t)F.cap_tiles, F.ranges, ok, ov);
+        radix_sort(st, &ok, &ov, &ok2, &ov2, (uint32_t)F.cap_tiles, nullptr, F.nb_tiles, 16, F.hist, F.scan_tmp, 8);
+        tm.end(CS_STAGE_ORDER);
+        F.order = ov;
+    }
+    tm.begin();
+    launch_render_fwd(st, F.K, kn.tile, F.d_frame, F.order, (uint32_t)F.cap_tiles, F.counters, F.ranges,
+                      F.sorted_ids, F.records, ra, F.pixstate, F.evalcount);
+    tm.end(CS_STAGE_RENDER_FWD);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CS_EHIP, "kernel launch: %s", hipGetErrorString(e));
+    return CS_OK;
+}
+
+int enqueue_backward(Frame &F, const cs_scene *sc, const cs_grads *g, const RenderArgs &ra, StageTimer &tm)
+{
+    hipStream_t st = F.st;
+    int r = F.ensure_acc();
+    if (r) return r;
+    launch_fill_u32(st, reinterpret_cast<uint32_t *>(F.acc), F.cap_inst * acc_stride(F.K), 0u);
+    launch_fill_u32(st, F.counters + CNT_QUEUE, 2 * NUM_QUEUES, 0u);
+    tm.begin();
+    launch_render_bwd(st, F.K, F.tile, F.d_frame, F.order, (uint32_t)F.cap_tiles, F.counters, F.ranges, F.sorted_ids,
+                      F.records, ra, F.pixstate, F.acc);
+    tm.end(CS_STAGE_RENDER_BWD);
+    tm.begin();
+    launch_preprocess_bwd(st, sc->n, F.V, F.K, F.deg, sc->points, sc->delta, sc->sigma, sc->sh, F.d_frame, F.hullpk,
+                          F.acc, g->points, g->delta, g->sigma, g->opacity, g->sh);
+    tm.end(CS_STAGE_PREPROCESS_BWD);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CS_EHIP, "kernel launch: %s", hipGetErrorString(e));
+    return CS_OK;
+}
+
+// Capture the work `enqueue` issues on frame F into an executable graph.
+template <class Fn> int capture_graph(cs_ctx *ctx, Frame &F, hipGraphExec_t *exec, Fn enqueue)
+{
+    if (!ctx->capture_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail(CS_EHIP, "capture stream: %s", hipGetErrorString(e));
+    }
+    hipStream_t caller = F.st;
+    F.st = ctx->capture_stream;
+    hipError_t e = hipStreamBeginCapture(F.st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        F.st = caller;
+        return fail(CS_EHIP, "begin capture: %s", hipGetErrorString(e));
+    }
+    int r = enqueue();
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(F.st, &g);
+    F.st = caller;
+    if (r) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    if (e != hipSuccess) return fail(CS_EHIP, "graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(CS_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+    return CS_OK;
+}
+
+uint64_t mix(uint64_t h, uint64_t v) { return (h ^ (v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2))); }
+
+uint64_t scene_key(const cs_scene *sc, int V, const Knobs &kn, const RenderArgs &ra)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (uint64_t v : {(uint64_t)sc->n, (uint64_t)sc->k, (uint64_t)sc->sh_degree, (uint64_t)V,
+                       (uint64_t)(uintptr_t)sc->points, (uint64_t)(uintptr_t)sc->delta, (uint64_t)(uintptr_t)sc->sigma,
+                       (uint64_t)(uintptr_t)sc->opacity, (uint64_t)(uintptr_t)sc->sh, (uint64_t)kn.tile,
+                       (uint64_t)kn.longest, (uint64_t)kn.digits})
+        h = mix(h, v);
+    uint32_t bits[5];
+    std::memcpy(bits, &ra, sizeof(float) * 5);
+    for (uint32_t b : bits) h = mix(h, b);
+    return h;
+}
+
+int check_grads(const cs_scene *sc, const cs_grads *g)
+{
+    if (!g) return fail(CS_EINVAL, "grads is NULL");
+    if (sc->n > 0 && (!g->points || !g->delta || !g->sigma || !g->opacity || !g->sh))
+        return fail(CS_EINVAL, "gradient array pointer is NULL");
     return CS_OK;
 }
 
 } // namespace
 
+#define CS_TRY(expr)                                                                                               \
+    do {                                                                                                           \
+        int r_ = (expr);                                                                                           \
+        if (r_ != CS_OK) return r_;                                                                                \
+    } while (0)
+#define CS_HIP(expr)                                                                                               \
+    do {                                                                                                           \
+        hipError_t e_ = (expr);                                                                                    \
+        if (e_ != hipSuccess) return fail(CS_EHIP, "%s: %s", #expr, hipGetErrorString(e_));                        \
+    } while (0)
+
+// ---------------------------------------------------------- entry points ---
+
 extern "C" {
 
-int cs_version(void) { return 100; }
+int cs_version(void) { return 200; }
 
 const char *cs_last_error(void) { return g_err.c_str(); }
 
@@ -238,9 +578,10 @@ int cs_create(int device, size_t hbm_budget_bytes, cs_ctx **out)
     cs_ctx *c = new cs_ctx;
     c->device = device;
     c->budget = hbm_budget_bytes;
-    if (hipHostMalloc((void **)&c->h_word, 16, hipHostMallocDefault) != hipSuccess) {
+    int r = c->ring.init();
+    if (r) {
         delete c;
-        return fail(CS_ENOMEM, "pinned host allocation failed");
+        return r;
     }
     *out = c;
     return CS_OK;
@@ -251,7 +592,9 @@ int cs_destroy(cs_ctx *ctx)
     if (!ctx) return CS_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    if (ctx->h_word) (void)hipHostFree(ctx->h_word);
+    delete ctx->batch;
+    (void)hipDeviceSynchronize();
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     for (auto &p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     for (auto e : ctx->spare) (void)hipEventDestroy(e);
     delete ctx;
@@ -262,9 +605,7 @@ int cs_state_release(cs_ctx *ctx, cs_fwd_state *s)
 {
     if (!s) return CS_OK;
     if (ctx) (void)hipSetDevice(ctx->device);
-    void *ptrs[] = {s->records, s->hullpk, s->pair_ids, s->ranges, s->pixstate, s->evalcount};
-    for (void *p : ptrs)
-        if (p) (void)hipFreeAsync(p, s->stream);
+    if (s->owned) delete s->frame;
     delete s;
     return CS_OK;
 }
@@ -277,101 +618,30 @@ int cs_render_forward(cs_ctx *ctx, const cs_scene *sc, const cs_camera *cam, con
     CS_TRY(check_scene(sc));
     CS_TRY(check_camera(cam));
     if (!out_rgb) return fail(CS_EINVAL, "out_rgb is NULL");
-    CamArgs ca;
     RenderArgs ra;
-    CS_TRY(make_args(cam, prm, ca, ra));
+    Knobs kn;
+    CS_TRY(render_args(prm, ra, kn));
     CS_HIP(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)hip_stream;
-    const int n = sc->n, K = sc->k;
-    const int ntiles = ra.tiles_x * ra.tiles_y;
-    const uint32_t un = (uint32_t)n;
-
-    Scratch S(st);
-    uint8_t *records;
-    uint32_t *keys, *ids, *keys_alt, *ids_alt, *counts, *hullpk, *counts_sorted, *offsets, *hist, *scan_tmp, *total;
-    uint2 *rects, *ranges, *pixstate;
-    unsigned long long *evalcount;
-    const int nb_depth = radix_blocks(un);
-    CS_TRY(S.get(&records, (size_t)n * rec_stride(K)));
-    CS_TRY(S.get(&keys, n));
-    CS_TRY(S.get(&ids, n));
-    CS_TRY(S.get(&keys_alt, n));
-    CS_TRY(S.get(&ids_alt, n));
-    CS_TRY(S.get(&counts, n));
-    CS_TRY(S.get(&hullpk, n));
-    CS_TRY(S.get(&counts_sorted, n));
-    CS_TRY(S.get(&offsets, n));
-    CS_TRY(S.get(&rects, n));
-    CS_TRY(S.get(&total, 4));
-    CS_TRY(S.get(&ranges, ntiles));
-    CS_TRY(S.get(&pixstate, (size_t)cam->width * cam->height));
-    CS_TRY(S.get(&evalcount, 1));
-
-    StageTimer tm(ctx, st, prm);
-    launch_fill_u32(st, reinterpret_cast<uint32_t *>(evalcount), 4, 0u);
-    tm.begin();
-    launch_preprocess_fwd(st, n, K, sc->sh_degree, sc->points, sc->delta, sc->sigma, sc->opacity, sc->sh, ca, ra,
-                          records, keys, ids, rects, counts, hullpk, nullptr);
-    tm.end(CS_STAGE_PREPROCESS);
-
-    // depth order of the convexes (stable, ties by index)
-    uint32_t M = 0;
-    if (n > 0) {
-        const size_t hw = radix_hist_words(nb_depth);
-        CS_TRY(S.get(&hist, hw));
-        CS_TRY(S.get(&scan_tmp, scan_temp_words((uint32_t)std::max<size_t>(hw, un)) + 16));
-        tm.begin();
-        radix_sort(st, &keys, &ids, &keys_alt, &ids_alt, un, nullptr, nb_depth, 32, hist, scan_tmp);
-        tm.end(CS_STAGE_DEPTH_SORT);
-        tm.begin();
-        launch_gather_counts(st, un, ids, counts, counts_sorted);
-        scan_exclusive(st, counts_sorted, offsets, un, total, scan_tmp);
-        tm.end(CS_STAGE_BIN_SCAN);
-        CS_HIP(hipMemcpyAsync(ctx->h_word, total, 4, hipMemcpyDeviceToHost, st));
-        CS_HIP(hipStreamSynchronize(st));
-        M = *ctx->h_word;
+    ViewPlan vp;
+    CS_TRY(plan_views(1, cam, kn.tile, &out_rgb, nullptr, vp));
+    Frame *F = new Frame;
+    int r = F->init(sc->n, sc->k, sc->sh_degree, 1, vp.hdr.total_tiles, (size_t)vp.hdr.total_pix, st, &ctx->ring);
+    if (!r) r = F->upload_views(vp.hdr, vp.views.data());
+    StageTimer tm(ctx, st, prm && (prm->flags & CS_FLAG_TIMING));
+    if (!r) r = enqueue_forward(ctx, *F, sc, ra, kn, false, 1.0, tm);
+    if (r) {
+        delete F;
+        return r;
     }
-
-    uint32_t *pt, *pi, *pt_alt, *pi_alt;
-    CS_TRY(S.get(&pt, M));
-    CS_TRY(S.get(&pi, M));
-    CS_TRY(S.get(&pt_alt, M));
-    CS_TRY(S.get(&pi_alt, M));
-    launch_fill_u32(st, reinterpret_cast<uint32_t *>(ranges), 2 * (size_t)ntiles, 0u);
-    if (M > 0) {
-        tm.begin();
-        launch_emit_pairs(st, un, ids, offsets, rects, ra.tiles_x, M, pt, pi);
-        tm.end(CS_STAGE_EMIT);
-        const int nb_pairs = radix_blocks(M);
-        uint32_t *hist2, *scan2;
-        const size_t hw2 = radix_hist_words(nb_pairs);
-        CS_TRY(S.get(&hist2, hw2));
-        CS_TRY(S.get(&scan2, scan_temp_words((uint32_t)hw2) + 16));
-        tm.begin();
-        radix_sort(st, &pt, &pi, &pt_alt, &pi_alt, M, nullptr, nb_pairs, std::max(1, ilog2_ceil((uint32_t)ntiles)),
-                   hist2, scan2);
-        tm.end(CS_STAGE_TILE_SORT);
-        tm.begin();
-        launch_tile_ranges(st, pt, M, nullptr, M, ranges);
-        tm.end(CS_STAGE_RANGES);
-    }
-    tm.begin();
-    launch_render_fwd(st, K, ntiles, ranges, pi, records, ra, cam->width, cam->height, out_rgb, pixstate, evalcount);
-    tm.end(CS_STAGE_RENDER_FWD);
-    CS_HIP(hipGetLastError());
-
     if (state_out) {
         cs_fwd_state *s = new cs_fwd_state;
-        s->n = n; s->K = K; s->deg = sc->sh_degree; s->W = cam->width; s->H = cam->height;
-        s->tiles_x = ra.tiles_x; s->tiles_y = ra.tiles_y;
-        s->npairs = M;
-        s->stream = st;
-        s->records = records; s->hullpk = hullpk; s->pair_ids = pi; s->ranges = ranges; s->pixstate = pixstate;
-        s->evalcount = evalcount;
-        for (const void *p : {(const void *)records, (const void *)hullpk, (const void *)pi, (const void *)ranges,
-                              (const void *)pixstate, (const void *)evalcount})
-            S.keep(p);
+        s->frame = F;
+        s->owned = true;
+        s->nviews = 1;
         *state_out = s;
+    } else {
+        delete F;
     }
     return CS_OK;
 }
@@ -383,43 +653,273 @@ int cs_render_backward(cs_ctx *ctx, const cs_scene *sc, const cs_camera *cam, co
     if (!state) return fail(CS_EINVAL, "state is NULL");
     CS_TRY(check_scene(sc));
     CS_TRY(check_camera(cam));
-    if (!dl_drgb || !g) return fail(CS_EINVAL, "dl_drgb or grads is NULL");
-    if (sc->n > 0 && (!g->points || !g->delta || !g->sigma || !g->opacity || !g->sh))
-        return fail(CS_EINVAL, "gradient array pointer is NULL");
-    if (sc->n != state->n || sc->k != state->K || sc->sh_degree != state->deg || cam->width != state->W ||
-        cam->height != state->H)
-        return fail(CS_EINVAL, "scene or camera differs from the forward call");
-    CamArgs ca;
+    if (!dl_drgb) return fail(CS_EINVAL, "dl_drgb is NULL");
+    CS_TRY(check_grads(sc, g));
+    return cs_render_backward_batch(ctx, sc, 1, cam, prm, state, &dl_drgb, g, hip_stream);
+}
+
+int cs_render_forward_batch(cs_ctx *ctx, const cs_scene *sc, int32_t n_views, const cs_camera *cams,
+                            const cs_params *prm, float *const *out_rgb, cs_fwd_state **state_out, void *hip_stream)
+{
+    if (state_out) *state_out = nullptr;
+    if (!ctx) return fail(CS_EINVAL, "ctx is NULL");
+    CS_TRY(check_scene(sc));
+    if (n_views < 1 || n_views > MAX_VIEWS) return fail(CS_EINVAL, "n_views = %d outside [1, %d]", n_views, MAX_VIEWS);
+    if (!cams) return fail(CS_EINVAL, "cameras are NULL");
+    for (int v = 0; v < n_views; ++v) CS_TRY(check_camera(&cams[v]));
+    if (!out_rgb) return fail(CS_EINVAL, "out_rgb is NULL");
+    for (int v = 0; v < n_views && v < MAX_VIEWS; ++v)
+        if (!out_rgb[v]) return fail(CS_EINVAL, "out_rgb[%d] is NULL", v);
     RenderArgs ra;
-    CS_TRY(make_args(cam, prm, ca, ra));
+    Knobs kn;
+    CS_TRY(render_args(prm, ra, kn));
+    const int flags = prm ? prm->flags : 0;
     CS_HIP(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)hip_stream;
-    const int n = sc->n, K = sc->k;
-    Scratch S(st);
-    float *acc;
-    CS_TRY(S.get(&acc, (size_t)n * acc_stride(K)));
-    launch_fill_u32(st, reinterpret_cast<uint32_t *>(acc), (size_t)n * acc_stride(K), 0u);
-    StageTimer tm(ctx, st, prm);
+    if ((flags & CS_FLAG_AUTOTUNE) && (!prm || prm->tile == 0)) {
+        cs_tuning t;
+        CS_TRY(cs_autotune(ctx, sc, n_views, cams, prm, &t, hip_stream));
+        kn.tile = t.tile;
+        kn.longest = t.longest_first;
+        kn.digits = t.digit_bits;
+        ra.tile = kn.tile;
+    }
+    ViewPlan vp;
+    CS_TRY(plan_views(n_views, cams, kn.tile, out_rgb, nullptr, vp));
+    StageTimer tm(ctx, st, (flags & CS_FLAG_TIMING) != 0);
+
+    if (!(flags & CS_FLAG_GRAPH)) { // eager: exact buffers owned by the state
+        Frame *F = new Frame;
+        int r = F->init(sc->n, sc->k, sc->sh_degree, n_views, vp.hdr.total_tiles, (size_t)vp.hdr.total_pix, st, &ctx->ring);
+        if (!r) r = F->upload_views(vp.hdr, vp.views.data());
+        if (!r) r = enqueue_forward(ctx, *F, sc, ra, kn, false, 1.0, tm);
+        if (r) { delete F; return r; }
+        if (state_out) {
+            cs_fwd_state *s = new cs_fwd_state;
+            s->frame = F;
+            s->nviews = n_views;
+            *state_out = s;
+        } else {
+            delete F;
+        }
+        return CS_OK;
+    }
+
+    // graph mode: the context's frame, captured once and replayed
+    const uint64_t key = scene_key(sc, n_views, kn, ra);
+    Frame *F = ctx->batch;
+    const bool fits = F && ctx->batch_key == key && F->st == st && vp.hdr.total_tiles <= F->cap_tiles &&
+                      (size_t)vp.hdr.total_pix <= F->cap_pix;
+    if (!fits) {
+        if (F) {
+            (void)hipStreamSynchronize(F->st);
+            delete F;
+        }
+        ctx->batch = nullptr;
+        F = new Frame;
+        int r = F->init(sc->n, sc->k, sc->sh_degree, n_views, vp.hdr.total_tiles, (size_t)vp.hdr.total_pix, st, &ctx->ring);
+        if (!r) r = F->upload_views(vp.hdr, vp.views.data());
+        if (!r) r = F->init_async_readback();
+        // first frame: eager, pair buffers sized from its count plus 30 %
+        if (!r) r = enqueue_forward(ctx, *F, sc, ra, kn, false, 1.3, tm);
+        if (r) { delete F; return r; }
+        ctx->batch = F;
+        ctx->batch_key = key;
+    } else {
+        CS_TRY(F->upload_views(vp.hdr, vp.views.data()));
+        if (!F->gfwd) {
+            StageTimer off(ctx, st, false);
+            CS_TRY(capture_graph(ctx, *F, &F->gfwd, [&] { return enqueue_forward(ctx, *F, sc, ra, kn, true, 1.0, off); }));
+        }
+        tm.begin();
+        CS_HIP(hipGraphLaunch(F->gfwd, st));
+        tm.end(CS_STAGE_GRAPH_FWD);
+    }
+    F->epoch++;
+    CS_HIP(hipMemcpyAsync(F->h_counters, F->counters, CNT_WORDS * 4, hipMemcpyDeviceToHost, st));
+    CS_HIP(hipEventRecord(F->counters_ev, st));
+    if (state_out) {
+        cs_fwd_state *s = new cs_fwd_state;
+        s->frame = F;
+        s->owned = false;
+        s->nviews = n_views;
+        s->epoch = F->epoch;
+        *state_out = s;
+    }
+    return CS_OK;
+}
+
+int cs_batch_check(cs_ctx *ctx, const cs_fwd_state *s)
+{
+    if (!ctx || !s || !s->frame) return fail(CS_EINVAL, "ctx or state is NULL");
+    Frame *F = s->frame;
+    if (!s->owned && (ctx->batch != F || F->epoch != s->epoch))
+        return fail(CS_EINVAL, "batch state was replaced by a later batched forward");
+    CS_HIP(hipSetDevice(ctx->device));
+    if (s->owned) {
+        CS_HIP(hipStreamSynchronize(F->st));
+        return CS_OK;
+    }
+    CS_HIP(hipEventSynchronize(F->counters_ev));
+    if (F->h_counters[CNT_OVERFLOW]) {
+        const size_t m = F->h_counters[CNT_PAIRS];
+        CS_HIP(hipStreamSynchronize(F->st));
+        if (F->gfwd) { (void)hipGraphExecDestroy(F->gfwd); F->gfwd = nullptr; }
+        if (F->gbwd) { (void)hipGraphExecDestroy(F->gbwd); F->gbwd = nullptr; }
+        int r = F->ensure_pairs((size_t)std::ceil(m * 1.3));
+        if (r) return r;
+        return fail(CS_EOVERFLOW, "frame needed %zu (convex, tile) pairs; buffers grown, render it again", m);
+    }
+    return CS_OK;
+}
+
+int cs_render_backward_batch(cs_ctx *ctx, const cs_scene *sc, int32_t n_views, const cs_camera *cams,
+                             const cs_params *prm, const cs_fwd_state *state, const float *const *dl_drgb,
+                             cs_grads *g, void *hip_stream)
+{
+    if (!ctx) return fail(CS_EINVAL, "ctx is NULL");
+    if (!state || !state->frame) return fail(CS_EINVAL, "state is NULL");
+    CS_TRY(check_scene(sc));
+    CS_TRY(check_grads(sc, g));
+    if (!dl_drgb) return fail(CS_EINVAL, "dl_drgb is NULL");
+    Frame *F = state->frame;
+    if (n_views != state->nviews || sc->n != F->n || sc->k != F->K || sc->sh_degree != F->deg)
+        return fail(CS_EINVAL, "scene or views differ from the forward call");
+    for (int v = 0; v < n_views; ++v)
+        if (!dl_drgb[v]) return fail(CS_EINVAL, "dl_drgb[%d] is NULL", v);
+    RenderArgs ra;
+    Knobs kn;
+    CS_TRY(render_args(prm, ra, kn));
+    ra.tile = F->tile;
+    CS_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (!state->owned) CS_TRY(cs_batch_check(ctx, state));
+    ViewPlan vp;
+    CS_TRY(plan_views(n_views, cams, F->tile, nullptr, dl_drgb, vp));
+    if (vp.hdr.total_tiles > F->cap_tiles || (size_t)vp.hdr.total_pix > F->cap_pix)
+        return fail(CS_EINVAL, "cameras differ from the forward call");
+    F->st = st;
+    CS_TRY(F->upload_views(vp.hdr, vp.views.data()));
+    const bool timing = prm && (prm->flags & CS_FLAG_TIMING);
+    if (state->owned || !(prm && (prm->flags & CS_FLAG_GRAPH))) {
+        StageTimer tm(ctx, st, timing);
+        return enqueue_backward(*F, sc, g, ra, tm);
+    }
+    uint64_t key = 1469598103934665603ull;
+    for (uint64_t v : {(uint64_t)(uintptr_t)g->points, (uint64_t)(uintptr_t)g->delta, (uint64_t)(uintptr_t)g->sigma,
+                       (uint64_t)(uintptr_t)g->opacity, (uint64_t)(uintptr_t)g->sh})
+        key = mix(key, v);
+    if (!F->gbwd || F->kbwd != key) {
+        if (F->gbwd) { (void)hipGraphExecDestroy(F->gbwd); F->gbwd = nullptr; }
+        CS_TRY(F->ensure_acc());
+        StageTimer off(ctx, st, false);
+        CS_TRY(capture_graph(ctx, *F, &F->gbwd, [&] { return enqueue_backward(*F, sc, g, ra, off); }));
+        F->kbwd = key;
+    }
+    StageTimer tm(ctx, st, timing);
     tm.begin();
-    launch_render_bwd(st, K, ra.tiles_x * ra.tiles_y, state->ranges, state->pair_ids, state->records, ra, cam->width,
-                      cam->height, dl_drgb, state->pixstate, acc);
-    tm.end(CS_STAGE_RENDER_BWD);
-    tm.begin();
-    launch_preprocess_bwd(st, n, K, sc->sh_degree, sc->points, sc->delta, sc->sigma, sc->sh, ca, state->hullpk, acc,
-                          g->points, g->delta, g->sigma, g->opacity, g->sh);
-    tm.end(CS_STAGE_PREPROCESS_BWD);
-    CS_HIP(hipGetLastError());
+    CS_HIP(hipGraphLaunch(F->gbwd, st));
+    tm.end(CS_STAGE_GRAPH_BWD);
+    return CS_OK;
+}
+
+int cs_autotune(cs_ctx *ctx, const cs_scene *sc, int32_t n_views, const cs_camera *cams, const cs_params *prm,
+                cs_tuning *out, void *hip_stream)
+{
+    if (!ctx || !out) return fail(CS_EINVAL, "ctx or out is NULL");
+    CS_TRY(check_scene(sc));
+    RenderArgs ra;
+    Knobs kn;
+    cs_params base = prm ? *prm : cs_params{1e-6f, 1e-5f, {0.f, 0.f, 0.f}, 16, 0};
+    base.tile = 16;
+    base.flags &= ~(CS_FLAG_AUTOTUNE | CS_FLAG_GRAPH | CS_FLAG_TIMING);
+    CS_TRY(render_args(&base, ra, kn));
+    CS_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    ViewPlan vp0;
+    CS_TRY(plan_views(n_views, cams, 16, nullptr, nullptr, vp0));
+    const auto tkey = std::make_tuple(sc->k, sc->sh_degree, (int)n_views, ilog2_ceil(std::max(1, sc->n)),
+                                      ilog2_ceil((uint64_t)std::max<int64_t>(1, vp0.hdr.total_pix)));
+    auto it = ctx->tune.find(tkey);
+    if (it != ctx->tune.end()) {
+        *out = it->second;
+        return CS_OK;
+    }
+    // scratch images, upstream gradient and parameter gradients
+    const size_t npix = (size_t)vp0.hdr.total_pix;
+    const int nc = (sc->sh_degree + 1) * (sc->sh_degree + 1);
+    float *img = nullptr, *gbuf = nullptr;
+    CS_HIP(hipMallocAsync((void **)&img, npix * 3 * 4 * 2, st));
+    CS_HIP(hipMallocAsync((void **)&gbuf, (size_t)std::max(1, sc->n) * (3 * sc->k + 3 + 3 * nc) * 4, st));
+    launch_fill_u32(st, reinterpret_cast<uint32_t *>(img), npix * 6, 0x358637bdu); // 1e-6f everywhere
+    std::vector<float *> outs(n_views), dls(n_views);
+    {
+        size_t off = 0;
+        for (int v = 0; v < n_views; ++v) {
+            outs[v] = img + off;
+            dls[v] = img + npix * 3 + off;
+            off += (size_t)cams[v].width * cams[v].height * 3;
+        }
+    }
+    cs_grads gr{gbuf, gbuf + (size_t)sc->n * 3 * sc->k, gbuf + (size_t)sc->n * (3 * sc->k + 1),
+                gbuf + (size_t)sc->n * (3 * sc->k + 2), gbuf + (size_t)sc->n * (3 * sc->k + 3)};
+    hipEvent_t e0, e1;
+    CS_HIP(hipEventCreate(&e0));
+    CS_HIP(hipEventCreate(&e1));
+    cs_tuning best{16, 0, 8, 1e30f, 0.0f};
+    int status = CS_OK;
+    for (int tile : {8, 16, 32})
+        for (int longest : {0, 1})
+            for (int digits : {6, 8}) {
+                cs_params p = base;
+                p.tile = tile;
+                p.flags = (base.flags & ~0xF0E) | (longest ? CS_FLAG_LONGEST_FIRST : 0) | CS_FLAG_DIGITS(digits);
+                float ms = 0.0f;
+                for (int rep = 0; rep < 3 && status == CS_OK; ++rep) {
+                    cs_fwd_state *s = nullptr;
+                    (void)hipEventRecord(e0, st);
+                    status = cs_render_forward_batch(ctx, sc, n_views, cams, &p, outs.data(), &s, hip_stream);
+                    if (status == CS_OK)
+                        status = cs_render_backward_batch(ctx, sc, n_views, cams, &p, s, dls.data(), &gr, hip_stream);
+                    (void)hipEventRecord(e1, st);
+                    (void)hipEventSynchronize(e1);
+                    cs_state_release(ctx, s);
+                    if (rep > 0) {
+                        float t = 0.0f;
+                        (void)hipEventElapsedTime(&t, e0, e1);
+                        ms += t / 2.0f;
+                    }
+                }
+                if (status != CS_OK) break;
+                if (tile == 16 && !longest && digits == 8) best.ms_default = ms;
+                if (ms < best.ms) {
+                    best.tile = tile;
+                    best.longest_first = longest;
+                    best.digit_bits = digits;
+                    best.ms = ms;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFreeAsync(img, st);
+    (void)hipFreeAsync(gbuf, st);
+    if (status != CS_OK) return status;
+    ctx->tune[tkey] = best;
+    *out = best;
     return CS_OK;
 }
 
 int cs_state_stats(cs_ctx *ctx, const cs_fwd_state *s, int64_t *n_pairs, int64_t *n_evaluated, int64_t *n_full)
 {
-    if (!ctx || !s) return fail(CS_EINVAL, "ctx or state is NULL");
+    if (!ctx || !s || !s->frame) return fail(CS_EINVAL, "ctx or state is NULL");
     CS_HIP(hipSetDevice(ctx->device));
+    Frame *F = s->frame;
     unsigned long long ev[2] = {0, 0};
-    CS_HIP(hipMemcpyAsync(ev, s->evalcount, sizeof(ev), hipMemcpyDeviceToHost, s->stream));
-    CS_HIP(hipStreamSynchronize(s->stream));
-    if (n_pairs) *n_pairs = s->npairs;
+    uint32_t cnt[CNT_WORDS];
+    CS_HIP(hipMemcpyAsync(ev, F->evalcount, sizeof(ev), hipMemcpyDeviceToHost, F->st));
+    CS_HIP(hipMemcpyAsync(cnt, F->counters, sizeof(cnt), hipMemcpyDeviceToHost, F->st));
+    CS_HIP(hipStreamSynchronize(F->st));
+    if (n_pairs) *n_pairs = cnt[CNT_PAIRS];
     if (n_evaluated) *n_evaluated = (int64_t)ev[0];
     if (n_full) *n_full = (int64_t)ev[1];
     return CS_OK;
@@ -454,29 +954,23 @@ int cs_debug_preprocess(cs_ctx *ctx, const cs_scene *sc, const cs_camera *cam, c
     if (!ctx || !out) return fail(CS_EINVAL, "ctx or out is NULL");
     CS_TRY(check_scene(sc));
     CS_TRY(check_camera(cam));
-    CamArgs ca;
     RenderArgs ra;
-    CS_TRY(make_args(cam, prm, ca, ra));
+    Knobs kn;
+    CS_TRY(render_args(prm, ra, kn));
     CS_HIP(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)hip_stream;
-    const int n = sc->n, K = sc->k;
-    if (n == 0) return CS_OK;
-    Scratch S(st);
-    uint8_t *records;
-    uint32_t *keys, *ids, *counts, *hullpk;
-    uint2 *rects;
-    DebugConvex *dbg;
-    CS_TRY(S.get(&records, (size_t)n * rec_stride(K)));
-    CS_TRY(S.get(&keys, n));
-    CS_TRY(S.get(&ids, n));
-    CS_TRY(S.get(&counts, n));
-    CS_TRY(S.get(&hullpk, n));
-    CS_TRY(S.get(&rects, n));
-    CS_TRY(S.get(&dbg, n));
-    launch_preprocess_fwd(st, n, K, sc->sh_degree, sc->points, sc->delta, sc->sigma, sc->opacity, sc->sh, ca, ra,
-                          records, keys, ids, rects, counts, hullpk, dbg);
+    if (sc->n == 0) return CS_OK;
+    ViewPlan vp;
+    CS_TRY(plan_views(1, cam, kn.tile, nullptr, nullptr, vp));
+    Frame F;
+    CS_TRY(F.init(sc->n, sc->k, sc->sh_degree, 1, vp.hdr.total_tiles, 1, st, &ctx->ring));
+    CS_TRY(F.upload_views(vp.hdr, vp.views.data()));
+    DebugConvex *dbg = nullptr;
+    CS_TRY(F.alloc((void **)&dbg, sizeof(DebugConvex) * (size_t)sc->n));
+    launch_preprocess_fwd(st, sc->n, 1, sc->k, sc->sh_degree, sc->points, sc->delta, sc->sigma, sc->opacity, sc->sh,
+                          F.d_frame, ra, F.records, F.keys, F.ids, F.rects, F.counts, F.hullpk, dbg);
     CS_HIP(hipGetLastError());
-    CS_HIP(hipMemcpyAsync(out, dbg, sizeof(DebugConvex) * (size_t)n, hipMemcpyDeviceToHost, st));
+    CS_HIP(hipMemcpyAsync(out, dbg, sizeof(DebugConvex) * (size_t)sc->n, hipMemcpyDeviceToHost, st));
     CS_HIP(hipStreamSynchronize(st));
     return CS_OK;
 }
@@ -484,16 +978,23 @@ int cs_debug_preprocess(cs_ctx *ctx, const cs_scene *sc, const cs_camera *cam, c
 int cs_debug_tile_lists(cs_ctx *ctx, const cs_fwd_state *s, int32_t *ranges, int64_t ranges_len, int32_t *ids,
                         int64_t ids_len)
 {
-    if (!ctx || !s || !ranges || (!ids && s->npairs)) return fail(CS_EINVAL, "NULL argument");
-    const int64_t nt = (int64_t)s->tiles_x * s->tiles_y;
-    if (ranges_len < 2 * nt || ids_len < (int64_t)s->npairs)
-        return fail(CS_EOVERFLOW, "host buffers too small (%lld ranges, %lld ids needed)", (long long)(2 * nt),
-                    (long long)s->npairs);
+    if (!ctx || !s || !s->frame || !ranges) return fail(CS_EINVAL, "NULL argument");
+    Frame *F = s->frame;
     CS_HIP(hipSetDevice(ctx->device));
-    CS_HIP(hipMemcpyAsync(ranges, s->ranges, sizeof(uint2) * nt, hipMemcpyDeviceToHost, s->stream));
-    if (s->npairs)
-        CS_HIP(hipMemcpyAsync(ids, s->pair_ids, sizeof(uint32_t) * s->npairs, hipMemcpyDeviceToHost, s->stream));
-    CS_HIP(hipStreamSynchronize(s->stream));
+    uint32_t cnt[CNT_WORDS];
+    CS_HIP(hipMemcpyAsync(cnt, F->counters, sizeof(cnt), hipMemcpyDeviceToHost, F->st));
+    CS_HIP(hipStreamSynchronize(F->st));
+    const int64_t npairs = cnt[CNT_PAIRS_EFF];
+    FrameHeader hdr;
+    CS_HIP(hipMemcpy(&hdr, F->d_frame, sizeof(hdr), hipMemcpyDeviceToHost));
+    const int64_t nt = hdr.total_tiles;
+    if (ranges_len < 2 * nt || ids_len < npairs || (!ids && npairs))
+        return fail(CS_EOVERFLOW, "host buffers too small (%lld ranges, %lld ids needed)", (long long)(2 * nt),
+                    (long long)npairs);
+    CS_HIP(hipMemcpyAsync(ranges, F->ranges, sizeof(uint2) * nt, hipMemcpyDeviceToHost, F->st));
+    if (npairs)
+        CS_HIP(hipMemcpyAsync(ids, F->sorted_ids, sizeof(uint32_t) * npairs, hipMemcpyDeviceToHost, F->st));
+    CS_HIP(hipStreamSynchronize(F->st));
     return CS_OK;
 }
 

@@ -1,0 +1,75 @@
+// Runtime-side structures of the convex rasterizer (host code only).
+#pragma once
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace cs {
+
+int fail(int code, const char *fmt, ...);
+
+// Pinned staging buffers for view-table uploads, shared by the frames of one
+// context; a slot is reused only after its previous copy has completed.
+struct HostRing {
+    struct Slot {
+        void *host = nullptr;
+        hipEvent_t ev = nullptr;
+        bool used = false;
+    } slot[8];
+    int next = 0;
+    uint32_t *h_word = nullptr; // pinned words for synchronous read-backs
+    int init();
+    ~HostRing();
+};
+
+// Device buffers of one forward pass over V views of an N-convex scene, plus
+// what its backward pass needs.  Instance i of view v is v * N + i.
+struct Frame {
+    int n = 0, K = 0, deg = 0, V = 0;
+    int tile = 16, longest = 0, digits = 8;
+    size_t cap_inst = 0, cap_pairs = 0, cap_tiles = 0, cap_pix = 0;
+    int nb_inst = 1, nb_pairs = 1, nb_tiles = 1;
+    uint32_t npairs = 0;
+    hipStream_t st = nullptr;
+    std::vector<void *> allocs;
+    size_t bytes_held = 0;
+
+    FrameHeader *d_frame = nullptr; // header + ViewDesc[MAX_VIEWS]
+    uint8_t *records = nullptr;
+    uint32_t *keys = nullptr, *ids = nullptr, *keys_alt = nullptr, *ids_alt = nullptr;
+    uint32_t *counts = nullptr, *counts_sorted = nullptr, *offsets = nullptr, *hullpk = nullptr;
+    uint2 *rects = nullptr;
+    uint32_t *hist = nullptr, *scan_tmp = nullptr;
+    uint32_t *pt = nullptr, *pi = nullptr, *pt_alt = nullptr, *pi_alt = nullptr;
+    uint2 *ranges = nullptr;
+    uint32_t *ord_k = nullptr, *ord_v = nullptr, *ord_k_alt = nullptr, *ord_v_alt = nullptr;
+    uint2 *pixstate = nullptr;
+    float *acc = nullptr;
+    uint32_t *counters = nullptr;
+    unsigned long long *evalcount = nullptr;
+    uint32_t *h_counters = nullptr; // pinned read-back of the counters
+    hipEvent_t counters_ev = nullptr;
+
+    // results of the last forward pass (point into the buffers above)
+    uint32_t *sorted_ids = nullptr;
+    uint32_t *order = nullptr;
+
+    // captured graphs (batched path)
+    hipGraphExec_t gfwd = nullptr, gbwd = nullptr;
+    uint64_t kbwd = 0;
+    uint64_t epoch = 0;
+
+    HostRing *ring = nullptr;
+
+    int init(int n, int K, int deg, int V, size_t tiles, size_t pix, hipStream_t st, HostRing *ring);
+    int init_async_readback();
+    int alloc(void **p, size_t bytes);
+    void release_buffer(void *p);
+    int ensure_pairs(size_t m);
+    int ensure_acc();
+    int upload_views(const FrameHeader &hdr, const ViewDesc *views);
+    ~Frame();
+};
+
+} // namespace cs

@@ -147,8 +147,8 @@ void scan_exclusive(hipStream_t st, const uint32_t *in, uint32_t *out, uint32_t 
 
 // ----------------------------------------------------------- radix sort ----
 
-constexpr int RS_BITS = 8;
-constexpr int RS_RADIX = 1 << RS_BITS;
+constexpr int RS_MAX_BITS = 8;
+constexpr int RS_MAX_RADIX = 1 << RS_MAX_BITS;
 constexpr int RS_BLOCK = 256;
 constexpr int RS_WAVES = RS_BLOCK / 64;
 constexpr int RS_ITEMS = 16;
@@ -163,10 +163,12 @@ __device__ __forceinline__ void rs_block_tiles(uint32_t n, int nblocks, uint32_t
     t1 = min(ntiles, t0 + per);
 }
 
+template <int RS_BITS>
 __global__ __launch_bounds__(RS_BLOCK) void radix_hist_kernel(const uint32_t *__restrict__ keys,
                                                                const uint32_t *__restrict__ n_dev, uint32_t n_host,
                                                                int shift, int nblocks, uint32_t *__restrict__ hist)
 {
+    constexpr int RS_RADIX = 1 << RS_BITS;
     __shared__ uint32_t h[RS_WAVES][RS_RADIX];
     const uint32_t n = n_dev ? *n_dev : n_host;
     const int wave = threadIdx.x >> 6;
@@ -190,15 +192,17 @@ __global__ __launch_bounds__(RS_BLOCK) void radix_hist_kernel(const uint32_t *__
     }
 }
 
-// Stable scatter of one 8-bit digit.  Within a tile the element order is
+// Stable scatter of one digit of RS_BITS (<= 8) bits.  Within a tile the element order is
 // (wave, item, lane); each wave ranks its elements with ballots over the digit
 // bits, the block places the tile digit-sorted in LDS and writes each digit's
 // run contiguously to its global position.
+template <int RS_BITS>
 __global__ __launch_bounds__(RS_BLOCK) void radix_scatter_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
     uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ n_dev, uint32_t n_host, int shift, int nblocks,
     const uint32_t *__restrict__ hist_scanned)
 {
+    constexpr int RS_RADIX = 1 << RS_BITS;
     __shared__ uint32_t s_keys[RS_TILE];
     __shared__ uint32_t s_vals[RS_TILE];
     __shared__ uint32_t s_wcnt[RS_WAVES][RS_RADIX];
@@ -299,19 +303,39 @@ int radix_blocks(uint32_t n_capacity)
     return (int)std::max<uint32_t>(1u, std::min<uint32_t>(tiles, 1024u));
 }
 
-size_t radix_hist_words(int nblocks) { return (size_t)nblocks * RS_RADIX; }
+size_t radix_hist_words(int nblocks) { return (size_t)nblocks * RS_MAX_RADIX; }
 
-// Sorts bits [0, end_bit) of the keys.  On return *keys/*vals point at the
-// sorted arrays (one of the two buffer pairs).  n_dev may be NULL (n_host used).
-void radix_sort(hipStream_t st, uint32_t **keys, uint32_t **vals, uint32_t **keys_alt, uint32_t **vals_alt,
-                uint32_t n_host, const uint32_t *n_dev, int nblocks, int end_bit, uint32_t *hist, uint32_t *scan_tmp)
+template <int B>
+static void radix_pass(hipStream_t st, const uint32_t *keys, const uint32_t *vals, uint32_t *keys_out,
+                       uint32_t *vals_out, uint32_t n_host, const uint32_t *n_dev, int nblocks, int shift,
+                       uint32_t *hist, uint32_t *scan_tmp)
 {
-    for (int shift = 0; shift < end_bit; shift += RS_BITS) {
-        hipLaunchKernelGGL(radix_hist_kernel, dim3(nblocks), dim3(RS_BLOCK), 0, st, *keys, n_dev, n_host, shift,
-                           nblocks, hist);
-        scan_exclusive(st, hist, hist, (uint32_t)(nblocks * RS_RADIX), nullptr, scan_tmp);
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblocks), dim3(RS_BLOCK), 0, st, *keys, *vals, *keys_alt,
-                           *vals_alt, n_dev, n_host, shift, nblocks, hist);
+    hipLaunchKernelGGL(radix_hist_kernel<B>, dim3(nblocks), dim3(RS_BLOCK), 0, st, keys, n_dev, n_host, shift,
+                       nblocks, hist);
+    scan_exclusive(st, hist, hist, (uint32_t)(nblocks * (1 << B)), nullptr, scan_tmp);
+    hipLaunchKernelGGL(radix_scatter_kernel<B>, dim3(nblocks), dim3(RS_BLOCK), 0, st, keys, vals, keys_out,
+                       vals_out, n_dev, n_host, shift, nblocks, hist);
+}
+
+// Sorts bits [0, end_bit) of the keys in passes of `digit_bits` (4..8; the
+// last pass takes what remains).  On return *keys/*vals point at the sorted
+// arrays (one of the two buffer pairs).  n_dev may be NULL (n_host used); with
+// n_dev the element count is read on the device (graph capture needs no
+// host read-back) and nblocks must cover the capacity.
+void radix_sort(hipStream_t st, uint32_t **keys, uint32_t **vals, uint32_t **keys_alt, uint32_t **vals_alt,
+                uint32_t n_host, const uint32_t *n_dev, int nblocks, int end_bit, uint32_t *hist, uint32_t *scan_tmp,
+                int digit_bits)
+{
+    digit_bits = std::min(8, std::max(4, digit_bits));
+    for (int shift = 0; shift < end_bit; shift += digit_bits) {
+        const int b = std::min(digit_bits, end_bit - shift);
+        switch (b) {
+        case 1: case 2: case 3: case 4: radix_pass<4>(st, *keys, *vals, *keys_alt, *vals_alt, n_host, n_dev, nblocks, shift, hist, scan_tmp); break;
+        case 5: radix_pass<5>(st, *keys, *vals, *keys_alt, *vals_alt, n_host, n_dev, nblocks, shift, hist, scan_tmp); break;
+        case 6: radix_pass<6>(st, *keys, *vals, *keys_alt, *vals_alt, n_host, n_dev, nblocks, shift, hist, scan_tmp); break;
+        case 7: radix_pass<7>(st, *keys, *vals, *keys_alt, *vals_alt, n_host, n_dev, nblocks, shift, hist, scan_tmp); break;
+        default: radix_pass<8>(st, *keys, *vals, *keys_alt, *vals_alt, n_host, n_dev, nblocks, shift, hist, scan_tmp); break;
+        }
         std::swap(*keys, *keys_alt);
         std::swap(*vals, *vals_alt);
     }
@@ -326,10 +350,13 @@ __global__ void gather_counts_kernel(uint32_t n, const uint32_t *__restrict__ so
     if (r < n) out[r] = counts[sorted_ids[r]];
 }
 
-// One thread per convex in depth order: write its (tile, convex) pairs, row-major over its tile rectangle.
-__global__ void emit_pairs_kernel(uint32_t n, const uint32_t *__restrict__ sorted_ids,
-                                  const uint32_t *__restrict__ offsets, const uint2 *__restrict__ rects, int tiles_x,
-                                  uint32_t capacity, uint32_t *__restrict__ pair_tiles, uint32_t *__restrict__ pair_ids)
+// One thread per (view, convex) instance in depth order: write its (global
+// tile, instance) pairs, row-major over its tile rectangle.  Instance id =
+// view * n_convex + convex; the view's tiles start at its tile_off.
+__global__ void emit_pairs_kernel(uint32_t n, uint32_t n_convex, const uint32_t *__restrict__ sorted_ids,
+                                  const uint32_t *__restrict__ offsets, const uint2 *__restrict__ rects,
+                                  const FrameHeader *__restrict__ frame, uint32_t capacity,
+                                  uint32_t *__restrict__ pair_tiles, uint32_t *__restrict__ pair_ids)
 {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
@@ -337,13 +364,37 @@ __global__ void emit_pairs_kernel(uint32_t n, const uint32_t *__restrict__ sorte
     const uint2 rc = rects[id];
     const int tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
     if (tx0 > tx1 || ty0 > ty1) return;
+    const ViewDesc &vd = reinterpret_cast<const ViewDesc *>(frame + 1)[id / n_convex];
+    const int tiles_x = vd.tiles_x, toff = vd.tile_off;
     uint32_t off = offsets[r];
     for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx, ++off)
             if (off < capacity) {
-                pair_tiles[off] = (uint32_t)(ty * tiles_x + tx);
+                pair_tiles[off] = (uint32_t)(toff + ty * tiles_x + tx);
                 pair_ids[off] = id;
             }
+}
+
+// Pair count that fits the buffers, and the overflow flag (for fixed-capacity frames).
+__global__ void clamp_pairs_kernel(uint32_t *__restrict__ counters, uint32_t capacity)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const uint32_t m = counters[CNT_PAIRS];
+        counters[CNT_PAIRS_EFF] = m < capacity ? m : capacity;
+        counters[CNT_OVERFLOW] = m > capacity ? 1u : 0u;
+    }
+}
+
+// Sort keys that put long tile lists first: key = 0xFFFF - min(length, 0xFFFF).
+__global__ void tile_length_keys_kernel(uint32_t ntiles, const uint2 *__restrict__ ranges,
+                                        uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const uint2 r = ranges[t];
+    const uint32_t len = r.y - r.x;
+    keys[t] = 0xFFFFu - (len < 0xFFFFu ? len : 0xFFFFu);
+    vals[t] = t;
 }
 
 __global__ void fill_u32_kernel(uint32_t *__restrict__ p, size_t n, uint32_t v)
@@ -377,12 +428,25 @@ void launch_gather_counts(hipStream_t st, uint32_t n, const uint32_t *sorted_ids
     hipLaunchKernelGGL(gather_counts_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, sorted_ids, counts, out);
 }
 
-void launch_emit_pairs(hipStream_t st, uint32_t n, const uint32_t *sorted_ids, const uint32_t *offsets,
-                       const uint2 *rects, int tiles_x, uint32_t capacity, uint32_t *pair_tiles, uint32_t *pair_ids)
+void launch_emit_pairs(hipStream_t st, uint32_t n, uint32_t n_convex, const uint32_t *sorted_ids,
+                       const uint32_t *offsets, const uint2 *rects, const FrameHeader *views, uint32_t capacity,
+                       uint32_t *pair_tiles, uint32_t *pair_ids)
 {
     if (n == 0) return;
-    hipLaunchKernelGGL(emit_pairs_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, sorted_ids, offsets, rects,
-                       tiles_x, capacity, pair_tiles, pair_ids);
+    hipLaunchKernelGGL(emit_pairs_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, n_convex, sorted_ids, offsets,
+                       rects, views, capacity, pair_tiles, pair_ids);
+}
+
+void launch_clamp_pairs(hipStream_t st, uint32_t *counters, uint32_t capacity)
+{
+    hipLaunchKernelGGL(clamp_pairs_kernel, dim3(1), dim3(64), 0, st, counters, capacity);
+}
+
+void launch_tile_length_keys(hipStream_t st, uint32_t ntiles, const uint2 *ranges, uint32_t *keys, uint32_t *vals)
+{
+    if (ntiles == 0) return;
+    hipLaunchKernelGGL(tile_length_keys_kernel, dim3((ntiles + 255) / 256), dim3(256), 0, st, ntiles, ranges, keys,
+                       vals);
 }
 
 void launch_tile_ranges(hipStream_t st, const uint32_t *tiles, uint32_t n_host, const uint32_t *n_dev,

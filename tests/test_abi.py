@@ -54,8 +54,17 @@ def test_null_and_shape_errors_without_a_gpu():
     bad_cam.width, bad_cam.height, bad_cam.fx, bad_cam.fy, bad_cam.znear = 0, 64, 50.0, 50.0, 0.1
     good = binding.SceneS(10, 6, 3, 1, 1, 1, 1, 1)
     assert L.cs_render_forward(dummy, C.byref(good), C.byref(bad_cam), None, 1, None, None) == binding.CS_EINVAL
-    p = binding.make_params(tile=8)
+    p = binding.make_params(tile=12)
     assert L.cs_render_forward(dummy, C.byref(good), C.byref(cam), C.byref(p), 1, None, None) == binding.CS_EINVAL
+    p = binding.make_params(flags=binding.FLAG_DIGITS(3))
+    assert L.cs_render_forward(dummy, C.byref(good), C.byref(cam), C.byref(p), 1, None, None) == binding.CS_EINVAL
+    # batched: view count and output pointers are checked first
+    cams = (binding.Camera * 2)(cam, cam)
+    outs = (C.c_void_p * 2)(1, 1)
+    assert L.cs_render_forward_batch(dummy, C.byref(good), 0, cams, None, outs, None, None) == binding.CS_EINVAL
+    null_outs = (C.c_void_p * 2)(1, 0)
+    assert L.cs_render_forward_batch(dummy, C.byref(good), 2, cams, None, null_outs, None, None) == binding.CS_EINVAL
+    assert L.cs_batch_check(None, None) == binding.CS_EINVAL
     assert L.cs_render_backward(dummy, C.byref(good), C.byref(cam), None, None, 1, 1, None) == binding.CS_EINVAL
 
 
