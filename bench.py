@@ -70,6 +70,122 @@ def stage_work(stage, n, m, K, T_mean, deg, stats, npix):
     return "hbm", 0
 
 
+def bench_batched(steps, warmup):
+    """32 views of the 500k-convex mixture scene, fwd+bwd: batched graph vs plain per-view loop."""
+    import torch
+
+    from paper_2411_14974_amd import scenes
+    from paper_2411_14974_amd.binding import (FLAG_AUTOTUNE, FLAG_GRAPH, FLAG_TIMING, DeviceScene, Renderer,
+                                              make_params)
+    scene, cams, targets = scenes.config4()
+    dev = torch.device("cuda:0")
+    R = Renderer(0)
+    ds = DeviceScene.from_scene(scene, dev)
+    tg = [torch.from_numpy(t).to(dev) for t in targets]
+    outs = [torch.empty_like(t) for t in tg]
+    dls = [torch.empty_like(t) for t in tg]
+    grads = {k: torch.empty_like(getattr(ds, k)) for k in ("points", "delta", "sigma", "opacity", "sh")}
+    mpix = sum(c.width * c.height for c in cams) / 1e6
+    t0 = time.perf_counter()
+    tune = R.autotune(ds, cams)
+    tune_s = time.perf_counter() - t0
+    pb = make_params(flags=FLAG_GRAPH | FLAG_AUTOTUNE)
+
+    def batched():
+        o, st = R.forward_batch(ds, cams, pb, want_state=True, outs=outs)
+        for a, t, d in zip(o, tg, dls):
+            R.l1_loss_grad(a, t, grad=d)
+        R.backward_batch(st, dls, grads=grads)
+        return st
+
+    pp = make_params()
+
+    def plain():
+        for c, a, t, d in zip(cams, outs, tg, dls):
+            o, st = R.forward(ds, c, pp, want_state=True, out=a)
+            R.l1_loss_grad(o, t, grad=d)
+            R.backward(st, d, grads=grads)
+            st.release()
+
+    res = {}
+    for name, fn in (("batched", batched), ("plain", plain)):
+        for _ in range(warmup):
+            r = fn()
+            if r is not None:
+                r.release()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        keep = []
+        for _ in range(steps):
+            r = fn()
+            if r is not None:
+                keep.append(r)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        for r in keep:
+            r.release()
+        res[name] = {"ms_per_step": ms, "mpixels_per_s": mpix / (ms / 1e3)}
+    R.close()
+    return {
+        "workload": "500k convexes K=6 SH3 mixture, 32 views (960x540 / 1297x840 / 1920x1080), fwd+bwd (L1)",
+        "mpixels_per_batch": mpix,
+        "batched_graph": res["batched"],
+        "plain_per_view": res["plain"],
+        "speedup": res["plain"]["ms_per_step"] / res["batched"]["ms_per_step"],
+        "autotune": {**tune, "seconds": tune_s},
+    }
+
+
+def bench_serving(rates, duration):
+    """Poisson request streams against 4 resident scenes (0.2/0.5/1/2 M convexes), forward only:
+    continuous batching (4 worker streams, batches up to 16 views) vs plain FIFO one request at a time."""
+    import torch
+
+    from paper_2411_14974_amd import scenes
+    from paper_2411_14974_amd.binding import DeviceScene, Renderer, make_camera
+    dev = torch.device("cuda:0")
+    ds = [DeviceScene.from_scene(scenes.serve_scene(i), dev) for i in range(4)]
+    R = Renderer(0)
+    pools = {wh: [torch.empty((wh[1], wh[0], 3), device=dev) for _ in range(48)] for wh in scenes.RESOLUTIONS_C5}
+    out = {"workload": "4 resident mixture scenes of 0.2/0.5/1/2 M convexes (K=6, SH3); requests uniform over "
+                       "scenes and 256x256 / 960x540 / 1920x1080, random orbit poses, Poisson arrivals, forward only",
+           "duration_s_per_rate": duration, "modes": {}}
+    for mode, cfg in (("continuous_batching", dict(workers=4, max_batch=16)),
+                      ("plain_fifo", dict(workers=1, max_batch=1))):
+        R.serve_start(hbm_budget_bytes=96 << 30, **cfg)
+        sids = [R.scene_register(d) for d in ds]
+        for i in range(8):  # warm-up
+            R.serve_wait(R.serve_submit(sids[i % 4], scenes.orbit_camera(np.random.default_rng(i), 256, 256),
+                                        pools[(256, 256)][0]))
+        rows = []
+        for rate in rates:
+            reqs = [(t, sids[s], make_camera(c)) for t, s, c in scenes.serve_requests(rate, duration)]
+            ids, pix, k = [], 0, 0
+            t0 = time.perf_counter()
+            for ta, sid, cam in reqs:
+                while True:
+                    dt = ta - (time.perf_counter() - t0)
+                    if dt <= 0:
+                        break
+                    time.sleep(min(dt, 2e-4))
+                buf = pools[(cam.width, cam.height)][k % 48]
+                k += 1
+                rc, rid = R.serve_submit_raw(sid, cam, buf.data_ptr())
+                if rc == 0:
+                    ids.append(rid)
+                    pix += cam.width * cam.height
+            lat = np.array([R.serve_wait(r) for r in ids])
+            wall = time.perf_counter() - t0
+            st = R.serve_stats()
+            rows.append({"rate_rps": rate, "requests": len(ids), "p50_ms": float(np.percentile(lat, 50)),
+                         "p99_ms": float(np.percentile(lat, 99)), "mpixels_per_s": pix / wall / 1e6,
+                         "mean_batch": st["mean_batch"]})
+        R.serve_stop()
+        out["modes"][mode] = rows
+    R.close()
+    return out
+
+
 def cpu_baseline(scene, cam, target, sample):
     """The FP64 oracle, as it stands, on a seeded pixel sample of the workload."""
     import oracle
@@ -108,6 +224,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
+    ap.add_argument("--forms", default="plain,batched,serving", help="comma list of plain, batched, serving")
+    ap.add_argument("--serve-rates", default="50,200,800", help="request rates (req/s) of the serving sweep")
+    ap.add_argument("--serve-seconds", type=float, default=1.5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -198,6 +317,11 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
     R.close()
+    forms = set(args.forms.split(","))
+    if "batched" in forms:
+        line["batched"] = bench_batched(max(3, args.steps // 4), 2)
+    if "serving" in forms:
+        line["serving"] = bench_serving([float(r) for r in args.serve_rates.split(",")], args.serve_seconds)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, cam, target, args.cpu_sample)
     print(json.dumps(line), flush=True)

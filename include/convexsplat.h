@@ -217,6 +217,51 @@ int cs_debug_preprocess(cs_ctx *ctx, const cs_scene *scene, const cs_camera *cam
 int cs_debug_tile_lists(cs_ctx *ctx, const cs_fwd_state *state, int32_t *ranges, int64_t ranges_len,
                         int32_t *ids, int64_t ids_len);
 
+/* ---------------------------------------------------------------- serving --
+ * A request renders one view of a resident scene (paper Sec. 3.2, forward
+ * only).  Requests queue on the host; worker threads, each with its own HIP
+ * stream, take every queued request of the oldest request's scene (up to
+ * max_batch, arrival order) as one batched forward pass as soon as a worker
+ * is free and the batch's estimated device memory fits the budget left by
+ * the batches in flight.  Requests that arrive while others run join the
+ * next batch, and batches on different workers overlap on the device.  A
+ * request's latency runs from cs_serve_submit to the completion of its batch
+ * (host clock).  Its image equals a lone cs_render_forward of the same view. */
+typedef struct {
+    int32_t workers;        /* concurrent batches (streams), >= 1 */
+    int32_t max_batch;      /* views per batch, 1..256 */
+    int32_t max_queue;      /* queued requests before cs_serve_submit returns CS_EBUSY */
+    int32_t start_paused;   /* 1: accept requests but run nothing until cs_serve_resume */
+    size_t hbm_budget_bytes;/* 0 = the context's budget (0 there = unlimited) */
+    cs_params params;       /* render parameters of every request */
+} cs_serve_config;
+
+typedef struct {
+    int64_t submitted, completed, failed, batches;
+    double mean_batch;      /* requests per batch */
+    size_t peak_bytes;      /* largest estimated device memory in flight */
+    int64_t queued, running;
+} cs_serve_stats;
+
+/* Start the request loop of a context (one server per context). */
+int cs_serve_start(cs_ctx *ctx, const cs_serve_config *config);
+/* Let a paused server run. */
+int cs_serve_resume(cs_ctx *ctx);
+/* Finish running batches, fail queued requests, join the workers. */
+int cs_serve_stop(cs_ctx *ctx);
+/* Make a scene resident for serving; the caller keeps its arrays alive and
+ * unchanged until cs_scene_unregister. */
+int cs_scene_register(cs_ctx *ctx, const cs_scene *scene, int32_t *scene_id);
+int cs_scene_unregister(cs_ctx *ctx, int32_t scene_id);
+/* Queue one request (non-blocking).  out_rgb: DEVICE [h][w][3], written when
+ * the request completes.  CS_EBUSY: queue full; CS_ENOMEM: the request alone
+ * exceeds the budget; CS_EINVAL: unknown scene or bad camera. */
+int cs_serve_submit(cs_ctx *ctx, int32_t scene_id, const cs_camera *cam, float *out_rgb, uint64_t *request_id);
+/* Block until a request completes; latency_ms (host, nullable) from submit to
+ * completion.  Returns the request's status (0, or the error of its batch). */
+int cs_serve_wait(cs_ctx *ctx, uint64_t request_id, double *latency_ms);
+int cs_serve_get_stats(cs_ctx *ctx, cs_serve_stats *stats);
+
 /* Accumulated GPU time per stage (ms) and number of timed launches of it, over
  * the calls made with CS_FLAG_TIMING since the last reset; waits for the
  * pending events.  ms and count are host arrays of CS_NUM_STAGES (nullable). */

@@ -23,6 +23,8 @@ EXPORTED = (
     "cs_version", "cs_last_error", "cs_create", "cs_destroy", "cs_render_forward", "cs_render_backward",
     "cs_state_release", "cs_state_stats", "cs_debug_preprocess", "cs_debug_tile_lists", "cs_l1_loss_grad",
     "cs_timing_read", "cs_render_forward_batch", "cs_render_backward_batch", "cs_batch_check", "cs_autotune",
+    "cs_serve_start", "cs_serve_resume", "cs_serve_stop", "cs_scene_register", "cs_scene_unregister",
+    "cs_serve_submit", "cs_serve_wait", "cs_serve_get_stats",
 )
 FLAG_TIMING = 1
 FLAG_LONGEST_FIRST = 2
@@ -65,6 +67,17 @@ class Params(C.Structure):
                 ("tile", C.c_int32), ("flags", C.c_int32)]
 
 
+class ServeConfig(C.Structure):
+    _fields_ = [("workers", C.c_int32), ("max_batch", C.c_int32), ("max_queue", C.c_int32),
+                ("start_paused", C.c_int32), ("hbm_budget_bytes", C.c_size_t), ("params", Params)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64), ("batches", C.c_int64),
+                ("mean_batch", C.c_double), ("peak_bytes", C.c_size_t), ("queued", C.c_int64),
+                ("running", C.c_int64)]
+
+
 class Tuning(C.Structure):
     _fields_ = [("tile", C.c_int32), ("longest_first", C.c_int32), ("digit_bits", C.c_int32), ("ms", C.c_float),
                 ("ms_default", C.c_float)]
@@ -104,6 +117,14 @@ def lib():
         L.cs_render_backward_batch.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp]
         L.cs_batch_check.argtypes = [vp, vp]
         L.cs_autotune.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+        L.cs_serve_start.argtypes = [vp, vp]
+        L.cs_serve_resume.argtypes = [vp]
+        L.cs_serve_stop.argtypes = [vp]
+        L.cs_scene_register.argtypes = [vp, vp, C.POINTER(i32)]
+        L.cs_scene_unregister.argtypes = [vp, i32]
+        L.cs_serve_submit.argtypes = [vp, i32, vp, vp, C.POINTER(C.c_uint64)]
+        L.cs_serve_wait.argtypes = [vp, C.c_uint64, C.POINTER(C.c_double)]
+        L.cs_serve_get_stats.argtypes = [vp, vp]
         _lib = L
     return _lib
 
@@ -314,6 +335,53 @@ class Renderer:
                                  C.byref(t), _stream_handle(scene.points.device)))
         return {"tile": t.tile, "longest_first": t.longest_first, "digit_bits": t.digit_bits, "ms": t.ms,
                 "ms_default": t.ms_default}
+
+    # ------------------------------------------------------------ serving --
+    def serve_start(self, workers=4, max_batch=16, max_queue=1 << 20, start_paused=False, hbm_budget_bytes=0,
+                    params: Params | None = None):
+        cfg = ServeConfig(workers, max_batch, max_queue, int(start_paused), hbm_budget_bytes, params or make_params())
+        _check(lib().cs_serve_start(self.ctx, C.byref(cfg)))
+        self._served_scenes = {}
+
+    def serve_resume(self):
+        _check(lib().cs_serve_resume(self.ctx))
+
+    def serve_stop(self):
+        _check(lib().cs_serve_stop(self.ctx))
+        self._served_scenes = {}
+
+    def scene_register(self, scene: DeviceScene) -> int:
+        sid = C.c_int32()
+        sS = scene.struct()
+        _check(lib().cs_scene_register(self.ctx, C.byref(sS), C.byref(sid)))
+        self._served_scenes[sid.value] = scene  # keep the arrays alive
+        return sid.value
+
+    def scene_unregister(self, sid: int):
+        _check(lib().cs_scene_unregister(self.ctx, sid))
+        self._served_scenes.pop(sid, None)
+
+    def serve_submit(self, sid: int, cam, out: torch.Tensor) -> int:
+        camS = cam if isinstance(cam, Camera) else make_camera(cam)
+        rid = C.c_uint64()
+        _check(lib().cs_serve_submit(self.ctx, sid, C.byref(camS), out.data_ptr(), C.byref(rid)))
+        return rid.value
+
+    def serve_submit_raw(self, sid: int, camS: Camera, out_ptr: int):
+        """Returns (status, request id) without raising (for load generators)."""
+        rid = C.c_uint64()
+        rc = lib().cs_serve_submit(self.ctx, sid, C.byref(camS), out_ptr, C.byref(rid))
+        return rc, rid.value
+
+    def serve_wait(self, rid: int) -> float:
+        lat = C.c_double()
+        _check(lib().cs_serve_wait(self.ctx, rid, C.byref(lat)))
+        return lat.value
+
+    def serve_stats(self) -> dict:
+        st = ServeStats()
+        _check(lib().cs_serve_get_stats(self.ctx, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServeStats._fields_}
 
     def timing(self, reset=True):
         """{stage: (total ms, launches)} of the calls made with FLAG_TIMING."""

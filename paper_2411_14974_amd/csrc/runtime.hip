@@ -226,30 +226,6 @@ int Frame::upload_views(const FrameHeader &hdr, const ViewDesc *views)
 
 // ------------------------------------------------------------- context -----
 
-struct cs_ctx {
-    int device = 0;
-    size_t budget = 0;
-    HostRing ring;
-    // stage timing
-    struct Pending { int stage; hipEvent_t a, b; };
-    std::vector<Pending> pending;
-    std::vector<hipEvent_t> spare;
-    double stage_ms[CS_NUM_STAGES] = {};
-    int64_t stage_count[CS_NUM_STAGES] = {};
-    // batched graph frame and tuning cache
-    hipStream_t capture_stream = nullptr; // graphs are captured here (the null stream cannot be) and launched on the caller's
-    Frame *batch = nullptr;
-    uint64_t batch_key = 0;
-    std::map<std::tuple<int, int, int, int, int>, cs_tuning> tune;
-};
-
-struct cs_fwd_state {
-    Frame *frame = nullptr;
-    bool owned = true; // plain states own their frame; batch-graph states borrow the context's
-    int nviews = 1;
-    uint64_t epoch = 0;
-};
-
 namespace {
 
 // Records hipEvents around the stages of one call when CS_FLAG_TIMING is set.
@@ -590,6 +566,7 @@ int cs_create(int device, size_t hbm_budget_bytes, cs_ctx **out)
 int cs_destroy(cs_ctx *ctx)
 {
     if (!ctx) return CS_OK;
+    if (ctx->server) cs_serve_stop(ctx);
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     delete ctx->batch;

@@ -1,8 +1,11 @@
 // Runtime-side structures of the convex rasterizer (host code only).
 #pragma once
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
+#include "convexsplat.h"
 #include "common.hpp"
 
 namespace cs {
@@ -72,4 +75,33 @@ struct Frame {
     ~Frame();
 };
 
+struct Server;
+
 } // namespace cs
+
+struct cs_ctx {
+    int device = 0;
+    size_t budget = 0;
+    cs::HostRing ring;
+    // stage timing
+    struct Pending { int stage; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> spare;
+    double stage_ms[CS_NUM_STAGES] = {};
+    int64_t stage_count[CS_NUM_STAGES] = {};
+    // batched graph frame and tuning cache
+    hipStream_t capture_stream = nullptr; // graphs are captured here (the null stream cannot be) and launched on the caller's
+    cs::Frame *batch = nullptr;
+    uint64_t batch_key = 0;
+    std::map<std::tuple<int, int, int, int, int>, cs_tuning> tune;
+    // request loop (serve.hip)
+    cs::Server *server = nullptr;
+};
+
+struct cs_fwd_state {
+    cs::Frame *frame = nullptr;
+    bool owned = true; // plain states own their frame; batch-graph states borrow the context's
+    int nviews = 1;
+    uint64_t epoch = 0;
+};
+

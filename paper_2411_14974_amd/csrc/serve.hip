@@ -1,0 +1,316 @@
+// Request loop of the renderer: resident scenes, a host queue of view
+// requests, and worker threads that turn the queued requests of one scene into
+// one batched forward pass on their own stream (continuous batching), admitted
+// by an estimate of the batch's device memory against a budget.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "runtime.hpp"
+
+namespace cs {
+
+namespace {
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+    int32_t scene = 0;
+    cs_camera cam{};
+    float *out = nullptr;
+    double t_submit = 0.0, t_done = 0.0;
+    size_t bytes = 0;
+    int status = 0;
+    bool done = false;
+};
+
+// Device memory of a batched forward pass: per (view, convex) instance the
+// record and 44 bytes of keys, ids, counts, offsets, rectangle and hull; an
+// allowance of 16 (tile, instance) pairs x 16 bytes (two ping-pong pairs of
+// 4-byte arrays); 8 bytes of per-pixel state; and a fixed 1 MiB.
+size_t estimate_bytes(const cs_scene &s, int64_t views, int64_t pixels)
+{
+    const int64_t inst = (int64_t)s.n * views;
+    return (size_t)(inst * (rec_stride(s.k) + 44) + inst * 16 * 16 + pixels * 8 + (1 << 20));
+}
+
+} // namespace
+
+struct Server {
+    cs_ctx *owner = nullptr;
+    cs_serve_config cfg{};
+    size_t budget = 0; // 0 = unlimited
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<uint64_t> queue;
+    std::unordered_map<uint64_t, Request> reqs;
+    std::map<int32_t, cs_scene> scenes;
+    int32_t next_scene = 1;
+    uint64_t next_id = 1;
+    bool stop = false, paused = false;
+    size_t in_flight = 0, peak = 0;
+    int64_t submitted = 0, completed = 0, failed = 0, batches = 0, batch_reqs = 0, running = 0;
+    std::vector<std::thread> workers;
+
+    bool fits(size_t bytes) const { return budget == 0 || in_flight == 0 || in_flight + bytes <= budget; }
+
+    // Under the lock: requests of the oldest request's scene, in arrival order,
+    // as many as max_batch and the budget allow.
+    bool take(std::vector<uint64_t> &ids, size_t &bytes)
+    {
+        ids.clear();
+        bytes = 0;
+        if (queue.empty() || paused) return false;
+        const Request &first = reqs[queue.front()];
+        auto sit = scenes.find(first.scene);
+        if (sit == scenes.end()) { // scene gone: fail it
+            Request &r = reqs[queue.front()];
+            r.status = CS_EINVAL;
+            r.done = true;
+            r.t_done = now_ms();
+            ++failed;
+            queue.pop_front();
+            cv_done.notify_all();
+            return false;
+        }
+        const cs_scene &sc = sit->second;
+        int64_t pix = 0;
+        std::vector<uint64_t> pick;
+        for (uint64_t id : queue) {
+            if ((int)pick.size() >= cfg.max_batch) break;
+            const Request &r = reqs[id];
+            if (r.scene != first.scene) continue;
+            const int64_t p = (int64_t)r.cam.width * r.cam.height;
+            const size_t b = estimate_bytes(sc, (int64_t)pick.size() + 1, pix + p);
+            if (!pick.empty() && budget && in_flight + b > budget) break;
+            pick.push_back(id);
+            pix += p;
+            bytes = b;
+        }
+        if (pick.empty() || !fits(bytes)) return false;
+        for (uint64_t id : pick) {
+            for (auto it = queue.begin(); it != queue.end(); ++it)
+                if (*it == id) {
+                    queue.erase(it);
+                    break;
+                }
+        }
+        ids = pick;
+        return true;
+    }
+
+    void worker(int device)
+    {
+        (void)hipSetDevice(device);
+        cs_ctx *ctx = nullptr;
+        hipStream_t st = nullptr;
+        int init = cs_create(device, 0, &ctx);
+        if (init == CS_OK && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) init = CS_EHIP;
+        cs_params prm = cfg.params;
+        prm.flags &= ~(CS_FLAG_GRAPH | CS_FLAG_AUTOTUNE | CS_FLAG_TIMING);
+        std::vector<uint64_t> ids;
+        std::vector<cs_camera> cams;
+        std::vector<float *> outs;
+        for (;;) {
+            size_t bytes = 0;
+            cs_scene sc{};
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait(lk, [&] { return stop || (!paused && !queue.empty()); });
+                if (stop) break;
+                if (!take(ids, bytes)) {
+                    cv_work.wait_for(lk, std::chrono::microseconds(200));
+                    continue;
+                }
+                sc = scenes[reqs[ids[0]].scene];
+                cams.clear();
+                outs.clear();
+                for (uint64_t id : ids) {
+                    cams.push_back(reqs[id].cam);
+                    outs.push_back(reqs[id].out);
+                }
+                in_flight += bytes;
+                peak = std::max(peak, in_flight);
+                running += (int64_t)ids.size();
+            }
+            int rc = init;
+            if (rc == CS_OK)
+                rc = cs_render_forward_batch(ctx, &sc, (int32_t)ids.size(), cams.data(), &prm, outs.data(), nullptr,
+                                             st);
+            if (rc == CS_OK && hipStreamSynchronize(st) != hipSuccess) rc = CS_EHIP;
+            const double t = now_ms();
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                for (uint64_t id : ids) {
+                    Request &r = reqs[id];
+                    r.status = rc;
+                    r.t_done = t;
+                    r.done = true;
+                }
+                in_flight -= bytes;
+                running -= (int64_t)ids.size();
+                ++batches;
+                batch_reqs += (int64_t)ids.size();
+                (rc == CS_OK ? completed : failed) += (int64_t)ids.size();
+            }
+            cv_done.notify_all();
+            cv_work.notify_all();
+        }
+        if (st) (void)hipStreamDestroy(st);
+        if (ctx) cs_destroy(ctx);
+    }
+};
+
+} // namespace cs
+
+using namespace cs;
+
+extern "C" {
+
+int cs_serve_start(cs_ctx *ctx, const cs_serve_config *cfg)
+{
+    if (!ctx || !cfg) return fail(CS_EINVAL, "ctx or config is NULL");
+    if (ctx->server) return fail(CS_EINVAL, "server already running on this context");
+    if (cfg->workers < 1 || cfg->workers > 16) return fail(CS_EINVAL, "workers = %d outside [1, 16]", cfg->workers);
+    if (cfg->max_batch < 1 || cfg->max_batch > MAX_VIEWS)
+        return fail(CS_EINVAL, "max_batch = %d outside [1, %d]", cfg->max_batch, MAX_VIEWS);
+    if (cfg->max_queue < 1) return fail(CS_EINVAL, "max_queue must be >= 1");
+    Server *S = new Server;
+    S->owner = ctx;
+    S->cfg = *cfg;
+    S->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : ctx->budget;
+    S->paused = cfg->start_paused != 0;
+    ctx->server = S;
+    for (int w = 0; w < cfg->workers; ++w) S->workers.emplace_back([S, dev = ctx->device] { S->worker(dev); });
+    return CS_OK;
+}
+
+int cs_serve_resume(cs_ctx *ctx)
+{
+    if (!ctx || !ctx->server) return fail(CS_EINVAL, "no server on this context");
+    Server *S = ctx->server;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->paused = false;
+    }
+    S->cv_work.notify_all();
+    return CS_OK;
+}
+
+int cs_serve_stop(cs_ctx *ctx)
+{
+    if (!ctx || !ctx->server) return CS_OK;
+    Server *S = ctx->server;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv_work.notify_all();
+    for (auto &t : S->workers) t.join();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (uint64_t id : S->queue) {
+            Request &r = S->reqs[id];
+            r.status = CS_EBUSY;
+            r.done = true;
+            ++S->failed;
+        }
+        S->queue.clear();
+    }
+    S->cv_done.notify_all();
+    ctx->server = nullptr;
+    delete S;
+    return CS_OK;
+}
+
+int cs_scene_register(cs_ctx *ctx, const cs_scene *scene, int32_t *scene_id)
+{
+    if (!ctx || !ctx->server || !scene_id) return fail(CS_EINVAL, "no server or NULL argument");
+    if (!scene) return fail(CS_EINVAL, "scene is NULL");
+    if (scene->k < 3 || scene->k > CS_MAX_K || scene->sh_degree < 0 || scene->sh_degree > 3 || scene->n < 0)
+        return fail(CS_EINVAL, "bad scene shape");
+    Server *S = ctx->server;
+    std::lock_guard<std::mutex> lk(S->mu);
+    *scene_id = S->next_scene++;
+    S->scenes[*scene_id] = *scene;
+    return CS_OK;
+}
+
+int cs_scene_unregister(cs_ctx *ctx, int32_t scene_id)
+{
+    if (!ctx || !ctx->server) return fail(CS_EINVAL, "no server on this context");
+    Server *S = ctx->server;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (!S->scenes.erase(scene_id)) return fail(CS_EINVAL, "unknown scene %d", scene_id);
+    return CS_OK;
+}
+
+int cs_serve_submit(cs_ctx *ctx, int32_t scene_id, const cs_camera *cam, float *out_rgb, uint64_t *request_id)
+{
+    if (!ctx || !ctx->server || !cam || !out_rgb || !request_id) return fail(CS_EINVAL, "NULL argument");
+    if (cam->width <= 0 || cam->height <= 0 || cam->width > 16384 || cam->height > 16384 || !(cam->fx > 0.0f) ||
+        !(cam->fy > 0.0f) || !(cam->znear > 0.0f))
+        return fail(CS_EINVAL, "bad camera");
+    Server *S = ctx->server;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->scenes.find(scene_id);
+        if (it == S->scenes.end()) return fail(CS_EINVAL, "unknown scene %d", scene_id);
+        if ((int)S->queue.size() >= S->cfg.max_queue) return fail(CS_EBUSY, "serving queue full");
+        const size_t b = estimate_bytes(it->second, 1, (int64_t)cam->width * cam->height);
+        if (S->budget && b > S->budget)
+            return fail(CS_ENOMEM, "request needs ~%zu bytes, budget %zu", b, S->budget);
+        const uint64_t id = S->next_id++;
+        Request &r = S->reqs[id];
+        r.scene = scene_id;
+        r.cam = *cam;
+        r.out = out_rgb;
+        r.bytes = b;
+        r.t_submit = now_ms();
+        S->queue.push_back(id);
+        ++S->submitted;
+        *request_id = id;
+    }
+    S->cv_work.notify_one();
+    return CS_OK;
+}
+
+int cs_serve_wait(cs_ctx *ctx, uint64_t request_id, double *latency_ms)
+{
+    if (!ctx || !ctx->server) return fail(CS_EINVAL, "no server on this context");
+    Server *S = ctx->server;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(request_id);
+    if (it == S->reqs.end()) return fail(CS_EINVAL, "unknown request %llu", (unsigned long long)request_id);
+    S->cv_done.wait(lk, [&] { return S->reqs[request_id].done; });
+    Request r = S->reqs[request_id];
+    S->reqs.erase(request_id);
+    if (latency_ms) *latency_ms = r.t_done - r.t_submit;
+    if (r.status != CS_OK) return fail(r.status, "request %llu failed (%d)", (unsigned long long)request_id, r.status);
+    return CS_OK;
+}
+
+int cs_serve_get_stats(cs_ctx *ctx, cs_serve_stats *out)
+{
+    if (!ctx || !ctx->server || !out) return fail(CS_EINVAL, "no server or NULL argument");
+    Server *S = ctx->server;
+    std::lock_guard<std::mutex> lk(S->mu);
+    out->submitted = S->submitted;
+    out->completed = S->completed;
+    out->failed = S->failed;
+    out->batches = S->batches;
+    out->mean_batch = S->batches ? (double)S->batch_reqs / S->batches : 0.0;
+    out->peak_bytes = S->peak;
+    out->queued = (int64_t)S->queue.size();
+    out->running = S->running;
+    return CS_OK;
+}
+
+} // extern "C"

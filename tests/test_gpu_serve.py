@@ -1,0 +1,98 @@
+"""Serving: continuous batching of view requests against resident scenes.
+
+Each served image must equal the same view rendered alone by the plain path
+(bit-identical: a batch evaluates every pixel exactly like a single view),
+whatever batch it landed in; admission and queue limits return their codes.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2411_14974_amd import scenes  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2411_14974_amd.binding import Renderer
+    r = Renderer(0)
+    yield r
+    r.close()
+
+
+def two_scenes():
+    from paper_2411_14974_amd.binding import DeviceScene
+    out = []
+    for i, n in enumerate((8000, 20000)):
+        rng = np.random.default_rng(5000 + i)
+        out.append(DeviceScene.from_scene(scenes.convexes_around(rng, scenes.gmm_centres(rng, n), 6, 3), "cuda:0"))
+    return out
+
+
+def test_served_equals_alone_in_the_mix(R):
+    from paper_2411_14974_amd.binding import make_params
+    ds = two_scenes()
+    R.serve_start(workers=3, max_batch=6, start_paused=True)
+    try:
+        sids = [R.scene_register(d) for d in ds]
+        rng = np.random.default_rng(11)
+        res = ((256, 256), (160, 90), (320, 180))
+        reqs = []
+        for i in range(20):
+            s = int(rng.integers(0, 2))
+            cam = scenes.orbit_camera(rng, *res[int(rng.integers(0, 3))])
+            out = torch.full((cam.height, cam.width, 3), -1.0, device="cuda:0")
+            reqs.append((s, cam, out, R.serve_submit(sids[s], cam, out)))
+        R.serve_resume()  # everything queued before the workers start: batches form
+        lat = [R.serve_wait(rid) for _, _, _, rid in reqs]
+        st = R.serve_stats()
+        print(f"[serve] stats {st}, latency ms max {max(lat):.2f}", flush=True)
+        assert st["completed"] == 20 and st["failed"] == 0 and st["mean_batch"] > 1.0
+        torch.cuda.synchronize()
+        for s, cam, out, _ in reqs:
+            alone, _ = R.forward(ds[s], cam, make_params())
+            torch.cuda.synchronize()
+            assert torch.equal(out, alone)
+        # while requests run, more arrive and join later batches
+        more = []
+        for i in range(30):
+            cam = scenes.orbit_camera(rng, 128, 96)
+            out = torch.empty((96, 128, 3), device="cuda:0")
+            more.append((cam, out, R.serve_submit(sids[1], cam, out)))
+        for cam, out, rid in more:
+            R.serve_wait(rid)
+        torch.cuda.synchronize()
+        for cam, out, _ in more[::5]:
+            alone, _ = R.forward(ds[1], cam, make_params())
+            torch.cuda.synchronize()
+            assert torch.equal(out, alone)
+    finally:
+        R.serve_stop()
+
+
+def test_admission_and_queue_limits(R):
+    from paper_2411_14974_amd.binding import CS_EBUSY, CS_EINVAL, CS_ENOMEM, make_camera
+    ds = two_scenes()
+    cam = make_camera(scenes.origin_camera(64, 64))
+    out = torch.empty((64, 64, 3), device="cuda:0")
+    # a budget no request fits
+    R.serve_start(workers=1, max_batch=4, hbm_budget_bytes=4096)
+    try:
+        sid = R.scene_register(ds[0])
+        rc, _ = R.serve_submit_raw(sid, cam, out.data_ptr())
+        assert rc == CS_ENOMEM
+        rc, _ = R.serve_submit_raw(sid + 100, cam, out.data_ptr())
+        assert rc == CS_EINVAL
+    finally:
+        R.serve_stop()
+    # queue limit while paused; stop fails what is still queued
+    R.serve_start(workers=1, max_batch=4, max_queue=2, start_paused=True)
+    sid = R.scene_register(ds[0])
+    rc1, r1 = R.serve_submit_raw(sid, cam, out.data_ptr())
+    rc2, r2 = R.serve_submit_raw(sid, cam, out.data_ptr())
+    rc3, _ = R.serve_submit_raw(sid, cam, out.data_ptr())
+    assert (rc1, rc2, rc3) == (0, 0, CS_EBUSY)
+    assert R.serve_stats()["queued"] == 2
+    R.serve_stop()
