@@ -289,72 +289,75 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
 // coefficients, sigma', opacity, colour, x2-weighted sum) through lines -> hull
 // vertices -> projection -> points, delta' and sigma' -> (delta, sigma, d),
 // d -> every point, colour -> SH and view direction.  The geometry is
-// recomputed from the points and the stored hull indices, bit-identically to
-// the forward pass.
+// recomputed from the points (camera transform in FP64, the rest in FP32 with
+// pixel coordinates relative to the record's origin, the frame in which the
+// forward pass stored its lines); gradients need relative, not absolute,
+// accuracy.
 template <int K>
-__device__ __forceinline__ void view_backward(int deg, const float *px, const float *py, const float *pz, double dl,
-                                              double sg, const float *f, const CamArgs &cam, uint32_t hp,
-                                              const float *__restrict__ A, float *gp, float &gdelta, float &gsigma,
-                                              float &gopac, float *gsh)
+__device__ __forceinline__ void view_backward(int deg, const float *px, const float *py, const float *pz, float dl,
+                                              float sg, const float *f, const CamArgs &cam, uint32_t hp,
+                                              const RecHeader &hdr, const float *__restrict__ A, float *gp,
+                                              float &gdelta, float &gsigma, float &gopac, float *gsh)
 {
     const int T = (int)(hp >> 28);
     const int nc = (deg + 1) * (deg + 1);
-    double X[K], Y[K], Z[K], qx[K], qy[K];
     const double r0 = cam.R[0], r1 = cam.R[1], r2 = cam.R[2], r3 = cam.R[3], r4 = cam.R[4], r5 = cam.R[5];
     const double r6 = cam.R[6], r7 = cam.R[7], r8 = cam.R[8];
+    // per point: projected position relative to the origin, 1/Z, X/Z, Y/Z
+    float qx[K], qy[K], iz[K], xz[K], yz[K];
     double zs = 0.0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const double x = px[k], y = py[k], z = pz[k];
-        X[k] = r0 * x + r1 * y + r2 * z + (double)cam.t[0];
-        Y[k] = r3 * x + r4 * y + r5 * z + (double)cam.t[1];
-        Z[k] = r6 * x + r7 * y + r8 * z + (double)cam.t[2];
-        qx[k] = (double)cam.fx * X[k] / Z[k] + (double)cam.cx;
-        qy[k] = (double)cam.fy * Y[k] / Z[k] + (double)cam.cy;
-        zs += Z[k];
+        const double X = r0 * x + r1 * y + r2 * z + (double)cam.t[0];
+        const double Y = r3 * x + r4 * y + r5 * z + (double)cam.t[1];
+        const double Z = r6 * x + r7 * y + r8 * z + (double)cam.t[2];
+        const double izd = 1.0 / Z;
+        qx[k] = (float)((double)cam.fx * X * izd + (double)cam.cx - (double)hdr.ox);
+        qy[k] = (float)((double)cam.fy * Y * izd + (double)cam.cy - (double)hdr.oy);
+        iz[k] = (float)izd;
+        xz[k] = (float)(X * izd);
+        yz[k] = (float)(Y * izd);
+        zs += Z;
     }
-    const double dd = zs / K;
-    const double dp = dd * dl;
-    const double s2 = dp * LOG2E;
+    const float dd = (float)(zs / K);
+    const float dp = dd * dl;
+    const float s2 = dp * (float)LOG2E;
 
-    // hull vertices in order
-    double vx[K], vy[K];
+    // hull vertices in order (relative to the origin)
+    float vx[K], vy[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const int v = (hp >> (3 * j)) & 7;
-        vx[j] = 0.0;
-        vy[j] = 0.0;
+        vx[j] = 0.0f;
+        vy[j] = 0.0f;
 #pragma unroll
         for (int k = 0; k < K; ++k)
             if (k == v) { vx[j] = qx[k]; vy[j] = qy[k]; }
     }
-    // origin used by the forward pass: the start vertex rounded
-    const double ox = rint(vx[0]), oy = rint(vy[0]);
-
-    double gvx[K], gvy[K];
+    float gvx[K], gvy[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) { gvx[j] = 0.0; gvy[j] = 0.0; }
+    for (int j = 0; j < K; ++j) { gvx[j] = 0.0f; gvy[j] = 0.0f; }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         if (j >= T) continue;
         // edge j: vertex j -> vertex j+1 (mod T)
-        double bxv = vx[0], byv = vy[0];
+        float bxv = vx[0], byv = vy[0];
 #pragma unroll
         for (int jj = 1; jj < K; ++jj)
             if (jj == j + 1 && jj < T) { bxv = vx[jj]; byv = vy[jj]; }
-        const double ex = bxv - vx[j], ey = byv - vy[j];
-        const double len = sqrt(ex * ex + ey * ey);
-        const double tx = ex / len, ty = ey / len;
-        const double nA = ty, nB = -tx;
-        const double ax = vx[j] - ox, ay = vy[j] - oy;
-        // stored (a, b, c) = s2 * (A, B, C'), C' = -(A ax + B ay)
-        const double gA = s2 * (double)A[j], gB = s2 * (double)A[K + j], gC = s2 * (double)A[2 * K + j];
-        const double gAt = gA - gC * ax, gBt = gB - gC * ay;
+        const float ex = bxv - vx[j], ey = byv - vy[j];
+        const float il = 1.0f / sqrtf(ex * ex + ey * ey);
+        const float tx = ex * il, ty = ey * il;
+        const float nA = ty, nB = -tx;
+        // stored (a, b, c) = s2 * (A, B, C'), C' = -(A vx + B vy) in the origin's frame
+        const float gA = s2 * A[j], gB = s2 * A[K + j], gC = s2 * A[2 * K + j];
+        const float gAt = gA - gC * vx[j], gBt = gB - gC * vy[j];
         gvx[j] -= gC * nA;
         gvy[j] -= gC * nB;
         // n = (e_y, -e_x)/|e|  =>  dL/de = -((g_n . t)/|e|) n
-        const double sdot = (gAt * tx + gBt * ty) / len;
-        const double gex = -sdot * nA, gey = -sdot * nB;
+        const float sdot = (gAt * tx + gBt * ty) * il;
+        const float gex = -sdot * nA, gey = -sdot * nB;
         gvx[j] -= gex;
         gvy[j] -= gey;
 #pragma unroll
@@ -362,17 +365,17 @@ __device__ __forceinline__ void view_backward(int deg, const float *px, const fl
             if (jj == ((j + 1 == T) ? 0 : j + 1)) { gvx[jj] += gex; gvy[jj] += gey; }
     }
     // x2_j = delta' log2(e) L_j  =>  dx2_j / ddelta' = x2_j / delta'
-    const double gdp = (double)A[3 * K + 5] / dp;
-    const double gsp = (double)A[3 * K];
-    gdelta += (float)(dd * gdp);
-    gsigma += (float)(dd * gsp);
+    const float gdp = A[3 * K + 5] / dp;
+    const float gsp = A[3 * K];
+    gdelta += dd * gdp;
+    gsigma += dd * gsp;
     gopac += A[3 * K + 1];
-    const double gd = dl * gdp + sg * gsp;
+    const float gd = dl * gdp + sg * gsp;
 
     // hull vertices -> projected points
-    double gqx[K], gqy[K];
+    float gqx[K], gqy[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) { gqx[k] = 0.0; gqy[k] = 0.0; }
+    for (int k = 0; k < K; ++k) { gqx[k] = 0.0f; gqy[k] = 0.0f; }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         if (j >= T) continue;
@@ -382,13 +385,13 @@ __device__ __forceinline__ void view_backward(int deg, const float *px, const fl
             if (k == v) { gqx[k] += gvx[j]; gqy[k] += gvy[j]; }
     }
 
-    // colour -> SH coefficients and the view direction
+    // colour -> SH coefficients and the view direction (same arithmetic as the forward pass)
     double cxw = 0, cyw = 0, czw = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) { cxw += px[k]; cyw += py[k]; czw += pz[k]; }
     const double wx = cxw / K - cam.campos[0], wy = cyw / K - cam.campos[1], wz = czw / K - cam.campos[2];
-    const double dist = sqrt(wx * wx + wy * wy + wz * wz);
-    const float dx = (float)(wx / dist), dy = (float)(wy / dist), dz = (float)(wz / dist);
+    const double inv = 1.0 / sqrt(wx * wx + wy * wy + wz * wz);
+    const float dx = (float)(wx * inv), dy = (float)(wy * inv), dz = (float)(wz * inv);
     float Yb[16];
     sh_eval(deg, dx, dy, dz, Yb);
     float raw[3] = {0.5f, 0.5f, 0.5f};
@@ -409,65 +412,105 @@ __device__ __forceinline__ void view_backward(int deg, const float *px, const fl
     }
     float gdx = 0.f, gdy = 0.f, gdz = 0.f;
     sh_grad_dot(deg, dx, dy, dz, wsum, gdx, gdy, gdz);
-    // unit direction -> centre:  (I - dir dir^T) / |centre - campos|
-    const double dot = (double)dx * gdx + (double)dy * gdy + (double)dz * gdz;
-    const double gcx = ((double)gdx - dx * dot) / dist / K;
-    const double gcy = ((double)gdy - dy * dot) / dist / K;
-    const double gcz = ((double)gdz - dz * dot) / dist / K;
+    // unit direction -> centre:  (I - dir dir^T) / |centre - campos|, then / K per point
+    const float dot = dx * gdx + dy * gdy + dz * gdz;
+    const float sc = (float)inv / K;
+    const float gcx = (gdx - dx * dot) * sc, gcy = (gdy - dy * dot) * sc, gcz = (gdz - dz * dot) * sc;
 
     // projection and depth -> camera space -> world (R^T)
-    const double fx = cam.fx, fy = cam.fy;
+    const float fx = cam.fx, fy = cam.fy;
+    const float R0 = cam.R[0], R1 = cam.R[1], R2 = cam.R[2], R3 = cam.R[3], R4 = cam.R[4], R5 = cam.R[5];
+    const float R6 = cam.R[6], R7 = cam.R[7], R8 = cam.R[8];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const double iz = 1.0 / Z[k];
-        const double gX = gqx[k] * fx * iz, gY = gqy[k] * fy * iz;
-        const double gZ = -(gqx[k] * fx * X[k] + gqy[k] * fy * Y[k]) * iz * iz + gd / K;
-        gp[3 * k + 0] += (float)(r0 * gX + r3 * gY + r6 * gZ + gcx);
-        gp[3 * k + 1] += (float)(r1 * gX + r4 * gY + r7 * gZ + gcy);
-        gp[3 * k + 2] += (float)(r2 * gX + r5 * gY + r8 * gZ + gcz);
+        const float gX = gqx[k] * fx * iz[k], gY = gqy[k] * fy * iz[k];
+        const float gZ = -(gX * xz[k] + gY * yz[k]) + gd / K;
+        gp[3 * k + 0] += R0 * gX + R3 * gY + R6 * gZ + gcx;
+        gp[3 * k + 1] += R1 * gX + R4 * gY + R7 * gZ + gcy;
+        gp[3 * k + 2] += R2 * gX + R5 * gY + R8 * gZ + gcz;
     }
 }
 
+constexpr int PB_BLOCK = 128;
+constexpr int PB_SH_STRIDE = 49; // odd LDS row strides keep per-thread rows conflict-free
+
+// Block-cooperative, coalesced copies between a contiguous global run of
+// `rows` rows of W floats and LDS rows of stride S.
+template <int W, int S> __device__ __forceinline__ void rows_to_lds(float *lds, const float *g, int rows)
+{
+    for (int j = threadIdx.x; j < rows * W; j += PB_BLOCK) lds[(j / W) * S + j % W] = g[j];
+}
+template <int W, int S> __device__ __forceinline__ void rows_from_lds(float *g, const float *lds, int rows)
+{
+    for (int j = threadIdx.x; j < rows * W; j += PB_BLOCK) g[j] = lds[(j / W) * S + j % W];
+}
+__device__ __forceinline__ void sh_rows(bool to_lds, int deg, float *lds, float *g, int rows)
+{
+    switch (deg) {
+    case 0: to_lds ? rows_to_lds<3, PB_SH_STRIDE>(lds, g, rows) : rows_from_lds<3, PB_SH_STRIDE>(g, lds, rows); break;
+    case 1: to_lds ? rows_to_lds<12, PB_SH_STRIDE>(lds, g, rows) : rows_from_lds<12, PB_SH_STRIDE>(g, lds, rows); break;
+    case 2: to_lds ? rows_to_lds<27, PB_SH_STRIDE>(lds, g, rows) : rows_from_lds<27, PB_SH_STRIDE>(g, lds, rows); break;
+    default: to_lds ? rows_to_lds<48, PB_SH_STRIDE>(lds, g, rows) : rows_from_lds<48, PB_SH_STRIDE>(g, lds, rows); break;
+    }
+}
+
+// One thread per convex, 128 convexes per workgroup.  Points are staged
+// through LDS with coalesced loads, the SH gradient is accumulated over the
+// views in LDS, and all gradients leave through LDS as coalesced stores.
 template <int K>
-__global__ __launch_bounds__(256) void preprocess_bwd_kernel(
+__global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
     int n, int nviews, int deg, const float *__restrict__ points, const float *__restrict__ delta,
     const float *__restrict__ sigma, const float *__restrict__ sh, const FrameHeader *__restrict__ frame,
-    const uint32_t *__restrict__ hullpk, const float *__restrict__ acc, float *__restrict__ g_points,
-    float *__restrict__ g_delta, float *__restrict__ g_sigma, float *__restrict__ g_opacity,
-    float *__restrict__ g_sh)
+    const uint8_t *__restrict__ records, const uint32_t *__restrict__ hullpk, const float *__restrict__ acc,
+    float *__restrict__ g_points, float *__restrict__ g_delta, float *__restrict__ g_sigma,
+    float *__restrict__ g_opacity, float *__restrict__ g_sh)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    constexpr int PS = 3 * K + 1;
+    __shared__ float s_pts[PB_BLOCK * PS];
+    __shared__ float s_gsh[PB_BLOCK * PB_SH_STRIDE];
+    const int base = blockIdx.x * PB_BLOCK;
+    const int cnt = min(PB_BLOCK, n - base);
+    const int tid = threadIdx.x;
     const int nc = (deg + 1) * (deg + 1);
-    float gp[3 * K], gsh[48];
+    rows_to_lds<3 * K, PS>(s_pts, points + (size_t)base * 3 * K, cnt);
+    for (int j = tid; j < PB_BLOCK * PB_SH_STRIDE; j += PB_BLOCK) s_gsh[j] = 0.0f;
+    __syncthreads();
+
+    const int i = base + tid;
+    float gp[3 * K];
 #pragma unroll
     for (int k = 0; k < 3 * K; ++k) gp[k] = 0.0f;
-#pragma unroll
-    for (int c = 0; c < 48; ++c) gsh[c] = 0.0f;
     float gdelta = 0.0f, gsigma = 0.0f, gopac = 0.0f;
-
-    const float *p = points + (size_t)i * K * 3;
-    float px[K], py[K], pz[K];
+    if (tid < cnt) {
+        float px[K], py[K], pz[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) { px[k] = p[3 * k]; py[k] = p[3 * k + 1]; pz[k] = p[3 * k + 2]; }
-    const double dl = (double)delta[i], sg = (double)sigma[i];
-    const float *f = sh + (size_t)i * nc * 3;
-    const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
-    for (int v = 0; v < nviews; ++v) {
-        const size_t inst = (size_t)v * n + i;
-        const uint32_t hp = hullpk[inst];
-        if ((int)(hp >> 28) < 3) continue; // dropped in this view: no gradient
-        view_backward<K>(deg, px, py, pz, dl, sg, f, views[v].cam, hp, acc + inst * acc_stride(K), gp, gdelta,
-                         gsigma, gopac, gsh);
+        for (int k = 0; k < K; ++k) {
+            px[k] = s_pts[tid * PS + 3 * k];
+            py[k] = s_pts[tid * PS + 3 * k + 1];
+            pz[k] = s_pts[tid * PS + 3 * k + 2];
+        }
+        const float dl = delta[i], sg = sigma[i];
+        const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
+        for (int v = 0; v < nviews; ++v) {
+            const size_t inst = (size_t)v * n + i;
+            const uint32_t hp = hullpk[inst];
+            if ((int)(hp >> 28) < 3) continue; // dropped in this view: no gradient
+            const RecHeader hdr = *reinterpret_cast<const RecHeader *>(records + inst * rec_stride(K));
+            view_backward<K>(deg, px, py, pz, dl, sg, sh + (size_t)i * 3 * nc, views[v].cam, hp, hdr,
+                             acc + inst * acc_stride(K), gp, gdelta, gsigma, gopac, &s_gsh[tid * PB_SH_STRIDE]);
+        }
     }
-    float *gpo = g_points + (size_t)i * K * 3;
+    __syncthreads();
+    if (tid < cnt) {
 #pragma unroll
-    for (int k = 0; k < 3 * K; ++k) gpo[k] = gp[k];
-    float *gso = g_sh + (size_t)i * nc * 3;
-    for (int c = 0; c < 3 * nc; ++c) gso[c] = gsh[c];
-    g_delta[i] = gdelta;
-    g_sigma[i] = gsigma;
-    g_opacity[i] = gopac;
+        for (int k = 0; k < 3 * K; ++k) s_pts[tid * PS + k] = gp[k];
+        g_delta[i] = gdelta;
+        g_sigma[i] = gsigma;
+        g_opacity[i] = gopac;
+    }
+    __syncthreads();
+    rows_from_lds<3 * K, PS>(g_points + (size_t)base * 3 * K, s_pts, cnt);
+    sh_rows(false, deg, s_gsh, g_sh + (size_t)base * 3 * nc, cnt);
 }
 
 // ------------------------------------------------------------- launchers ---
@@ -496,13 +539,14 @@ void launch_preprocess_fwd(hipStream_t st, int n, int nviews, int K, int deg, co
 
 void launch_preprocess_bwd(hipStream_t st, int n, int nviews, int K, int deg, const float *points,
                            const float *delta, const float *sigma, const float *sh, const FrameHeader *views,
-                           const uint32_t *hullpk, const float *acc, float *g_points, float *g_delta,
+                           const uint8_t *records, const uint32_t *hullpk, const float *acc, float *g_points, float *g_delta,
                            float *g_sigma, float *g_opacity, float *g_sh)
 {
     if (n <= 0) return;
-    dim3 grid((n + 255) / 256), block(256);
+    dim3 grid((n + PB_BLOCK - 1) / PB_BLOCK), block(PB_BLOCK);
     CS_DISPATCH_K(K, hipLaunchKernelGGL(preprocess_bwd_kernel<KK>, grid, block, 0, st, n, nviews, deg, points, delta,
-                                        sigma, sh, views, hullpk, acc, g_points, g_delta, g_sigma, g_opacity, g_sh));
+                                        sigma, sh, views, records, hullpk, acc, g_points, g_delta, g_sigma,
+                                        g_opacity, g_sh));
 }
 
 } // namespace cs

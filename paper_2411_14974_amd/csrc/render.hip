@@ -16,8 +16,9 @@
 //
 // The backward kernel walks the same lists back to front from each pixel's
 // last contributor, recomputing alpha with the same function (bit-identical
-// decisions), recovering T_n = T_{n+1} / (1 - alpha_n), and reduces the per-pair
-// gradients over the wavefront before one atomic add per convex value.
+// decisions), recovering T_n = T_{n+1} / (1 - alpha_n); the per-pair gradients
+// are reduced over the wavefront (DPP), summed over the workgroup's waves in
+// LDS, and leave as one float atomic add per (convex, value) and workgroup.
 #include <algorithm>
 #include <mutex>
 #include <unordered_map>
@@ -80,17 +81,29 @@ __device__ __forceinline__ bool eval_pair(const uint8_t *rec, float pxf, float p
     return true;
 }
 
-__device__ __forceinline__ float wave_sum(float x)
+// Sums of NV values over the 64 lanes; lane q (q < NV) receives the sum of
+// value q.  The DPP steps run across all values at once (independent chains
+// hide the DPP hazards): quad_perm / half-mirror / mirror give every lane its
+// row sum, row_bcast:15 and row_bcast:31 fold the rows into lane 63.
+template <int NV> __device__ __forceinline__ float wave_sums_to_lanes(float *v, int lane)
 {
-    x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, true));  // quad_perm 1,0,3,2
-    x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x4E, 0xF, 0xF, true));  // quad_perm 2,3,0,1
-    x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x141, 0xF, 0xF, true)); // row_half_mirror
-    x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x140, 0xF, 0xF, true)); // row_mirror
-    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
-    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
-    const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
-    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
-    return (a + b) + (c + d);
+#define CS_DPP_STEP(CTRL, ROWMASK)                                                                                 \
+    _Pragma("unroll") for (int q = 0; q < NV; ++q) v[q] += __int_as_float(                                          \
+        __builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), CTRL, ROWMASK, 0xF, false));
+    CS_DPP_STEP(0xB1, 0xF)  // quad_perm 1,0,3,2
+    CS_DPP_STEP(0x4E, 0xF)  // quad_perm 2,3,0,1
+    CS_DPP_STEP(0x141, 0xF) // row_half_mirror
+    CS_DPP_STEP(0x140, 0xF) // row_mirror
+    CS_DPP_STEP(0x142, 0xA) // row_bcast:15 into rows 1, 3
+    CS_DPP_STEP(0x143, 0xC) // row_bcast:31 into rows 2, 3
+#undef CS_DPP_STEP
+    float mine = 0.0f;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[q]), 63));
+        if (lane == q) mine = s;
+    }
+    return mine;
 }
 
 template <int K, int NT>
@@ -244,8 +257,10 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
     static_assert(NV <= 64, "one lane per reduced value");
     __shared__ uint4 lds[BATCH * CH];
     __shared__ uint32_t s_ids[BATCH];
+    __shared__ float s_acc[BATCH * NV]; // per-entry sums of the block's waves, flushed after each batch
     __shared__ int s_maxn;
     __shared__ uint32_t s_item;
+    for (int c = threadIdx.x; c < BATCH * NV; c += NT) s_acc[c] = 0.0f;
     const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
     const int nviews = (int)frame->nviews;
     const uint32_t total_tiles = frame->total_tiles;
@@ -332,19 +347,18 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
                     B1 = fmaf(pe.alpha, h.rgb[1], pe.oma * B1);
                     B2 = fmaf(pe.alpha, h.rgb[2], pe.oma * B2);
                 }
-                const int T = h.T;
-                float mine = 0.0f;
-#pragma unroll
-                for (int qv = 0; qv < NV; ++qv) {
-                    const int j = qv < 3 * K ? qv % K : 0;
-                    if (j < T) { // uniform
-                        const float s = wave_sum(val[qv]);
-                        if (lane == qv) mine = s;
-                    }
+                const float mine = wave_sums_to_lanes<NV>(val, lane);
+                if (lane < NV && mine != 0.0f) atomicAdd(&s_acc[e * NV + lane], mine);
+            }
+            // one global atomic per (entry, value) for the whole block
+            __syncthreads();
+            for (int c = threadIdx.x; c < cnt * NV; c += NT) {
+                const float a = s_acc[c];
+                if (a != 0.0f) {
+                    const int e = c / NV, qv = c - e * NV;
+                    unsafeAtomicAdd(&acc[(size_t)s_ids[e] * AS + qv], a);
+                    s_acc[c] = 0.0f;
                 }
-                const int jl = lane < 3 * K ? lane % K : 0;
-                if (lane < NV && jl < T && mine != 0.0f)
-                    unsafeAtomicAdd(&acc[(size_t)s_ids[e] * AS + lane], mine);
             }
         }
     }

@@ -21,8 +21,8 @@ void launch_preprocess_fwd(hipStream_t, int, int, int, int, const float *, const
                            const float *, const float *, const FrameHeader *, const RenderArgs &, uint8_t *,
                            uint32_t *, uint32_t *, uint2 *, uint32_t *, uint32_t *, DebugConvex *);
 void launch_preprocess_bwd(hipStream_t, int, int, int, int, const float *, const float *, const float *,
-                           const float *, const FrameHeader *, const uint32_t *, const float *, float *, float *,
-                           float *, float *, float *);
+                           const float *, const FrameHeader *, const uint8_t *, const uint32_t *, const float *,
+                           float *, float *, float *, float *, float *);
 void radix_sort(hipStream_t, uint32_t **, uint32_t **, uint32_t **, uint32_t **, uint32_t, const uint32_t *, int, int,
                 uint32_t *, uint32_t *, int);
 int radix_blocks(uint32_t);
@@ -105,6 +105,7 @@ Frame::~Frame()
         if (p) (void)hipFreeAsync(p, st);
     if (counters_ev) (void)hipEventSynchronize(counters_ev), (void)hipEventDestroy(counters_ev);
     if (h_counters) (void)hipHostFree(h_counters);
+    if (ready) (void)hipEventDestroy(ready);
 }
 
 static constexpr size_t VIEW_TABLE_BYTES = sizeof(FrameHeader) + sizeof(ViewDesc) * MAX_VIEWS;
@@ -453,8 +454,8 @@ int enqueue_backward(Frame &F, const cs_scene *sc, const cs_grads *g, const Rend
                       F.records, ra, F.pixstate, F.acc);
     tm.end(CS_STAGE_RENDER_BWD);
     tm.begin();
-    launch_preprocess_bwd(st, sc->n, F.V, F.K, F.deg, sc->points, sc->delta, sc->sigma, sc->sh, F.d_frame, F.hullpk,
-                          F.acc, g->points, g->delta, g->sigma, g->opacity, g->sh);
+    launch_preprocess_bwd(st, sc->n, F.V, F.K, F.deg, sc->points, sc->delta, sc->sigma, sc->sh, F.d_frame, F.records,
+                          F.hullpk, F.acc, g->points, g->delta, g->sigma, g->opacity, g->sh);
     tm.end(CS_STAGE_PREPROCESS_BWD);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(CS_EHIP, "kernel launch: %s", hipGetErrorString(e));
@@ -504,6 +505,50 @@ uint64_t scene_key(const cs_scene *sc, int V, const Knobs &kn, const RenderArgs 
     std::memcpy(bits, &ra, sizeof(float) * 5);
     for (uint32_t b : bits) h = mix(h, b);
     return h;
+}
+
+// An eager frame for (n, K, deg, V) with at least the given tile and pixel
+// capacity: a cached one when available (ordered after its last use), else new.
+int acquire_frame(cs_ctx *ctx, int n, int K, int deg, int V, size_t tiles, size_t pix, hipStream_t st, Frame **out)
+{
+    for (size_t i = 0; i < ctx->free_frames.size(); ++i) {
+        Frame *F = ctx->free_frames[i];
+        if (F->n == n && F->K == K && F->deg == deg && F->V == V && F->cap_tiles >= tiles && F->cap_pix >= pix &&
+            F->cap_tiles <= 4 * std::max<size_t>(tiles, 1)) {
+            ctx->free_frames.erase(ctx->free_frames.begin() + i);
+            if (F->ready) (void)hipStreamWaitEvent(st, F->ready, 0);
+            F->st = st;
+            *out = F;
+            return CS_OK;
+        }
+    }
+    Frame *F = new Frame;
+    int r = F->init(n, K, deg, V, tiles, pix, st, &ctx->ring);
+    if (r) {
+        delete F;
+        return r;
+    }
+    *out = F;
+    return CS_OK;
+}
+
+void release_frame(cs_ctx *ctx, Frame *F)
+{
+    if (!F) return;
+    if (!F->ready && hipEventCreateWithFlags(&F->ready, hipEventDisableTiming) != hipSuccess) {
+        delete F;
+        return;
+    }
+    (void)hipEventRecord(F->ready, F->st);
+    // the cache must not outlive the caller's stream: later users order on the event
+    F->st = nullptr;
+    ctx->free_frames.push_back(F);
+    while (ctx->free_frames.size() > 4) {
+        Frame *old = ctx->free_frames.front();
+        if (old->ready) (void)hipEventSynchronize(old->ready); // its last stream may not order with the null stream
+        delete old;
+        ctx->free_frames.erase(ctx->free_frames.begin());
+    }
 }
 
 int check_grads(const cs_scene *sc, const cs_grads *g)
@@ -569,7 +614,14 @@ int cs_destroy(cs_ctx *ctx)
     if (ctx->server) cs_serve_stop(ctx);
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    // everything has completed: free on the null stream, whatever became of the callers' streams
+    if (ctx->batch) ctx->batch->st = nullptr;
     delete ctx->batch;
+    for (Frame *F : ctx->free_frames) {
+        F->st = nullptr;
+        delete F;
+    }
+    ctx->free_frames.clear();
     (void)hipDeviceSynchronize();
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     for (auto &p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
@@ -582,7 +634,10 @@ int cs_state_release(cs_ctx *ctx, cs_fwd_state *s)
 {
     if (!s) return CS_OK;
     if (ctx) (void)hipSetDevice(ctx->device);
-    if (s->owned) delete s->frame;
+    if (s->owned) {
+        if (ctx) release_frame(ctx, s->frame);
+        else delete s->frame;
+    }
     delete s;
     return CS_OK;
 }
@@ -602,9 +657,9 @@ int cs_render_forward(cs_ctx *ctx, const cs_scene *sc, const cs_camera *cam, con
     hipStream_t st = (hipStream_t)hip_stream;
     ViewPlan vp;
     CS_TRY(plan_views(1, cam, kn.tile, &out_rgb, nullptr, vp));
-    Frame *F = new Frame;
-    int r = F->init(sc->n, sc->k, sc->sh_degree, 1, vp.hdr.total_tiles, (size_t)vp.hdr.total_pix, st, &ctx->ring);
-    if (!r) r = F->upload_views(vp.hdr, vp.views.data());
+    Frame *F = nullptr;
+    CS_TRY(acquire_frame(ctx, sc->n, sc->k, sc->sh_degree, 1, vp.hdr.total_tiles, (size_t)vp.hdr.total_pix, st, &F));
+    int r = F->upload_views(vp.hdr, vp.views.data());
     StageTimer tm(ctx, st, prm && (prm->flags & CS_FLAG_TIMING));
     if (!r) r = enqueue_forward(ctx, *F, sc, ra, kn, false, 1.0, tm);
     if (r) {
@@ -618,7 +673,7 @@ int cs_render_forward(cs_ctx *ctx, const cs_scene *sc, const cs_camera *cam, con
         s->nviews = 1;
         *state_out = s;
     } else {
-        delete F;
+        release_frame(ctx, F);
     }
     return CS_OK;
 }
@@ -665,10 +720,11 @@ int cs_render_forward_batch(cs_ctx *ctx, const cs_scene *sc, int32_t n_views, co
     CS_TRY(plan_views(n_views, cams, kn.tile, out_rgb, nullptr, vp));
     StageTimer tm(ctx, st, (flags & CS_FLAG_TIMING) != 0);
 
-    if (!(flags & CS_FLAG_GRAPH)) { // eager: exact buffers owned by the state
-        Frame *F = new Frame;
-        int r = F->init(sc->n, sc->k, sc->sh_degree, n_views, vp.hdr.total_tiles, (size_t)vp.hdr.total_pix, st, &ctx->ring);
-        if (!r) r = F->upload_views(vp.hdr, vp.views.data());
+    if (!(flags & CS_FLAG_GRAPH)) { // eager: buffers owned by the state (cached by the context after it)
+        Frame *F = nullptr;
+        CS_TRY(acquire_frame(ctx, sc->n, sc->k, sc->sh_degree, n_views, vp.hdr.total_tiles,
+                             (size_t)vp.hdr.total_pix, st, &F));
+        int r = F->upload_views(vp.hdr, vp.views.data());
         if (!r) r = enqueue_forward(ctx, *F, sc, ra, kn, false, 1.0, tm);
         if (r) { delete F; return r; }
         if (state_out) {
@@ -677,7 +733,7 @@ int cs_render_forward_batch(cs_ctx *ctx, const cs_scene *sc, int32_t n_views, co
             s->nviews = n_views;
             *state_out = s;
         } else {
-            delete F;
+            release_frame(ctx, F);
         }
         return CS_OK;
     }

@@ -64,6 +64,7 @@ struct Frame {
     uint64_t epoch = 0;
 
     HostRing *ring = nullptr;
+    hipEvent_t ready = nullptr; // recorded when the frame is handed back to the context's cache
 
     int init(int n, int K, int deg, int V, size_t tiles, size_t pix, hipStream_t st, HostRing *ring);
     int init_async_readback();
@@ -96,6 +97,8 @@ struct cs_ctx {
     std::map<std::tuple<int, int, int, int, int>, cs_tuning> tune;
     // request loop (serve.hip)
     cs::Server *server = nullptr;
+    // frames of finished eager calls, reused by later ones
+    std::vector<cs::Frame *> free_frames;
 };
 
 struct cs_fwd_state {

@@ -163,8 +163,9 @@ struct Server {
             cv_done.notify_all();
             cv_work.notify_all();
         }
-        if (st) (void)hipStreamDestroy(st);
+        // the context's cached frames were last used on st: free them before st goes
         if (ctx) cs_destroy(ctx);
+        if (st) (void)hipStreamDestroy(st);
     }
 };
 
