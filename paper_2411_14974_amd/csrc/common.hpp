@@ -26,7 +26,9 @@ struct RecHeader {
     float rgb[3];
     int32_t T;        // number of hull lines
     int32_t id;       // convex index
-    int32_t pad[6];
+    uint32_t box_u;   // pixel columns u0 | u1 << 16 (inclusive) where alpha can reach eps
+    uint32_t box_v;   // pixel rows    v0 | v1 << 16
+    int32_t pad[4];
 };
 static_assert(sizeof(RecHeader) == 64, "record header is 64 bytes");
 

@@ -218,12 +218,10 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
             h.rgb[0] = rgb[0]; h.rgb[1] = rgb[1]; h.rgb[2] = rgb[2];
             h.T = T;
             h.id = (int32_t)inst;
+            h.box_u = 1u; // empty until the cut-off rectangle is known
+            h.box_v = 1u;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) h.pad[q] = 0;
-            const uint4 *hs = reinterpret_cast<const uint4 *>(&h);
-            uint4 *hd = reinterpret_cast<uint4 *>(rec);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) hd[q] = hs[q];
+            for (int q = 0; q < 4; ++q) h.pad[q] = 0;
 
             if (faint) {
                 status = ST_FAINT;
@@ -248,8 +246,14 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
                 if (u0 <= u1 && v0 <= v1) {
                     tx0 = u0 / ra.tile; tx1 = u1 / ra.tile;
                     ty0 = v0 / ra.tile; ty1 = v1 / ra.tile;
+                    h.box_u = (uint32_t)u0 | ((uint32_t)u1 << 16);
+                    h.box_v = (uint32_t)v0 | ((uint32_t)v1 << 16);
                 }
             }
+            const uint4 *hs = reinterpret_cast<const uint4 *>(&h);
+            uint4 *hd = reinterpret_cast<uint4 *>(rec);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) hd[q] = hs[q];
         }
     }
 

@@ -17,7 +17,7 @@
 // The backward kernel walks the same lists back to front from each pixel's
 // last contributor, recomputing alpha with the same function (bit-identical
 // decisions), recovering T_n = T_{n+1} / (1 - alpha_n); the per-pair gradients
-// are reduced over the wavefront (DPP), summed over the workgroup's waves in
+// are reduced over each 16-lane row (DPP), summed over the workgroup's rows in
 // LDS, and leave as one float atomic add per (convex, value) and workgroup.
 #include <algorithm>
 #include <mutex>
@@ -81,29 +81,36 @@ __device__ __forceinline__ bool eval_pair(const uint8_t *rec, float pxf, float p
     return true;
 }
 
-// Sums of NV values over the 64 lanes; lane q (q < NV) receives the sum of
-// value q.  The DPP steps run across all values at once (independent chains
-// hide the DPP hazards): quad_perm / half-mirror / mirror give every lane its
-// row sum, row_bcast:15 and row_bcast:31 fold the rows into lane 63.
-template <int NV> __device__ __forceinline__ float wave_sums_to_lanes(float *v, int lane)
+// Row sums: after it every lane of each 16-lane row holds that row's sum of
+// each of the NV values (DPP quad_perm, half-mirror, mirror; run across all
+// values at once so that independent chains hide the DPP hazards).
+template <int NV> __device__ __forceinline__ void row_sums(float *v)
 {
-#define CS_DPP_STEP(CTRL, ROWMASK)                                                                                 \
+#define CS_DPP_STEP(CTRL)                                                                                          \
     _Pragma("unroll") for (int q = 0; q < NV; ++q) v[q] += __int_as_float(                                          \
-        __builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), CTRL, ROWMASK, 0xF, false));
-    CS_DPP_STEP(0xB1, 0xF)  // quad_perm 1,0,3,2
-    CS_DPP_STEP(0x4E, 0xF)  // quad_perm 2,3,0,1
-    CS_DPP_STEP(0x141, 0xF) // row_half_mirror
-    CS_DPP_STEP(0x140, 0xF) // row_mirror
-    CS_DPP_STEP(0x142, 0xA) // row_bcast:15 into rows 1, 3
-    CS_DPP_STEP(0x143, 0xC) // row_bcast:31 into rows 2, 3
+        __builtin_amdgcn_mov_dpp(__float_as_int(v[q]), CTRL, 0xF, 0xF, true));
+    CS_DPP_STEP(0xB1)  // quad_perm 1,0,3,2
+    CS_DPP_STEP(0x4E)  // quad_perm 2,3,0,1
+    CS_DPP_STEP(0x141) // row_half_mirror
+    CS_DPP_STEP(0x140) // row_mirror
 #undef CS_DPP_STEP
-    float mine = 0.0f;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[q]), 63));
-        if (lane == q) mine = s;
-    }
-    return mine;
+}
+
+// Pixel of a thread within its tile: each wavefront covers an 8x8 square
+// (a compact patch: more of its lanes fall inside the same convex than in a
+// 16x4 strip), wavefronts tile the TILE x TILE tile row-major.
+template <int TILE> __device__ __forceinline__ void tile_pixel(int &dx, int &dy)
+{
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    dx = (w % (TILE / 8)) * 8 + (l & 7);
+    dy = (w / (TILE / 8)) * 8 + (l >> 3);
+}
+
+// A pixel's (u, y) lies in the record's box, outside of which alpha < eps.
+__device__ __forceinline__ bool in_box(const RecHeader &h, int u, int y)
+{
+    return u >= (int)(h.box_u & 0xFFFFu) && u <= (int)(h.box_u >> 16) && y >= (int)(h.box_v & 0xFFFFu) &&
+           y <= (int)(h.box_v >> 16);
 }
 
 template <int K, int NT>
@@ -185,7 +192,9 @@ __global__ __launch_bounds__(TILE *TILE) void render_fwd_kernel(
         const int lt = gt - vd.tile_off;
         const int tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
         const int W = vd.cam.W, H = vd.cam.H;
-        const int u = tx * TILE + (threadIdx.x % TILE), y = ty * TILE + (threadIdx.x / TILE);
+        int pdx, pdy;
+        tile_pixel<TILE>(pdx, pdy);
+        const int u = tx * TILE + pdx, y = ty * TILE + pdy;
         const bool inside = u < W && y < H;
         const float pxf = (float)u + 0.5f, pyf = (float)y + 0.5f;
         const uint2 rg = ranges[gt];
@@ -202,6 +211,7 @@ __global__ __launch_bounds__(TILE *TILE) void render_fwd_kernel(
             if (!done) {
                 for (int e = 0; e < cnt; ++e) {
                     const uint8_t *rec = reinterpret_cast<const uint8_t *>(&lds[e * CH]);
+                    if (!in_box(*reinterpret_cast<const RecHeader *>(rec), u, y)) continue;
                     PairEval<K> pe;
                     ++nevals;
                     const bool hit = eval_pair<K>(rec, pxf, pyf, ra.eps_alpha, pe);
@@ -257,15 +267,17 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
     static_assert(NV <= 64, "one lane per reduced value");
     __shared__ uint4 lds[BATCH * CH];
     __shared__ uint32_t s_ids[BATCH];
-    __shared__ float s_acc[BATCH * NV]; // per-entry sums of the block's waves, flushed after each batch
+    // per (entry, row of 16 lanes) sums of the block's waves, flushed after each batch
+    __shared__ float s_acc[BATCH * 4 * NV];
     __shared__ int s_maxn;
     __shared__ uint32_t s_item;
-    for (int c = threadIdx.x; c < BATCH * NV; c += NT) s_acc[c] = 0.0f;
+    for (int c = threadIdx.x; c < BATCH * 4 * NV; c += NT) s_acc[c] = 0.0f;
     const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
     const int nviews = (int)frame->nviews;
     const uint32_t total_tiles = frame->total_tiles;
     const int lane = threadIdx.x & 63;
     int q = blockIdx.x % NUM_QUEUES, tried = 0;
+    static_assert(BATCH <= 64, "LDS budget of the per-row sums");
     for (;;) {
         const uint32_t item = next_item(counters, total_tiles, q, tried, &s_item);
         if (item == 0xFFFFFFFFu) break;
@@ -275,7 +287,9 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
         const int lt = gt - vd.tile_off;
         const int tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
         const int W = vd.cam.W, H = vd.cam.H;
-        const int u = tx * TILE + (threadIdx.x % TILE), y = ty * TILE + (threadIdx.x / TILE);
+        int pdx, pdy;
+        tile_pixel<TILE>(pdx, pdy);
+        const int u = tx * TILE + pdx, y = ty * TILE + pdy;
         const bool inside = u < W && y < H;
         const float pxf = (float)u + 0.5f, pyf = (float)y + 0.5f;
         const int start = (int)ranges[gt].x;
@@ -310,11 +324,12 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
             __syncthreads();
             for (int e = cnt - 1; e >= 0; --e) {
                 const int pos = lo + e;
-                if (!__any(pos < nend)) continue; // wave-uniform
                 const uint8_t *rec = reinterpret_cast<const uint8_t *>(&lds[e * CH]);
                 const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
+                const bool live = pos < nend && in_box(h, u, y);
+                if (!__any(live)) continue; // wave-uniform
                 PairEval<K> pe;
-                const bool contrib = (pos < nend) && eval_pair<K>(rec, pxf, pyf, ra.eps_alpha, pe);
+                const bool contrib = live && eval_pair<K>(rec, pxf, pyf, ra.eps_alpha, pe);
                 if (__ballot(contrib) == 0ull) continue; // wave-uniform
                 float val[NV];
 #pragma unroll
@@ -347,17 +362,22 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
                     B1 = fmaf(pe.alpha, h.rgb[1], pe.oma * B1);
                     B2 = fmaf(pe.alpha, h.rgb[2], pe.oma * B2);
                 }
-                const float mine = wave_sums_to_lanes<NV>(val, lane);
-                if (lane < NV && mine != 0.0f) atomicAdd(&s_acc[e * NV + lane], mine);
+                row_sums<NV>(val);
+                if ((lane & 15) == 0) { // one lane per row adds the row's sums (LDS atomics)
+                    float *dst = &s_acc[(e * 4 + (lane >> 4)) * NV];
+#pragma unroll
+                    for (int qv = 0; qv < NV; ++qv) atomicAdd(dst + qv, val[qv]);
+                }
             }
-            // one global atomic per (entry, value) for the whole block
+            // one global atomic per (entry, value) for the whole workgroup
             __syncthreads();
             for (int c = threadIdx.x; c < cnt * NV; c += NT) {
-                const float a = s_acc[c];
+                const int e = c / NV, qv = c - e * NV;
+                float *src = &s_acc[e * 4 * NV + qv];
+                const float a = (src[0] + src[NV]) + (src[2 * NV] + src[3 * NV]);
                 if (a != 0.0f) {
-                    const int e = c / NV, qv = c - e * NV;
                     unsafeAtomicAdd(&acc[(size_t)s_ids[e] * AS + qv], a);
-                    s_acc[c] = 0.0f;
+                    src[0] = src[NV] = src[2 * NV] = src[3 * NV] = 0.0f;
                 }
             }
         }
@@ -425,7 +445,7 @@ void launch_render_bwd(hipStream_t st, int K, int tile, const FrameHeader *frame
 {
     if (max_items == 0) return;
     CS_DISPATCH_K(K, CS_DISPATCH_TILE(tile, {
-        auto kern = render_bwd_kernel<KK, TT, BB>;
+        auto kern = render_bwd_kernel<KK, TT, 32>;
         const int grid = std::min<int>(persistent_grid(kern, TT * TT), (int)max_items);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(TT * TT), 0, st, frame, order, counters, ranges, ids, records, ra,
                            pixstate, acc);
