@@ -17,8 +17,9 @@
 // The backward kernel walks the same lists back to front from each pixel's
 // last contributor, recomputing alpha with the same function (bit-identical
 // decisions), recovering T_n = T_{n+1} / (1 - alpha_n); the per-pair gradients
-// are reduced over each 16-lane row (DPP), summed over the workgroup's rows in
-// LDS, and leave as one float atomic add per (convex, value) and workgroup.
+// are reduced over the wavefront (lane swaps + DPP), summed over the
+// workgroup's waves in LDS, and leave as one float atomic add per
+// (convex, value) and workgroup.
 #include <algorithm>
 #include <mutex>
 #include <unordered_map>
@@ -96,6 +97,30 @@ template <int NV> __device__ __forceinline__ void row_sums(float *v)
 #undef CS_DPP_STEP
 }
 
+// Whole-wavefront sums of NP values (NP a multiple of 4) by transposition:
+// a 32-lane swap (v_permlane32_swap) pairs value j with value j + NP/2 so that
+// one add leaves the two half-wave sums of j in the lower half and of j + NP/2
+// in the upper half; a 16-lane swap (v_permlane16_swap) does the same between
+// rows; the 16-lane row sums finish.  On return every lane of row r holds in
+// v[j], j < NP/4, the wave's sum of value j + r NP/4: 3 NP/4 + NP adds and
+// swaps where plain row sums would take 4 NP and still leave 4 partial sums.
+template <int NP> __device__ __forceinline__ void wave_sums(float *v)
+{
+    static_assert(NP % 4 == 0, "pad the values to a multiple of 4");
+    constexpr int H = NP / 2, Q = NP / 4;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[j]), __float_as_uint(v[j + H]), false, false);
+        v[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[j]), __float_as_uint(v[j + Q]), false, false);
+        v[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    row_sums<Q>(v);
+}
+
 // Pixel of a thread within its tile: each wavefront covers an 8x8 square
 // (a compact patch: more of its lanes fall inside the same convex than in a
 // 16x4 strip), wavefronts tile the TILE x TILE tile row-major.
@@ -113,15 +138,54 @@ __device__ __forceinline__ bool in_box(const RecHeader &h, int u, int y)
            y <= (int)(h.box_v >> 16);
 }
 
+// Software pipeline of the LDS record batches.  While a batch is composited
+// from LDS, the records of the next batch are in flight into registers and
+// the list ids of the batch after that into a register, so a record load never
+// waits on its id load; one LDS record buffer and two LDS id buffers suffice.
+template <int K, int NT, int BATCH> constexpr int pipe_regs() { return (BATCH * (rec_stride(K) / 16) + NT - 1) / NT; }
+
+// native 16-byte vector (HIP's uint4 is a struct with a union, which keeps a
+// register array of it in scratch)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t pipe_load_id(const uint32_t *__restrict__ ids, int base, int cnt)
+{
+    return (int)threadIdx.x < cnt ? ids[base + threadIdx.x] : 0u;
+}
+
+template <int K, int NT, int NL>
+__device__ __forceinline__ void pipe_load_records(u32x4 (&pre)[NL], const uint32_t *s_ids,
+                                                  const uint8_t *__restrict__ records, int cnt)
+{
+    constexpr int CH = rec_stride(K) / 16;
+    const int last = cnt * CH - 1; // chunks past the batch reload its last chunk (never stored)
+#pragma clang loop unroll(full)
+    for (int r = 0; r < NL; ++r) {
+        const int c = min((int)threadIdx.x + r * NT, last);
+        const int e = c / CH, part = c - e * CH;
+        pre[r] = reinterpret_cast<const u32x4 *>(records + (size_t)s_ids[e] * rec_stride(K))[part];
+    }
+}
+
 template <int K, int NT>
-__device__ __forceinline__ void load_batch(uint4 *lds, const uint32_t *__restrict__ ids,
-                                           const uint8_t *__restrict__ records, int base, int cnt)
+__device__ __forceinline__ void load_records_direct(uint4 *lds, const uint32_t *s_ids, const uint8_t *__restrict__ records,
+                                                    int cnt)
 {
     constexpr int CH = rec_stride(K) / 16;
     for (int c = threadIdx.x; c < cnt * CH; c += NT) {
         const int e = c / CH, part = c - e * CH;
-        const uint32_t id = ids[base + e];
-        lds[c] = reinterpret_cast<const uint4 *>(records + (size_t)id * rec_stride(K))[part];
+        lds[c] = reinterpret_cast<const uint4 *>(records + (size_t)s_ids[e] * rec_stride(K))[part];
+    }
+}
+
+template <int K, int NT, int NL>
+__device__ __forceinline__ void pipe_store_records(const u32x4 (&pre)[NL], uint4 *lds, int cnt)
+{
+    constexpr int CH = rec_stride(K) / 16;
+#pragma clang loop unroll(full)
+    for (int r = 0; r < NL; ++r) {
+        const int c = (int)threadIdx.x + r * NT;
+        if (c < cnt * CH) reinterpret_cast<u32x4 *>(lds)[c] = pre[r];
     }
 }
 
@@ -167,8 +231,10 @@ __device__ __forceinline__ int find_view(const ViewDesc *__restrict__ views, int
 
 } // namespace
 
+// At least 4 wavefronts per SIMD: lets the compiler use up to 128 VGPRs (the
+// record prefetch registers) instead of spilling to reach 8.
 template <int K, int TILE, int BATCH>
-__global__ __launch_bounds__(TILE *TILE) void render_fwd_kernel(
+__global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4))) void render_fwd_kernel(
     const FrameHeader *__restrict__ frame, const uint32_t *__restrict__ order, uint32_t *__restrict__ counters,
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ ids,
     const uint8_t *__restrict__ records, RenderArgs ra, uint2 *__restrict__ pixstate,
@@ -176,8 +242,13 @@ __global__ __launch_bounds__(TILE *TILE) void render_fwd_kernel(
 {
     constexpr int NT = TILE * TILE;
     constexpr int CH = rec_stride(K) / 16;
+    static_assert(BATCH <= NT, "one id per thread");
     __shared__ uint4 lds[BATCH * CH];
+    __shared__ uint32_t s_ids[2][BATCH];
     __shared__ uint32_t s_item;
+    constexpr int NL = pipe_regs<K, NT, BATCH>();
+    u32x4 pre[NL];
+    uint32_t idr = 0;
     const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
     const int nviews = (int)frame->nviews;
     const uint32_t total_tiles = frame->total_tiles;
@@ -203,11 +274,23 @@ __global__ __launch_bounds__(TILE *TILE) void render_fwd_kernel(
         float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, Tlast = 1.0f;
         int nend = 0;
         bool done = !inside;
-        for (int base = start; base < end; base += BATCH) {
+        const int nb = (end - start + BATCH - 1) / BATCH;
+        if (nb > 0) { // prologue: ids of batches 0 and 1, records of batch 0
+            idr = pipe_load_id(ids, start, min(BATCH, end - start));
+            if ((int)threadIdx.x < BATCH) s_ids[0][threadIdx.x] = idr;
+            if (nb > 1) idr = pipe_load_id(ids, start + BATCH, min(BATCH, end - start - BATCH));
+            __syncthreads();
+            pipe_load_records<K, NT, NL>(pre, s_ids[0], records, min(BATCH, end - start));
+        }
+        for (int bi = 0; bi < nb; ++bi) {
+            const int base = start + bi * BATCH;
             const int cnt = min(BATCH, end - base);
             __syncthreads();
-            load_batch<K, NT>(lds, ids, records, base, cnt);
+            pipe_store_records<K, NT, NL>(pre, lds, cnt);
+            if ((int)threadIdx.x < BATCH) s_ids[(bi + 1) & 1][threadIdx.x] = idr;
             __syncthreads();
+            if (bi + 2 < nb) idr = pipe_load_id(ids, base + 2 * BATCH, min(BATCH, end - base - 2 * BATCH));
+            if (bi + 1 < nb) pipe_load_records<K, NT, NL>(pre, s_ids[(bi + 1) & 1], records, min(BATCH, end - base - BATCH));
             if (!done) {
                 for (int e = 0; e < cnt; ++e) {
                     const uint8_t *rec = reinterpret_cast<const uint8_t *>(&lds[e * CH]);
@@ -264,20 +347,21 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
     constexpr int CH = rec_stride(K) / 16;
     constexpr int NV = acc_values(K); // a[K] b[K] c[K] sigma' o rgb[3] x2-weighted sum
     constexpr int AS = acc_stride(K);
-    static_assert(NV <= 64, "one lane per reduced value");
+    constexpr int NP = (NV + 3) & ~3; // padded for the wave sums
+    constexpr int Q = NP / 4;
+    static_assert(BATCH <= NT, "one id per thread");
     __shared__ uint4 lds[BATCH * CH];
     __shared__ uint32_t s_ids[BATCH];
-    // per (entry, row of 16 lanes) sums of the block's waves, flushed after each batch
-    __shared__ float s_acc[BATCH * 4 * NV];
+    // per entry sums of the block's waves, flushed after each batch
+    __shared__ float s_acc[BATCH * NP];
     __shared__ int s_maxn;
     __shared__ uint32_t s_item;
-    for (int c = threadIdx.x; c < BATCH * 4 * NV; c += NT) s_acc[c] = 0.0f;
+    for (int c = threadIdx.x; c < BATCH * NP; c += NT) s_acc[c] = 0.0f;
     const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
     const int nviews = (int)frame->nviews;
     const uint32_t total_tiles = frame->total_tiles;
     const int lane = threadIdx.x & 63;
     int q = blockIdx.x % NUM_QUEUES, tried = 0;
-    static_assert(BATCH <= 64, "LDS budget of the per-row sums");
     for (;;) {
         const uint32_t item = next_item(counters, total_tiles, q, tried, &s_item);
         if (item == 0xFFFFFFFFu) break;
@@ -315,12 +399,16 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
         float B0 = ra.bg[0], B1 = ra.bg[1], B2 = ra.bg[2];
         float Tcur = Tlast;
         bool first = true;
+        // batches walk the list back to front (the walk is VALU-bound: plain loads,
+        // no prefetch registers)
         for (int hi = maxn; hi > 0; hi -= BATCH) {
             const int lo = max(hi - BATCH, 0);
             const int cnt = hi - lo;
+            uint32_t *cur_ids = s_ids;
             __syncthreads();
-            load_batch<K, NT>(lds, ids, records, start + lo, cnt);
-            for (int c = threadIdx.x; c < cnt; c += NT) s_ids[c] = ids[start + lo + c];
+            if ((int)threadIdx.x < cnt) cur_ids[threadIdx.x] = ids[start + lo + threadIdx.x];
+            __syncthreads();
+            load_records_direct<K, NT>(lds, cur_ids, records, cnt);
             __syncthreads();
             for (int e = cnt - 1; e >= 0; --e) {
                 const int pos = lo + e;
@@ -331,9 +419,9 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
                 PairEval<K> pe;
                 const bool contrib = live && eval_pair<K>(rec, pxf, pyf, ra.eps_alpha, pe);
                 if (__ballot(contrib) == 0ull) continue; // wave-uniform
-                float val[NV];
+                float val[NP];
 #pragma unroll
-                for (int qv = 0; qv < NV; ++qv) val[qv] = 0.0f;
+                for (int qv = 0; qv < NP; ++qv) val[qv] = 0.0f;
                 if (contrib) {
                     const float Tn = first ? Tlast : Tcur / pe.oma;
                     first = false;
@@ -362,22 +450,22 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
                     B1 = fmaf(pe.alpha, h.rgb[1], pe.oma * B1);
                     B2 = fmaf(pe.alpha, h.rgb[2], pe.oma * B2);
                 }
-                row_sums<NV>(val);
-                if ((lane & 15) == 0) { // one lane per row adds the row's sums (LDS atomics)
-                    float *dst = &s_acc[(e * 4 + (lane >> 4)) * NV];
+                wave_sums<NP>(val);
+                if ((lane & 15) == 0) { // one lane per row adds its quarter of the wave's sums
+                    float *dst = &s_acc[e * NP + (lane >> 4) * Q];
 #pragma unroll
-                    for (int qv = 0; qv < NV; ++qv) atomicAdd(dst + qv, val[qv]);
+                    for (int qv = 0; qv < Q; ++qv) atomicAdd(dst + qv, val[qv]);
                 }
             }
             // one global atomic per (entry, value) for the whole workgroup
             __syncthreads();
             for (int c = threadIdx.x; c < cnt * NV; c += NT) {
                 const int e = c / NV, qv = c - e * NV;
-                float *src = &s_acc[e * 4 * NV + qv];
-                const float a = (src[0] + src[NV]) + (src[2 * NV] + src[3 * NV]);
+                float *src = &s_acc[e * NP + qv];
+                const float a = *src;
                 if (a != 0.0f) {
-                    unsafeAtomicAdd(&acc[(size_t)s_ids[e] * AS + qv], a);
-                    src[0] = src[NV] = src[2 * NV] = src[3 * NV] = 0.0f;
+                    unsafeAtomicAdd(&acc[(size_t)cur_ids[e] * AS + qv], a);
+                    *src = 0.0f;
                 }
             }
         }

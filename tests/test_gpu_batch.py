@@ -37,14 +37,20 @@ def dev(scene):
     return DeviceScene.from_scene(scene, "cuda:0")
 
 
-def grads_close(a, b, tol=1e-4):
-    """Two float-atomic sums of the same terms: close in norm, and per element
-    relative to max(|b|, 1e-2 rms(b))."""
+def grad_gap(a, b):
+    """(relative L2 gap, worst element gap relative to max(|b|, 1e-2 rms(b)))."""
     a = a.detach().double().cpu().numpy().ravel()
     b = b.detach().double().cpu().numpy().ravel()
     rms = np.sqrt(np.mean(b * b)) if b.size else 0.0
-    return (np.linalg.norm(a - b) <= tol * 0.1 * max(np.linalg.norm(b), 1e-300)
-            and np.all(np.abs(a - b) <= tol * np.maximum(np.abs(b), 1e-2 * rms)))
+    return (float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)),
+            float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-2 * rms + 1e-300))) if b.size else 0.0)
+
+
+def grads_close(a, b, tol=1e-3):
+    """Two float-atomic sums of the same terms in different orders: within the
+    parity tolerance per element (floor 1e-2 rms) and 1e-5 in norm."""
+    rel, worst = grad_gap(a, b)
+    return rel <= 1e-5 and worst <= tol
 
 
 def small_batch(n=20000, views=5, seed=0, res=((200, 120), (97, 61), (256, 144))):
@@ -154,8 +160,15 @@ def test_graph_replay_matches_eager_with_changing_cameras(R):
         torch.cuda.synchronize()
         for a, b in zip(outs, ref_outs):
             assert torch.equal(a, b), rep
+        # two eager runs: the size of summation-order noise alone
+        ref_outs2, st3 = R.forward_batch(ds, cams, make_params(), want_state=True)
+        g3 = R.backward_batch(st3, dls)
+        torch.cuda.synchronize()
         for k in NAMES:
-            assert grads_close(grads[k], g2[k]), (rep, k)
+            say(f"[graph rep {rep}] {k}: graph vs eager {grad_gap(grads[k], g2[k])}, "
+                f"eager vs eager {grad_gap(g3[k], g2[k])}")
+            assert grads_close(grads[k], g2[k]), (rep, k, grad_gap(grads[k], g2[k]))
+        st3.release()
         assert R.batch_check(st) == 0
         st.release()
         st2.release()
