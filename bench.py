@@ -45,7 +45,7 @@ def workload(name):
 def stage_work(stage, n, m, K, T_mean, deg, stats, npix):
     """Algorithmic bytes (or VALU lane-ops) of one launch of a stage."""
     nc = (deg + 1) ** 2
-    rec = 64 + 24 * T_mean
+    rec = 48 + 24 * T_mean  # header + the T hull lines written
     if stage == "preprocess":  # read points, delta, sigma, opacity, SH; write record, key, id, rect, count, hull
         return "hbm", n * (12 * K + 12 + 12 * nc + rec + 4 + 4 + 8 + 4 + 4)
     if stage == "depth_sort":  # 4 passes x (histogram read 4 B + scatter read 8 B + write 8 B)

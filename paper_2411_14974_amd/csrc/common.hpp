@@ -28,11 +28,12 @@ struct RecHeader {
     int32_t id;       // convex index
     uint32_t box_u;   // pixel columns u0 | u1 << 16 (inclusive) where alpha can reach eps
     uint32_t box_v;   // pixel rows    v0 | v1 << 16
-    int32_t pad[4];
 };
-static_assert(sizeof(RecHeader) == 64, "record header is 64 bytes");
+// the K lines (three doubles each) follow the header
+constexpr int REC_HEADER = 48;
+static_assert(sizeof(RecHeader) == REC_HEADER, "record header is 48 bytes");
 
-__host__ __device__ constexpr int rec_stride(int K) { return (64 + 24 * K + 15) & ~15; }
+__host__ __device__ constexpr int rec_stride(int K) { return (REC_HEADER + 24 * K + 15) & ~15; }
 // accumulator slots per convex for the backward pass:
 //   a[K] b[K] c[K]  (base-2 line coefficients), sigma', opacity, rgb[3], and
 //   sum_j dL/dx2_j * x2_j  (= delta' dL/ddelta', accumulated per pair because

@@ -38,29 +38,46 @@ __device__ __forceinline__ void pixel_span(double a, double b, int n, int &lo, i
 
 } // namespace
 
-template <int K>
-__global__ __launch_bounds__(256) void preprocess_fwd_kernel(
+constexpr int PF_BLOCK = 256;
+
+// DBG: also fill the per-instance debug record (a separate instantiation, so
+// that the debug copies of the lines cost no registers in the plain one).
+template <int K, bool DBG>
+__global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
     int n, int deg, const float *__restrict__ points, const float *__restrict__ delta,
     const float *__restrict__ sigma, const float *__restrict__ opacity, const float *__restrict__ sh,
     const FrameHeader *__restrict__ frame, RenderArgs ra, uint8_t *__restrict__ records, uint32_t *__restrict__ keys,
     uint32_t *__restrict__ ids, uint2 *__restrict__ rects, uint32_t *__restrict__ counts,
     uint32_t *__restrict__ hullpk, DebugConvex *__restrict__ dbg)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // the block's points arrive through LDS (coalesced loads; odd row stride)
+    constexpr int PS = 3 * K + 1;
+    __shared__ float s_pts[PF_BLOCK * PS];
+    const int base = blockIdx.x * PF_BLOCK;
+    const int cnt = min(PF_BLOCK, n - base);
+    {
+        const float *g = points + (size_t)base * 3 * K;
+        for (int j = threadIdx.x; j < cnt * 3 * K; j += PF_BLOCK) s_pts[(j / (3 * K)) * PS + j % (3 * K)] = g[j];
+    }
+    __syncthreads();
+    const int i = base + threadIdx.x;
     if (i >= n) return;
     // one (view, convex) instance per thread; all outputs are indexed by the instance
     const CamArgs cam = reinterpret_cast<const ViewDesc *>(frame + 1)[blockIdx.y].cam;
     const size_t inst = (size_t)blockIdx.y * n + i;
     ids[inst] = (uint32_t)inst;
 
-    const float *p = points + (size_t)i * K * 3;
     float px[K], py[K], pz[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        px[k] = p[3 * k];
-        py[k] = p[3 * k + 1];
-        pz[k] = p[3 * k + 2];
+        px[k] = s_pts[threadIdx.x * PS + 3 * k];
+        py[k] = s_pts[threadIdx.x * PS + 3 * k + 1];
+        pz[k] = s_pts[threadIdx.x * PS + 3 * k + 2];
     }
+    // point centroid (for the SH view direction), taken now so the points can retire early
+    double cxw = 0, cyw = 0, czw = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) { cxw += px[k]; cyw += py[k]; czw += pz[k]; }
 
     // float32 depth key: each Z_k as an fma chain, summed in point order
     float zsum = 0.0f;
@@ -80,7 +97,7 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
     double dd = 0.0, dp = 0.0, sp = 0.0;
     float rgb[3] = {0.f, 0.f, 0.f};
     int clampmask = 0;
-    double lineA[K], lineB[K], lineC[K]; // debug copy (unscaled, absolute pixel frame)
+    double lineA[DBG ? K : 1], lineB[DBG ? K : 1], lineC[DBG ? K : 1]; // debug copy (unscaled, absolute pixel frame)
 
     if (near) {
         status = ST_NEAR;
@@ -115,7 +132,11 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
         const double ox = rint(sx), oy = rint(sy);
         const double s2 = dp * LOG2E;
         uint8_t *rec = records + inst * rec_stride(K);
-        double *lines = reinterpret_cast<double *>(rec + 64);
+        // the lines leave as aligned pairs of doubles (16-byte stores): line j
+        // occupies doubles 3j..3j+2 after the header; an odd line's first value
+        // waits in `carry` for the even line's last one
+        double2 *lines2 = reinterpret_cast<double2 *>(rec + REC_HEADER);
+        double carry = 0.0;
 
         // cut-off radius: outside { L_j <= r for all j } alpha < eps_alpha
         const double eps = (double)ra.eps_alpha;
@@ -154,12 +175,18 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
             const double Cabs = -(A * cxp + B * cyp);
             const double Crel = -(A * (cxp - ox) + B * (cyp - oy));
             const int j = T - 1;
-            lines[3 * j + 0] = s2 * A;
-            lines[3 * j + 1] = s2 * B;
-            lines[3 * j + 2] = s2 * Crel;
+            if ((j & 1) == 0) {
+                lines2[(3 * j) >> 1] = make_double2(s2 * A, s2 * B);
+                carry = s2 * Crel;
+            } else {
+                lines2[(3 * j - 1) >> 1] = make_double2(carry, s2 * A);
+                lines2[(3 * j + 1) >> 1] = make_double2(s2 * B, s2 * Crel);
+            }
+            if constexpr (DBG) {
 #pragma unroll
-            for (int jj = 0; jj < K; ++jj)
-                if (jj == j) { lineA[jj] = A; lineB[jj] = B; lineC[jj] = Cabs; }
+                for (int jj = 0; jj < K; ++jj)
+                    if (jj == j) { lineA[jj] = A; lineB[jj] = B; lineC[jj] = Cabs; }
+            }
             // corner of the pushed-out polygon at vertex cur (needs the incoming line)
             if (j == 0) {
                 firstA = A; firstB = B; firstC = Cabs;
@@ -175,6 +202,7 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
             cur = nxt; cxp = nxp; cyp = nyp;
         }
         (void)prevC; (void)firstC;
+        if (T & 1) lines2[(3 * T - 1) >> 1] = make_double2(carry, 0.0); // the last line's c
         if (closed && T >= 3) {
             const double den = 1.0 + prevA * firstA + prevB * firstB;
             if (den < 1e-6) unbounded = true;
@@ -187,9 +215,6 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
             status = ST_HULL;
         } else {
             // colour from SH at the direction camera -> point centroid
-            double cxw = 0, cyw = 0, czw = 0;
-#pragma unroll
-            for (int k = 0; k < K; ++k) { cxw += px[k]; cyw += py[k]; czw += pz[k]; }
             const double vx = cxw / K - cam.campos[0], vy = cyw / K - cam.campos[1], vz = czw / K - cam.campos[2];
             const double inv = 1.0 / sqrt(vx * vx + vy * vy + vz * vz);
             float Yb[16];
@@ -197,10 +222,24 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
             const int nc = (deg + 1) * (deg + 1);
             const float *f = sh + (size_t)i * nc * 3;
             float raw[3] = {0.5f, 0.5f, 0.5f};
-            for (int c = 0; c < nc; ++c) {
-                raw[0] = fmaf(Yb[c], f[3 * c + 0], raw[0]);
-                raw[1] = fmaf(Yb[c], f[3 * c + 1], raw[1]);
-                raw[2] = fmaf(Yb[c], f[3 * c + 2], raw[2]);
+            if (deg == 3) { // 192-byte rows: 16-byte loads, same summation order
+                const float4 *f4 = reinterpret_cast<const float4 *>(f);
+#pragma unroll
+                for (int q = 0; q < 12; ++q) {
+                    const float4 w = f4[q];
+                    const float wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int e = 4 * q + t; // coefficient e / 3, channel e % 3
+                        raw[e % 3] = fmaf(Yb[e / 3], wv[t], raw[e % 3]);
+                    }
+                }
+            } else {
+                for (int c = 0; c < nc; ++c) {
+                    raw[0] = fmaf(Yb[c], f[3 * c + 0], raw[0]);
+                    raw[1] = fmaf(Yb[c], f[3 * c + 1], raw[1]);
+                    raw[2] = fmaf(Yb[c], f[3 * c + 2], raw[2]);
+                }
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -220,8 +259,6 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
             h.id = (int32_t)inst;
             h.box_u = 1u; // empty until the cut-off rectangle is known
             h.box_v = 1u;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) h.pad[q] = 0;
 
             if (faint) {
                 status = ST_FAINT;
@@ -253,7 +290,7 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
             const uint4 *hs = reinterpret_cast<const uint4 *>(&h);
             uint4 *hd = reinterpret_cast<uint4 *>(rec);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) hd[q] = hs[q];
+            for (int q = 0; q < REC_HEADER / 16; ++q) hd[q] = hs[q];
         }
     }
 
@@ -264,7 +301,7 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
                          : make_uint2(1u, 0u);
     hullpk[inst] = (status == ST_VISIBLE || status == ST_FAINT) ? (packed | ((uint32_t)T << 28)) : 0u;
 
-    if (dbg) {
+    if constexpr (DBG) {
         DebugConvex &o = dbg[inst];
         o.status = status;
         o.T = (status == ST_NEAR) ? 0 : T;
@@ -300,9 +337,16 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(
 template <int K>
 __device__ __forceinline__ void view_backward(int deg, const float *px, const float *py, const float *pz, float dl,
                                               float sg, const float *f, const CamArgs &cam, uint32_t hp,
-                                              const RecHeader &hdr, const float *__restrict__ A, float *gp,
+                                              const RecHeader &hdr, const float *__restrict__ Ag, float *gp,
                                               float &gdelta, float &gsigma, float &gopac, float *gsh)
 {
+    // the instance's accumulator row, in 16-byte loads
+    float A[acc_stride(K)];
+#pragma unroll
+    for (int q = 0; q < acc_stride(K) / 4; ++q) {
+        const float4 w = reinterpret_cast<const float4 *>(Ag)[q];
+        A[4 * q] = w.x; A[4 * q + 1] = w.y; A[4 * q + 2] = w.z; A[4 * q + 3] = w.w;
+    }
     const int T = (int)(hp >> 28);
     const int nc = (deg + 1) * (deg + 1);
     const double r0 = cam.R[0], r1 = cam.R[1], r2 = cam.R[2], r3 = cam.R[3], r4 = cam.R[4], r5 = cam.R[5];
@@ -399,10 +443,21 @@ __device__ __forceinline__ void view_backward(int deg, const float *px, const fl
     float Yb[16];
     sh_eval(deg, dx, dy, dz, Yb);
     float raw[3] = {0.5f, 0.5f, 0.5f};
-    for (int c = 0; c < nc; ++c) {
-        raw[0] = fmaf(Yb[c], f[3 * c + 0], raw[0]);
-        raw[1] = fmaf(Yb[c], f[3 * c + 1], raw[1]);
-        raw[2] = fmaf(Yb[c], f[3 * c + 2], raw[2]);
+    const float4 *f4 = reinterpret_cast<const float4 *>(f); // degree 3: 192-byte rows, 16-byte loads
+    if (deg == 3) {
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            const float4 w = f4[q];
+            const float wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) raw[(4 * q + t) % 3] = fmaf(Yb[(4 * q + t) / 3], wv[t], raw[(4 * q + t) % 3]);
+        }
+    } else {
+        for (int c = 0; c < nc; ++c) {
+            raw[0] = fmaf(Yb[c], f[3 * c + 0], raw[0]);
+            raw[1] = fmaf(Yb[c], f[3 * c + 1], raw[1]);
+            raw[2] = fmaf(Yb[c], f[3 * c + 2], raw[2]);
+        }
     }
     float graw[3];
 #pragma unroll
@@ -412,7 +467,23 @@ __device__ __forceinline__ void view_backward(int deg, const float *px, const fl
         gsh[3 * c + 0] += graw[0] * Yb[c];
         gsh[3 * c + 1] += graw[1] * Yb[c];
         gsh[3 * c + 2] += graw[2] * Yb[c];
-        wsum[c] = graw[0] * f[3 * c + 0] + graw[1] * f[3 * c + 1] + graw[2] * f[3 * c + 2];
+    }
+    if (deg == 3) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) wsum[c] = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) { // wsum_c = sum_k graw_k f_ck, same order as below
+            const float4 w = f4[q];
+            const float wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int e = 4 * q + t;
+                wsum[e / 3] = (e % 3 == 0) ? graw[0] * wv[t] : wsum[e / 3] + graw[e % 3] * wv[t];
+            }
+        }
+    } else {
+        for (int c = 0; c < nc; ++c)
+            wsum[c] = graw[0] * f[3 * c + 0] + graw[1] * f[3 * c + 1] + graw[2] * f[3 * c + 2];
     }
     float gdx = 0.f, gdy = 0.f, gdz = 0.f;
     sh_grad_dot(deg, dx, dy, dz, wsum, gdx, gdy, gdz);
@@ -536,9 +607,15 @@ void launch_preprocess_fwd(hipStream_t st, int n, int nviews, int K, int deg, co
                            uint32_t *ids, uint2 *rects, uint32_t *counts, uint32_t *hullpk, DebugConvex *dbg)
 {
     if (n <= 0 || nviews <= 0) return;
-    dim3 grid((n + 255) / 256, nviews), block(256);
-    CS_DISPATCH_K(K, hipLaunchKernelGGL(preprocess_fwd_kernel<KK>, grid, block, 0, st, n, deg, points, delta, sigma,
-                                        opacity, sh, views, ra, records, keys, ids, rects, counts, hullpk, dbg));
+    dim3 grid((n + PF_BLOCK - 1) / PF_BLOCK, nviews), block(PF_BLOCK);
+    if (dbg)
+        CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_fwd_kernel<KK, true>), grid, block, 0, st, n, deg, points,
+                                            delta, sigma, opacity, sh, views, ra, records, keys, ids, rects, counts,
+                                            hullpk, dbg))
+    else
+        CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_fwd_kernel<KK, false>), grid, block, 0, st, n, deg, points,
+                                            delta, sigma, opacity, sh, views, ra, records, keys, ids, rects, counts,
+                                            hullpk, dbg))
 }
 
 void launch_preprocess_bwd(hipStream_t st, int n, int nviews, int K, int deg, const float *points,

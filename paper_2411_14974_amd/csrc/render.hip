@@ -43,7 +43,7 @@ template <int K>
 __device__ __forceinline__ bool eval_pair(const uint8_t *rec, float pxf, float pyf, float eps, PairEval<K> &pe)
 {
     const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
-    const double *ln = reinterpret_cast<const double *>(rec + 64);
+    const double *ln = reinterpret_cast<const double *>(rec + REC_HEADER);
     const int T = h.T;
     pe.inv_sum = 0.0f;
     const double dx = (double)(pxf - h.ox), dy = (double)(pyf - h.oy);
@@ -138,6 +138,25 @@ __device__ __forceinline__ bool in_box(const RecHeader &h, int u, int y)
            y <= (int)(h.box_v >> 16);
 }
 
+// Which of the tile's 8x8 wavefront squares (bit w for wave w, numbered as in
+// tile_pixel) a record's pixel box meets.  Computed once per record and batch,
+// so a wavefront walks only the records that can touch one of its pixels.
+template <int TILE> __device__ __forceinline__ uint32_t wave_mask(uint32_t box_u, uint32_t box_v, int tu, int tv)
+{
+    constexpr int WX = TILE / 8;
+    const int u0 = (int)(box_u & 0xFFFFu) - tu, u1 = (int)(box_u >> 16) - tu;
+    const int v0 = (int)(box_v & 0xFFFFu) - tv, v1 = (int)(box_v >> 16) - tv;
+    if (u1 < 0 || v1 < 0 || u0 >= TILE || v0 >= TILE || u0 > u1 || v0 > v1) return 0u;
+    const int cx0 = max(u0, 0) >> 3, cx1 = min(u1, TILE - 1) >> 3;
+    const int cy0 = max(v0, 0) >> 3, cy1 = min(v1, TILE - 1) >> 3;
+    const uint32_t cols = ((2u << cx1) - 1u) & ~((1u << cx0) - 1u);
+    uint32_t m = 0u;
+#pragma unroll
+    for (int r = 0; r < WX; ++r)
+        if (r >= cy0 && r <= cy1) m |= cols << (r * WX);
+    return m;
+}
+
 // Software pipeline of the LDS record batches.  While a batch is composited
 // from LDS, the records of the next batch are in flight into registers and
 // the list ids of the batch after that into a register, so a record load never
@@ -167,25 +186,34 @@ __device__ __forceinline__ void pipe_load_records(u32x4 (&pre)[NL], const uint32
     }
 }
 
-template <int K, int NT>
-__device__ __forceinline__ void load_records_direct(uint4 *lds, const uint32_t *s_ids, const uint8_t *__restrict__ records,
-                                                    int cnt)
+template <int K, int TILE>
+__device__ __forceinline__ void load_records_direct(uint4 *lds, uint32_t *s_wmask, const uint32_t *s_ids,
+                                                    const uint8_t *__restrict__ records, int cnt, int tu, int tv)
 {
-    constexpr int CH = rec_stride(K) / 16;
+    constexpr int CH = rec_stride(K) / 16, NT = TILE * TILE;
     for (int c = threadIdx.x; c < cnt * CH; c += NT) {
         const int e = c / CH, part = c - e * CH;
-        lds[c] = reinterpret_cast<const uint4 *>(records + (size_t)s_ids[e] * rec_stride(K))[part];
+        const u32x4 x = reinterpret_cast<const u32x4 *>(records + (size_t)s_ids[e] * rec_stride(K))[part];
+        reinterpret_cast<u32x4 *>(lds)[c] = x;
+        if (part == 2) s_wmask[e] = wave_mask<TILE>(x.z, x.w, tu, tv);
     }
 }
 
-template <int K, int NT, int NL>
-__device__ __forceinline__ void pipe_store_records(const u32x4 (&pre)[NL], uint4 *lds, int cnt)
+// Stores the batch into LDS; the thread holding a record's third chunk
+// (T, id, box_u, box_v) also stores the record's wave mask.
+template <int K, int TILE, int NL>
+__device__ __forceinline__ void pipe_store_records(const u32x4 (&pre)[NL], uint4 *lds, uint32_t *s_wmask, int cnt,
+                                                   int tu, int tv)
 {
-    constexpr int CH = rec_stride(K) / 16;
+    constexpr int CH = rec_stride(K) / 16, NT = TILE * TILE;
 #pragma clang loop unroll(full)
     for (int r = 0; r < NL; ++r) {
         const int c = (int)threadIdx.x + r * NT;
-        if (c < cnt * CH) reinterpret_cast<u32x4 *>(lds)[c] = pre[r];
+        if (c < cnt * CH) {
+            reinterpret_cast<u32x4 *>(lds)[c] = pre[r];
+            const int e = c / CH;
+            if (c - e * CH == 2) s_wmask[e] = wave_mask<TILE>(pre[r].z, pre[r].w, tu, tv);
+        }
     }
 }
 
@@ -243,9 +271,12 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4)))
     constexpr int NT = TILE * TILE;
     constexpr int CH = rec_stride(K) / 16;
     static_assert(BATCH <= NT, "one id per thread");
+    static_assert(BATCH <= 64, "one ballot bit per batch entry");
     __shared__ uint4 lds[BATCH * CH];
     __shared__ uint32_t s_ids[2][BATCH];
+    __shared__ uint32_t s_wmask[BATCH];
     __shared__ uint32_t s_item;
+    const int lane = threadIdx.x & 63, wbit = threadIdx.x >> 6;
     constexpr int NL = pipe_regs<K, NT, BATCH>();
     u32x4 pre[NL];
     uint32_t idr = 0;
@@ -286,30 +317,36 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4)))
             const int base = start + bi * BATCH;
             const int cnt = min(BATCH, end - base);
             __syncthreads();
-            pipe_store_records<K, NT, NL>(pre, lds, cnt);
+            pipe_store_records<K, TILE, NL>(pre, lds, s_wmask, cnt, tx * TILE, ty * TILE);
             if ((int)threadIdx.x < BATCH) s_ids[(bi + 1) & 1][threadIdx.x] = idr;
             __syncthreads();
             if (bi + 2 < nb) idr = pipe_load_id(ids, base + 2 * BATCH, min(BATCH, end - base - 2 * BATCH));
             if (bi + 1 < nb) pipe_load_records<K, NT, NL>(pre, s_ids[(bi + 1) & 1], records, min(BATCH, end - base - BATCH));
-            if (!done) {
-                for (int e = 0; e < cnt; ++e) {
-                    const uint8_t *rec = reinterpret_cast<const uint8_t *>(&lds[e * CH]);
-                    if (!in_box(*reinterpret_cast<const RecHeader *>(rec), u, y)) continue;
+            // the wave's records of this batch, front to back (a wave-uniform walk)
+            uint64_t M = __ballot(lane < cnt && ((s_wmask[min(lane, BATCH - 1)] >> wbit) & 1u));
+            if (__all(done)) M = 0;
+            while (M) {
+                const int e = __builtin_ctzll(M);
+                M &= M - 1;
+                const uint8_t *rec = reinterpret_cast<const uint8_t *>(&lds[e * CH]);
+                const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
+                if (!done && in_box(h, u, y)) {
                     PairEval<K> pe;
                     ++nevals;
                     const bool hit = eval_pair<K>(rec, pxf, pyf, ra.eps_alpha, pe);
                     nfull += pe.inv_sum > 0.0f;
-                    if (!hit) continue;
-                    const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
-                    const float w = T * pe.alpha;
-                    C0 = fmaf(w, h.rgb[0], C0);
-                    C1 = fmaf(w, h.rgb[1], C1);
-                    C2 = fmaf(w, h.rgb[2], C2);
-                    Tlast = T;
-                    T = T * pe.oma;
-                    nend = base - start + e + 1;
-                    if (T < ra.t_min) { done = true; break; }
+                    if (hit) {
+                        const float w = T * pe.alpha;
+                        C0 = fmaf(w, h.rgb[0], C0);
+                        C1 = fmaf(w, h.rgb[1], C1);
+                        C2 = fmaf(w, h.rgb[2], C2);
+                        Tlast = T;
+                        T = T * pe.oma;
+                        nend = base - start + e + 1;
+                        done = T < ra.t_min;
+                    }
                 }
+                if (__all(done)) break;
             }
             if (__syncthreads_and(done)) break;
         }
@@ -350,8 +387,10 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
     constexpr int NP = (NV + 3) & ~3; // padded for the wave sums
     constexpr int Q = NP / 4;
     static_assert(BATCH <= NT, "one id per thread");
+    static_assert(BATCH <= 64, "one ballot bit per batch entry");
     __shared__ uint4 lds[BATCH * CH];
     __shared__ uint32_t s_ids[BATCH];
+    __shared__ uint32_t s_wmask[BATCH];
     // per entry sums of the block's waves, flushed after each batch
     __shared__ float s_acc[BATCH * NP];
     __shared__ int s_maxn;
@@ -360,7 +399,7 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
     const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
     const int nviews = (int)frame->nviews;
     const uint32_t total_tiles = frame->total_tiles;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wbit = threadIdx.x >> 6;
     int q = blockIdx.x % NUM_QUEUES, tried = 0;
     for (;;) {
         const uint32_t item = next_item(counters, total_tiles, q, tried, &s_item);
@@ -395,6 +434,9 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
         if (nend > 0) atomicMax(&s_maxn, nend);
         __syncthreads();
         const int maxn = s_maxn;
+        int wmaxn = nend; // the wave's last contributor
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) wmaxn = max(wmaxn, __shfl_xor(wmaxn, o, 64));
 
         float B0 = ra.bg[0], B1 = ra.bg[1], B2 = ra.bg[2];
         float Tcur = Tlast;
@@ -408,9 +450,13 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
             __syncthreads();
             if ((int)threadIdx.x < cnt) cur_ids[threadIdx.x] = ids[start + lo + threadIdx.x];
             __syncthreads();
-            load_records_direct<K, NT>(lds, cur_ids, records, cnt);
+            load_records_direct<K, TILE>(lds, s_wmask, cur_ids, records, cnt, tx * TILE, ty * TILE);
             __syncthreads();
-            for (int e = cnt - 1; e >= 0; --e) {
+            // the wave's records of this batch before its last contributor, back to front
+            uint64_t M = __ballot(lane < min(cnt, wmaxn - lo) && ((s_wmask[min(lane, BATCH - 1)] >> wbit) & 1u));
+            while (M) {
+                const int e = 63 - __builtin_clzll(M);
+                M &= ~(1ull << e);
                 const int pos = lo + e;
                 const uint8_t *rec = reinterpret_cast<const uint8_t *>(&lds[e * CH]);
                 const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
@@ -450,6 +496,8 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
                     B1 = fmaf(pe.alpha, h.rgb[1], pe.oma * B1);
                     B2 = fmaf(pe.alpha, h.rgb[2], pe.oma * B2);
                 }
+                // whole-wave sums even when few lanes contribute: lane-by-lane
+                // LDS atomics serialise badly when a record covers the square
                 wave_sums<NP>(val);
                 if ((lane & 15) == 0) { // one lane per row adds its quarter of the wave's sums
                     float *dst = &s_acc[e * NP + (lane >> 4) * Q];
@@ -487,9 +535,9 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
 
 #define CS_DISPATCH_TILE(TILEV, ...)                                                                               \
     switch (TILEV) {                                                                                               \
-    case 8: { constexpr int TT = 8; constexpr int BB = 32; __VA_ARGS__; } break;                                   \
-    case 16: { constexpr int TT = 16; constexpr int BB = 64; __VA_ARGS__; } break;                                 \
-    case 32: { constexpr int TT = 32; constexpr int BB = 64; __VA_ARGS__; } break;                                 \
+    case 8: { constexpr int TT = 8, BF = 32, BBW = 32; __VA_ARGS__; } break;                                       \
+    case 16: { constexpr int TT = 16, BF = 32, BBW = 64; __VA_ARGS__; } break;                                     \
+    case 32: { constexpr int TT = 32, BF = 64, BBW = 64; __VA_ARGS__; } break;                                     \
     default: break;                                                                                                \
     }
 
@@ -520,7 +568,7 @@ void launch_render_fwd(hipStream_t st, int K, int tile, const FrameHeader *frame
 {
     if (max_items == 0) return;
     CS_DISPATCH_K(K, CS_DISPATCH_TILE(tile, {
-        auto kern = render_fwd_kernel<KK, TT, BB>;
+        auto kern = render_fwd_kernel<KK, TT, BF>;
         const int grid = std::min<int>(persistent_grid(kern, TT * TT), (int)max_items);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(TT * TT), 0, st, frame, order, counters, ranges, ids, records, ra,
                            pixstate, evalcount);
@@ -533,7 +581,7 @@ void launch_render_bwd(hipStream_t st, int K, int tile, const FrameHeader *frame
 {
     if (max_items == 0) return;
     CS_DISPATCH_K(K, CS_DISPATCH_TILE(tile, {
-        auto kern = render_bwd_kernel<KK, TT, 32>;
+        auto kern = render_bwd_kernel<KK, TT, BBW>;
         const int grid = std::min<int>(persistent_grid(kern, TT * TT), (int)max_items);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(TT * TT), 0, st, frame, order, counters, ranges, ids, records, ra,
                            pixstate, acc);
