@@ -48,14 +48,14 @@ def stage_work(stage, n, m, K, T_mean, deg, stats, npix):
     rec = 48 + 24 * T_mean  # header + the T hull lines written
     if stage == "preprocess":  # read points, delta, sigma, opacity, SH; write record, key, id, rect, count, hull
         return "hbm", n * (12 * K + 12 + 12 * nc + rec + 4 + 4 + 8 + 4 + 4)
-    if stage == "depth_sort":  # 4 passes x (histogram read 4 B + scatter read 8 B + write 8 B)
-        return "hbm", n * 4 * 20
-    if stage == "bin_scan":  # gather: id 4 + count 4 + write 4; scan: read twice 8 + write 4
-        return "hbm", n * 24
+    if stage == "depth_sort":  # one histogram read (4 B) + 4 passes x (read 8 B + write 8 B)
+        return "hbm", n * (4 + 4 * 16)
+    if stage == "bin_scan":  # read id 4 + count 4; write sorted count 4 + offset 4
+        return "hbm", n * 16
     if stage == "emit":  # per convex: id, offset, rect 16 B; per pair: write 8 B
         return "hbm", n * 16 + m * 8
-    if stage == "tile_sort":  # 2 passes of 8-bit digits over the tile id
-        return "hbm", m * 2 * 20
+    if stage == "tile_sort":  # one histogram read (4 B) + 2 passes x (read 8 B + write 8 B) over the pairs
+        return "hbm", m * (4 + 2 * 16)
     if stage == "ranges":
         return "hbm", m * 4
     if stage == "render_fwd":  # per tested pair: 2T DFMA + (T-1) max + 4; full pairs: 7T + 24 (4 per transcendental)

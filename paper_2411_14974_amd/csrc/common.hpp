@@ -82,7 +82,13 @@ constexpr int MAX_VIEWS = 256;
 constexpr int NUM_QUEUES = 8; // one work queue per XCD
 
 // Device counters of one frame (u32 words).
-enum : int { CNT_PAIRS = 0, CNT_PAIRS_EFF = 1, CNT_OVERFLOW = 2, CNT_QUEUE = 4 /* .. 4 + 2*NUM_QUEUES */, CNT_WORDS = 32 };
+// CNT_SORT_ERR: a radix-sort look-back wait ran out of its bound (never expected)
+// CNT_SCAN_TILE: tile claims of the pair-offset scan, whose look-back status
+// words (u64 per tile) follow the CNT_WORDS counters in the same buffer
+enum : int {
+    CNT_PAIRS = 0, CNT_PAIRS_EFF = 1, CNT_OVERFLOW = 2, CNT_SORT_ERR = 3,
+    CNT_QUEUE = 4 /* .. 4 + 2*NUM_QUEUES */, CNT_SCAN_TILE = 20, CNT_WORDS = 32
+};
 
 // Host-visible debug record (mirrors cs_debug_convex of the public header).
 struct DebugConvex {

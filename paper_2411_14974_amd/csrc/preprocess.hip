@@ -48,7 +48,7 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
     const float *__restrict__ sigma, const float *__restrict__ opacity, const float *__restrict__ sh,
     const FrameHeader *__restrict__ frame, RenderArgs ra, uint8_t *__restrict__ records, uint32_t *__restrict__ keys,
     uint32_t *__restrict__ ids, uint2 *__restrict__ rects, uint32_t *__restrict__ counts,
-    uint32_t *__restrict__ hullpk, DebugConvex *__restrict__ dbg)
+    uint64_t *__restrict__ tmasks, uint32_t *__restrict__ hullpk, DebugConvex *__restrict__ dbg)
 {
     // the block's points arrive through LDS (coalesced loads; odd row stride)
     constexpr int PS = 3 * K + 1;
@@ -94,6 +94,8 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
     uint32_t packed = 0;
     int T = 0;
     int tx0 = 1, tx1 = 0, ty0 = 1, ty1 = 0;
+    uint64_t tmask = 0;  // tiles of a rectangle of <= 64 tiles that keep the convex (row-major)
+    int ntiles_kept = 0;
     double dd = 0.0, dp = 0.0, sp = 0.0;
     float rgb[3] = {0.f, 0.f, 0.f};
     int clampmask = 0;
@@ -113,6 +115,7 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
             X[k] = r0 * x + r1 * y + r2 * z + (double)cam.t[0];
             Y[k] = r3 * x + r4 * y + r5 * z + (double)cam.t[1];
             Z[k] = r6 * x + r7 * y + r8 * z + (double)cam.t[2];
+            // the projection's own arithmetic (the hull's orientation tests read it bit for bit)
             qx[k] = (double)cam.fx * X[k] / Z[k] + (double)cam.cx;
             qy[k] = (double)cam.fy * Y[k] / Z[k] + (double)cam.cy;
             zs += Z[k];
@@ -170,8 +173,8 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
             }
             // edge cur -> nxt: outward unit normal (e_y, -e_x)/|e|
             const double ex = nxp - cxp, ey = nyp - cyp;
-            const double len = sqrt(ex * ex + ey * ey);
-            const double A = ey / len, B = -ex / len;
+            const double il = 1.0 / sqrt(ex * ex + ey * ey);
+            const double A = ey * il, B = -ex * il;
             const double Cabs = -(A * cxp + B * cyp);
             const double Crel = -(A * (cxp - ox) + B * (cyp - oy));
             const int j = T - 1;
@@ -193,7 +196,8 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
             } else {
                 const double den = 1.0 + prevA * A + prevB * B;
                 if (den < 1e-6) unbounded = true;
-                const double mx = cxp + r * (prevA + A) / den, my = cyp + r * (prevB + B) / den;
+                const double rd = r / den;
+                const double mx = cxp + rd * (prevA + A), my = cyp + rd * (prevB + B);
                 bx0 = fmin(bx0, fmin(mx, cxp)); bx1 = fmax(bx1, fmax(mx, cxp));
                 by0 = fmin(by0, fmin(my, cyp)); by1 = fmax(by1, fmax(my, cyp));
             }
@@ -206,7 +210,8 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
         if (closed && T >= 3) {
             const double den = 1.0 + prevA * firstA + prevB * firstB;
             if (den < 1e-6) unbounded = true;
-            const double mx = sx + r * (prevA + firstA) / den, my = sy + r * (prevB + firstB) / den;
+            const double rd = r / den;
+            const double mx = sx + rd * (prevA + firstA), my = sy + rd * (prevB + firstB);
             bx0 = fmin(bx0, fmin(mx, sx)); bx1 = fmax(bx1, fmax(mx, sx));
             by0 = fmin(by0, fmin(my, sy)); by1 = fmax(by1, fmax(my, sy));
         }
@@ -285,6 +290,48 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
                     ty0 = v0 / ra.tile; ty1 = v1 / ra.tile;
                     h.box_u = (uint32_t)u0 | ((uint32_t)u1 << 16);
                     h.box_v = (uint32_t)v0 | ((uint32_t)v1 << 16);
+                    // Drop the tiles where one line keeps x2 above the skip
+                    // threshold over every pixel centre of the tile's part of the
+                    // box: there the compositing skips the convex at every pixel
+                    // (max_j x2_j > thr2), so the pair is not emitted.  The minimum
+                    // of a line over the rectangle is at a corner; the margin covers
+                    // the rounding of both evaluations.
+                    // A rectangle one tile wide or high keeps every tile: the
+                    // polygon is connected and its bounding box spans the strip.
+                    const int tw = tx1 - tx0 + 1, th = ty1 - ty0 + 1;
+                    ntiles_kept = tw * th;
+                    tmask = (tw * th < 64) ? ((1ull << (tw * th)) - 1ull) : ~0ull;
+                    if (tw >= 2 && th >= 2 && tw * th <= 64) {
+                        // the lines as stored, into registers once (slots past T unused)
+                        const double *ln = reinterpret_cast<const double *>(rec + REC_HEADER);
+                        double la[K], lb[K], lc[K];
+#pragma unroll
+                        for (int j = 0; j < K; ++j) {
+                            la[j] = ln[3 * j];
+                            lb[j] = ln[3 * j + 1];
+                            lc[j] = ln[3 * j + 2];
+                        }
+                        const double lim = (double)h.thr2 + 1e-3;
+                        uint64_t m = 0;
+                        for (int ty = ty0; ty <= ty1; ++ty) {
+                            const double c0 = (double)max(ty * ra.tile, v0) + 0.5 - oy;
+                            const double c1 = (double)min(ty * ra.tile + ra.tile - 1, v1) + 0.5 - oy;
+                            double rowt[K]; // the line's constant and row part, less the threshold
+#pragma unroll
+                            for (int j = 0; j < K; ++j) rowt[j] = (lc[j] + fmin(lb[j] * c0, lb[j] * c1)) - lim;
+                            for (int tx = tx0; tx <= tx1; ++tx) {
+                                const double a0 = (double)max(tx * ra.tile, u0) + 0.5 - ox;
+                                const double a1 = (double)min(tx * ra.tile + ra.tile - 1, u1) + 0.5 - ox;
+                                bool keep = true;
+#pragma unroll
+                                for (int j = 0; j < K; ++j)
+                                    keep = keep && !(j < T && fmin(la[j] * a0, la[j] * a1) + rowt[j] > 0.0);
+                                if (keep) m |= 1ull << ((ty - ty0) * tw + (tx - tx0));
+                            }
+                        }
+                        tmask = m;
+                        ntiles_kept = __popcll(m);
+                    }
                 }
             }
             const uint4 *hs = reinterpret_cast<const uint4 *>(&h);
@@ -296,7 +343,8 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
 
     const bool has_tiles = status == ST_VISIBLE && tx0 <= tx1 && ty0 <= ty1;
     keys[inst] = status == ST_VISIBLE ? key : KEY_CULLED;
-    counts[inst] = has_tiles ? (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1)) : 0u;
+    counts[inst] = has_tiles ? (uint32_t)ntiles_kept : 0u;
+    tmasks[inst] = tmask;
     rects[inst] = has_tiles ? make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16))
                          : make_uint2(1u, 0u);
     hullpk[inst] = (status == ST_VISIBLE || status == ST_FAINT) ? (packed | ((uint32_t)T << 28)) : 0u;
@@ -604,18 +652,19 @@ __global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
 void launch_preprocess_fwd(hipStream_t st, int n, int nviews, int K, int deg, const float *points,
                            const float *delta, const float *sigma, const float *opacity, const float *sh,
                            const FrameHeader *views, const RenderArgs &ra, uint8_t *records, uint32_t *keys,
-                           uint32_t *ids, uint2 *rects, uint32_t *counts, uint32_t *hullpk, DebugConvex *dbg)
+                           uint32_t *ids, uint2 *rects, uint32_t *counts, uint64_t *tmasks, uint32_t *hullpk,
+                           DebugConvex *dbg)
 {
     if (n <= 0 || nviews <= 0) return;
     dim3 grid((n + PF_BLOCK - 1) / PF_BLOCK, nviews), block(PF_BLOCK);
     if (dbg)
         CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_fwd_kernel<KK, true>), grid, block, 0, st, n, deg, points,
                                             delta, sigma, opacity, sh, views, ra, records, keys, ids, rects, counts,
-                                            hullpk, dbg))
+                                            tmasks, hullpk, dbg))
     else
         CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_fwd_kernel<KK, false>), grid, block, 0, st, n, deg, points,
                                             delta, sigma, opacity, sh, views, ra, records, keys, ids, rects, counts,
-                                            hullpk, dbg))
+                                            tmasks, hullpk, dbg))
 }
 
 void launch_preprocess_bwd(hipStream_t st, int n, int nviews, int K, int deg, const float *points,

@@ -39,11 +39,22 @@ template <int K> struct PairEval {
 
 // The one evaluation of a (pixel, convex) pair shared by both passes.
 // Returns false when the pair is skipped (alpha < eps_alpha).
+// The record (header and all K line slots) is read from LDS in one burst of
+// 16-byte reads with a single wait; slots past T hold stale values and are
+// masked with selects, not branches (a branch per line would serialise the
+// LDS round trips).
 template <int K>
 __device__ __forceinline__ bool eval_pair(const uint8_t *rec, float pxf, float pyf, float eps, PairEval<K> &pe)
 {
-    const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
-    const double *ln = reinterpret_cast<const double *>(rec + REC_HEADER);
+    const RecHeader h = *reinterpret_cast<const RecHeader *>(rec);
+    double L[3 * K + 1]; // one spare slot: odd 3K reads into the record's padding
+    const double2 *l2 = reinterpret_cast<const double2 *>(rec + REC_HEADER);
+#pragma unroll
+    for (int q = 0; q < (3 * K + 1) / 2; ++q) {
+        const double2 w = l2[q];
+        L[2 * q] = w.x;
+        L[2 * q + 1] = w.y;
+    }
     const int T = h.T;
     pe.inv_sum = 0.0f;
     const double dx = (double)(pxf - h.ox), dy = (double)(pyf - h.oy);
@@ -51,12 +62,9 @@ __device__ __forceinline__ bool eval_pair(const uint8_t *rec, float pxf, float p
     double m = -INFINITY;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        if (j < T) {
-            x[j] = fma(ln[3 * j], dx, fma(ln[3 * j + 1], dy, ln[3 * j + 2]));
-            m = fmax(m, x[j]);
-        } else {
-            x[j] = -INFINITY;
-        }
+        const double v = fma(L[3 * j], dx, fma(L[3 * j + 1], dy, L[3 * j + 2]));
+        x[j] = (j < T) ? v : -INFINITY;
+        m = fmax(m, x[j]);
     }
     // LogSumExp >= its largest term: past thr2 alpha < eps for certain
     if (!(m <= (double)h.thr2)) return false;
@@ -131,30 +139,59 @@ template <int TILE> __device__ __forceinline__ void tile_pixel(int &dx, int &dy)
     dy = (w / (TILE / 8)) * 8 + (l >> 3);
 }
 
-// A pixel's (u, y) lies in the record's box, outside of which alpha < eps.
-__device__ __forceinline__ bool in_box(const RecHeader &h, int u, int y)
+// A pixel's (u, y) lies in a record's box (box_u, box_v), outside of which alpha < eps.
+__device__ __forceinline__ bool in_box(uint32_t box_u, uint32_t box_v, int u, int y)
 {
-    return u >= (int)(h.box_u & 0xFFFFu) && u <= (int)(h.box_u >> 16) && y >= (int)(h.box_v & 0xFFFFu) &&
-           y <= (int)(h.box_v >> 16);
+    return u >= (int)(box_u & 0xFFFFu) && u <= (int)(box_u >> 16) && y >= (int)(box_v & 0xFFFFu) &&
+           y <= (int)(box_v >> 16);
 }
 
-// Which of the tile's 8x8 wavefront squares (bit w for wave w, numbered as in
-// tile_pixel) a record's pixel box meets.  Computed once per record and batch,
-// so a wavefront walks only the records that can touch one of its pixels.
-template <int TILE> __device__ __forceinline__ uint32_t wave_mask(uint32_t box_u, uint32_t box_v, int tu, int tv)
+// Lane l of each wave holds the pixel box of batch entry l; a record's box is
+// then a readlane away (no LDS round trip per record).
+template <int K, int BATCH>
+__device__ __forceinline__ void lane_boxes(const uint4 *lds, int cnt, uint32_t &bu, uint32_t &bv)
 {
-    constexpr int WX = TILE / 8;
-    const int u0 = (int)(box_u & 0xFFFFu) - tu, u1 = (int)(box_u >> 16) - tu;
-    const int v0 = (int)(box_v & 0xFFFFu) - tv, v1 = (int)(box_v >> 16) - tv;
-    if (u1 < 0 || v1 < 0 || u0 >= TILE || v0 >= TILE || u0 > u1 || v0 > v1) return 0u;
-    const int cx0 = max(u0, 0) >> 3, cx1 = min(u1, TILE - 1) >> 3;
-    const int cy0 = max(v0, 0) >> 3, cy1 = min(v1, TILE - 1) >> 3;
-    const uint32_t cols = ((2u << cx1) - 1u) & ~((1u << cx0) - 1u);
-    uint32_t m = 0u;
+    constexpr int CH = rec_stride(K) / 16;
+    const int lane = threadIdx.x & 63;
+    bu = 1u; // empty box
+    bv = 1u;
+    if (lane < cnt) {
+        const uint4 c2 = lds[min(lane, BATCH - 1) * CH + 2]; // T, id, box_u, box_v
+        bu = c2.z;
+        bv = c2.w;
+    }
+}
+
+// Can a record reach alpha >= eps_alpha at a pixel centre of the 8x8 square
+// [su, su + 7] x [sv, sv + 7]?  Its pixel box must meet the square, and no
+// hull line may keep x2 above the skip threshold over all pixel centres of
+// the square's part of the box (then the pair evaluation skips every one of
+// them).  A line's minimum over a rectangle is at a corner; the margin covers
+// the rounding of this test and of the pair evaluation.
+template <int K> __device__ __forceinline__ bool square_meets(const uint8_t *rec, int su, int sv)
+{
+    const RecHeader h = *reinterpret_cast<const RecHeader *>(rec);
+    double L[3 * K + 1];
+    const double2 *l2 = reinterpret_cast<const double2 *>(rec + REC_HEADER);
 #pragma unroll
-    for (int r = 0; r < WX; ++r)
-        if (r >= cy0 && r <= cy1) m |= cols << (r * WX);
-    return m;
+    for (int q = 0; q < (3 * K + 1) / 2; ++q) {
+        const double2 w = l2[q];
+        L[2 * q] = w.x;
+        L[2 * q + 1] = w.y;
+    }
+    const int u0 = max(su, (int)(h.box_u & 0xFFFFu)), u1 = min(su + 7, (int)(h.box_u >> 16));
+    const int v0 = max(sv, (int)(h.box_v & 0xFFFFu)), v1 = min(sv + 7, (int)(h.box_v >> 16));
+    if (u0 > u1 || v0 > v1) return false;
+    const double a0 = (double)u0 + 0.5 - (double)h.ox, a1 = (double)u1 + 0.5 - (double)h.ox;
+    const double c0 = (double)v0 + 0.5 - (double)h.oy, c1 = (double)v1 + 0.5 - (double)h.oy;
+    const double lim = (double)h.thr2 + 1e-3;
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const double mn = L[3 * j + 2] + fmin(L[3 * j] * a0, L[3 * j] * a1) + fmin(L[3 * j + 1] * c0, L[3 * j + 1] * c1);
+        ok = ok && !(j < h.T && mn > lim);
+    }
+    return ok;
 }
 
 // Software pipeline of the LDS record batches.  While a batch is composited
@@ -186,34 +223,25 @@ __device__ __forceinline__ void pipe_load_records(u32x4 (&pre)[NL], const uint32
     }
 }
 
-template <int K, int TILE>
-__device__ __forceinline__ void load_records_direct(uint4 *lds, uint32_t *s_wmask, const uint32_t *s_ids,
-                                                    const uint8_t *__restrict__ records, int cnt, int tu, int tv)
+template <int K, int NT>
+__device__ __forceinline__ void load_records_direct(uint4 *lds, const uint32_t *s_ids, const uint8_t *__restrict__ records,
+                                                    int cnt)
 {
-    constexpr int CH = rec_stride(K) / 16, NT = TILE * TILE;
+    constexpr int CH = rec_stride(K) / 16;
     for (int c = threadIdx.x; c < cnt * CH; c += NT) {
         const int e = c / CH, part = c - e * CH;
-        const u32x4 x = reinterpret_cast<const u32x4 *>(records + (size_t)s_ids[e] * rec_stride(K))[part];
-        reinterpret_cast<u32x4 *>(lds)[c] = x;
-        if (part == 2) s_wmask[e] = wave_mask<TILE>(x.z, x.w, tu, tv);
+        reinterpret_cast<u32x4 *>(lds)[c] = reinterpret_cast<const u32x4 *>(records + (size_t)s_ids[e] * rec_stride(K))[part];
     }
 }
 
-// Stores the batch into LDS; the thread holding a record's third chunk
-// (T, id, box_u, box_v) also stores the record's wave mask.
-template <int K, int TILE, int NL>
-__device__ __forceinline__ void pipe_store_records(const u32x4 (&pre)[NL], uint4 *lds, uint32_t *s_wmask, int cnt,
-                                                   int tu, int tv)
+template <int K, int NT, int NL>
+__device__ __forceinline__ void pipe_store_records(const u32x4 (&pre)[NL], uint4 *lds, int cnt)
 {
-    constexpr int CH = rec_stride(K) / 16, NT = TILE * TILE;
+    constexpr int CH = rec_stride(K) / 16;
 #pragma clang loop unroll(full)
     for (int r = 0; r < NL; ++r) {
         const int c = (int)threadIdx.x + r * NT;
-        if (c < cnt * CH) {
-            reinterpret_cast<u32x4 *>(lds)[c] = pre[r];
-            const int e = c / CH;
-            if (c - e * CH == 2) s_wmask[e] = wave_mask<TILE>(pre[r].z, pre[r].w, tu, tv);
-        }
+        if (c < cnt * CH) reinterpret_cast<u32x4 *>(lds)[c] = pre[r];
     }
 }
 
@@ -274,7 +302,6 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4)))
     static_assert(BATCH <= 64, "one ballot bit per batch entry");
     __shared__ uint4 lds[BATCH * CH];
     __shared__ uint32_t s_ids[2][BATCH];
-    __shared__ uint32_t s_wmask[BATCH];
     __shared__ uint32_t s_item;
     const int lane = threadIdx.x & 63, wbit = threadIdx.x >> 6;
     constexpr int NL = pipe_regs<K, NT, BATCH>();
@@ -297,6 +324,7 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4)))
         int pdx, pdy;
         tile_pixel<TILE>(pdx, pdy);
         const int u = tx * TILE + pdx, y = ty * TILE + pdy;
+        const int su = tx * TILE + (wbit % (TILE / 8)) * 8, sv = ty * TILE + (wbit / (TILE / 8)) * 8; // wave's square
         const bool inside = u < W && y < H;
         const float pxf = (float)u + 0.5f, pyf = (float)y + 0.5f;
         const uint2 rg = ranges[gt];
@@ -317,25 +345,32 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4)))
             const int base = start + bi * BATCH;
             const int cnt = min(BATCH, end - base);
             __syncthreads();
-            pipe_store_records<K, TILE, NL>(pre, lds, s_wmask, cnt, tx * TILE, ty * TILE);
+            pipe_store_records<K, NT, NL>(pre, lds, cnt);
             if ((int)threadIdx.x < BATCH) s_ids[(bi + 1) & 1][threadIdx.x] = idr;
             __syncthreads();
             if (bi + 2 < nb) idr = pipe_load_id(ids, base + 2 * BATCH, min(BATCH, end - base - 2 * BATCH));
             if (bi + 1 < nb) pipe_load_records<K, NT, NL>(pre, s_ids[(bi + 1) & 1], records, min(BATCH, end - base - BATCH));
-            // the wave's records of this batch, front to back (a wave-uniform walk)
-            uint64_t M = __ballot(lane < cnt && ((s_wmask[min(lane, BATCH - 1)] >> wbit) & 1u));
-            if (__all(done)) M = 0;
+            // the wave's records of this batch (lane e tests entry e against
+            // the wave's square), front to back in a wave-uniform walk
+            uint64_t M = 0;
+            if (!__all(done)) {
+                const bool meets = lane < cnt && square_meets<K>(reinterpret_cast<const uint8_t *>(&lds[min(lane, BATCH - 1) * CH]), su, sv);
+                M = __ballot(meets);
+            }
+            uint32_t lbu, lbv;
+            lane_boxes<K, BATCH>(lds, cnt, lbu, lbv);
             while (M) {
                 const int e = __builtin_ctzll(M);
                 M &= M - 1;
                 const uint8_t *rec = reinterpret_cast<const uint8_t *>(&lds[e * CH]);
-                const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
-                if (!done && in_box(h, u, y)) {
+                const uint32_t bu = __builtin_amdgcn_readlane(lbu, e), bv = __builtin_amdgcn_readlane(lbv, e);
+                if (!done && in_box(bu, bv, u, y)) {
                     PairEval<K> pe;
                     ++nevals;
                     const bool hit = eval_pair<K>(rec, pxf, pyf, ra.eps_alpha, pe);
                     nfull += pe.inv_sum > 0.0f;
                     if (hit) {
+                        const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
                         const float w = T * pe.alpha;
                         C0 = fmaf(w, h.rgb[0], C0);
                         C1 = fmaf(w, h.rgb[1], C1);
@@ -390,7 +425,6 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
     static_assert(BATCH <= 64, "one ballot bit per batch entry");
     __shared__ uint4 lds[BATCH * CH];
     __shared__ uint32_t s_ids[BATCH];
-    __shared__ uint32_t s_wmask[BATCH];
     // per entry sums of the block's waves, flushed after each batch
     __shared__ float s_acc[BATCH * NP];
     __shared__ int s_maxn;
@@ -413,6 +447,7 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
         int pdx, pdy;
         tile_pixel<TILE>(pdx, pdy);
         const int u = tx * TILE + pdx, y = ty * TILE + pdy;
+        const int su = tx * TILE + (wbit % (TILE / 8)) * 8, sv = ty * TILE + (wbit / (TILE / 8)) * 8; // wave's square
         const bool inside = u < W && y < H;
         const float pxf = (float)u + 0.5f, pyf = (float)y + 0.5f;
         const int start = (int)ranges[gt].x;
@@ -450,17 +485,22 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
             __syncthreads();
             if ((int)threadIdx.x < cnt) cur_ids[threadIdx.x] = ids[start + lo + threadIdx.x];
             __syncthreads();
-            load_records_direct<K, TILE>(lds, s_wmask, cur_ids, records, cnt, tx * TILE, ty * TILE);
+            load_records_direct<K, NT>(lds, cur_ids, records, cnt);
             __syncthreads();
             // the wave's records of this batch before its last contributor, back to front
-            uint64_t M = __ballot(lane < min(cnt, wmaxn - lo) && ((s_wmask[min(lane, BATCH - 1)] >> wbit) & 1u));
+            const bool meets = lane < min(cnt, wmaxn - lo) &&
+                               square_meets<K>(reinterpret_cast<const uint8_t *>(&lds[min(lane, BATCH - 1) * CH]), su, sv);
+            uint64_t M = __ballot(meets);
+            uint32_t lbu, lbv;
+            lane_boxes<K, BATCH>(lds, cnt, lbu, lbv);
             while (M) {
                 const int e = 63 - __builtin_clzll(M);
                 M &= ~(1ull << e);
                 const int pos = lo + e;
                 const uint8_t *rec = reinterpret_cast<const uint8_t *>(&lds[e * CH]);
                 const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
-                const bool live = pos < nend && in_box(h, u, y);
+                const uint32_t bu = __builtin_amdgcn_readlane(lbu, e), bv = __builtin_amdgcn_readlane(lbv, e);
+                const bool live = pos < nend && in_box(bu, bv, u, y);
                 if (!__any(live)) continue; // wave-uniform
                 PairEval<K> pe;
                 const bool contrib = live && eval_pair<K>(rec, pxf, pyf, ra.eps_alpha, pe);

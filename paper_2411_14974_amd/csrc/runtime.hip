@@ -19,20 +19,18 @@
 namespace cs {
 void launch_preprocess_fwd(hipStream_t, int, int, int, int, const float *, const float *, const float *,
                            const float *, const float *, const FrameHeader *, const RenderArgs &, uint8_t *,
-                           uint32_t *, uint32_t *, uint2 *, uint32_t *, uint32_t *, DebugConvex *);
+                           uint32_t *, uint32_t *, uint2 *, uint32_t *, uint64_t *, uint32_t *, DebugConvex *);
 void launch_preprocess_bwd(hipStream_t, int, int, int, int, const float *, const float *, const float *,
                            const float *, const FrameHeader *, const uint8_t *, const uint32_t *, const float *,
                            float *, float *, float *, float *, float *);
-void radix_sort(hipStream_t, uint32_t **, uint32_t **, uint32_t **, uint32_t **, uint32_t, const uint32_t *, int, int,
-                uint32_t *, uint32_t *, int);
-int radix_blocks(uint32_t);
-size_t radix_hist_words(int);
-size_t scan_temp_words(uint32_t);
-void scan_exclusive(hipStream_t, const uint32_t *, uint32_t *, uint32_t, uint32_t *, uint32_t *);
+void radix_sort(hipStream_t, uint32_t **, uint32_t **, uint32_t **, uint32_t **, uint32_t, const uint32_t *, uint32_t, int,
+                uint32_t *, int, uint32_t *);
+size_t sort_temp_words(uint32_t, int, int);
+size_t scan_status_words(uint32_t);
+void launch_gather_scan(hipStream_t, uint32_t, const uint32_t *, const uint32_t *, uint32_t *, uint32_t *, uint32_t *);
 void launch_fill_u32(hipStream_t, uint32_t *, size_t, uint32_t);
-void launch_gather_counts(hipStream_t, uint32_t, const uint32_t *, const uint32_t *, uint32_t *);
-void launch_emit_pairs(hipStream_t, uint32_t, uint32_t, const uint32_t *, const uint32_t *, const uint2 *,
-                       const FrameHeader *, uint32_t, uint32_t *, uint32_t *);
+void launch_emit_pairs(hipStream_t, uint32_t, uint32_t, const uint32_t *, const uint32_t *, const uint32_t *,
+                       const uint2 *, const uint64_t *, const FrameHeader *, uint32_t, uint32_t *, uint32_t *);
 void launch_clamp_pairs(hipStream_t, uint32_t *, uint32_t);
 void launch_tile_length_keys(hipStream_t, uint32_t, const uint2 *, uint32_t *, uint32_t *);
 void launch_tile_ranges(hipStream_t, const uint32_t *, uint32_t, const uint32_t *, uint32_t, uint2 *);
@@ -151,8 +149,6 @@ int Frame::init(int n_, int K_, int deg_, int V_, size_t tiles, size_t pix, hipS
     cap_tiles = std::max<size_t>(tiles, 1);
     cap_pix = std::max<size_t>(pix, 1);
     const uint32_t ui = (uint32_t)cap_inst;
-    nb_inst = radix_blocks(ui);
-    nb_tiles = radix_blocks((uint32_t)cap_tiles);
 #define CS_A(ptr, bytes) do { int r_ = alloc((void **)&(ptr), (bytes)); if (r_) return r_; } while (0)
     CS_A(d_frame, VIEW_TABLE_BYTES);
     CS_A(records, cap_inst * rec_stride(K));
@@ -165,13 +161,15 @@ int Frame::init(int n_, int K_, int deg_, int V_, size_t tiles, size_t pix, hipS
     CS_A(offsets, cap_inst * 4);
     CS_A(hullpk, cap_inst * 4);
     CS_A(rects, cap_inst * 8);
+    CS_A(tmasks, cap_inst * 8);
     CS_A(ranges, cap_tiles * 8);
     CS_A(ord_k, cap_tiles * 4);
     CS_A(ord_v, cap_tiles * 4);
     CS_A(ord_k_alt, cap_tiles * 4);
     CS_A(ord_v_alt, cap_tiles * 4);
     CS_A(pixstate, cap_pix * 8);
-    CS_A(counters, CNT_WORDS * 4);
+    counter_words = CNT_WORDS + scan_status_words((uint32_t)cap_inst);
+    CS_A(counters, counter_words * 4);
     CS_A(evalcount, 16);
 #undef CS_A
     return CS_OK;
@@ -180,20 +178,21 @@ int Frame::init(int n_, int K_, int deg_, int V_, size_t tiles, size_t pix, hipS
 int Frame::ensure_pairs(size_t m)
 {
     if (m <= cap_pairs && pt) return CS_OK;
-    for (void *p : {(void *)pt, (void *)pi, (void *)pt_alt, (void *)pi_alt, (void *)hist, (void *)scan_tmp})
+    for (void *p : {(void *)pt, (void *)pi, (void *)pt_alt, (void *)pi_alt, (void *)hist})
         if (p) release_buffer(p);
     cap_pairs = std::max<size_t>(m, 1);
-    nb_pairs = radix_blocks((uint32_t)cap_pairs);
-    const int nb = std::max(std::max(nb_inst, nb_pairs), nb_tiles);
-    const size_t hw = radix_hist_words(nb);
-    const size_t scan_n = std::max<size_t>(std::max<size_t>(hw, cap_inst), cap_tiles);
+    // sort temporaries: the largest of the depth, tile and tile-order sorts
+    // (tile keys sorted in digits of 4 to 8 bits: sized for the most passes)
+    const int tile_bits = std::max(1, ilog2_ceil(cap_tiles));
+    const size_t hw = std::max({sort_temp_words((uint32_t)cap_inst, 32, 8),
+                                sort_temp_words((uint32_t)cap_pairs, tile_bits, 4),
+                                sort_temp_words((uint32_t)cap_tiles, 16, 8)});
 #define CS_A(ptr, bytes) do { int r_ = alloc((void **)&(ptr), (bytes)); if (r_) return r_; } while (0)
     CS_A(pt, cap_pairs * 4);
     CS_A(pi, cap_pairs * 4);
     CS_A(pt_alt, cap_pairs * 4);
     CS_A(pi_alt, cap_pairs * 4);
     CS_A(hist, hw * 4);
-    CS_A(scan_tmp, (scan_temp_words((uint32_t)scan_n) + 16) * 4);
 #undef CS_A
     return CS_OK;
 }
@@ -371,11 +370,11 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
     F.tile = kn.tile;
     F.longest = kn.longest;
     F.digits = kn.digits;
-    launch_fill_u32(st, F.counters, CNT_WORDS, 0u);
+    launch_fill_u32(st, F.counters, F.counter_words, 0u);
     launch_fill_u32(st, reinterpret_cast<uint32_t *>(F.evalcount), 4, 0u);
     tm.begin();
     launch_preprocess_fwd(st, n, F.V, F.K, F.deg, sc->points, sc->delta, sc->sigma, sc->opacity, sc->sh, F.d_frame,
-                          ra, F.records, F.keys, F.ids, F.rects, F.counts, F.hullpk, nullptr);
+                          ra, F.records, F.keys, F.ids, F.rects, F.counts, F.tmasks, F.hullpk, nullptr);
     tm.end(CS_STAGE_PREPROCESS);
 
     uint32_t *keys = F.keys, *ids = F.ids, *keys_alt = F.keys_alt, *ids_alt = F.ids_alt;
@@ -386,11 +385,10 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
             if (r) return r;
         }
         tm.begin();
-        radix_sort(st, &keys, &ids, &keys_alt, &ids_alt, ninst, nullptr, F.nb_inst, 32, F.hist, F.scan_tmp, 8);
+        radix_sort(st, &keys, &ids, &keys_alt, &ids_alt, ninst, nullptr, ninst, 32, F.hist, 8, F.counters + CNT_SORT_ERR);
         tm.end(CS_STAGE_DEPTH_SORT);
         tm.begin();
-        launch_gather_counts(st, ninst, ids, F.counts, F.counts_sorted);
-        scan_exclusive(st, F.counts_sorted, F.offsets, ninst, F.counters + CNT_PAIRS, F.scan_tmp);
+        launch_gather_scan(st, ninst, ids, F.counts, F.counts_sorted, F.offsets, F.counters);
         tm.end(CS_STAGE_BIN_SCAN);
         if (!device_count) {
             uint32_t *hw = F.ring->h_word;
@@ -413,11 +411,14 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
     uint32_t *pt = F.pt, *pi = F.pi, *pt_alt = F.pt_alt, *pi_alt = F.pi_alt;
     if (ninst > 0) {
         tm.begin();
-        launch_emit_pairs(st, ninst, (uint32_t)n, ids, F.offsets, F.rects, F.d_frame, (uint32_t)F.cap_pairs, pt, pi);
+        launch_emit_pairs(st, ninst, (uint32_t)n, ids, F.offsets, F.counts_sorted, F.rects, F.tmasks, F.d_frame,
+                          (uint32_t)F.cap_pairs,
+                          pt, pi);
         tm.end(CS_STAGE_EMIT);
         const int tile_bits = std::max(1, ilog2_ceil(F.cap_tiles));
         tm.begin();
-        radix_sort(st, &pt, &pi, &pt_alt, &pi_alt, M, m_dev, F.nb_pairs, tile_bits, F.hist, F.scan_tmp, kn.digits);
+        radix_sort(st, &pt, &pi, &pt_alt, &pi_alt, M, m_dev, (uint32_t)F.cap_pairs, tile_bits, F.hist, kn.digits,
+                   F.counters + CNT_SORT_ERR);
         tm.end(CS_STAGE_TILE_SORT);
         tm.begin();
         launch_tile_ranges(st, pt, M, m_dev, device_count ? (uint32_t)F.cap_pairs : M, F.ranges);
@@ -429,7 +430,8 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
         uint32_t *ok = F.ord_k, *ov = F.ord_v, *ok2 = F.ord_k_alt, *ov2 = F.ord_v_alt;
         tm.begin();
         launch_tile_length_keys(st, (uint32_t)F.cap_tiles, F.ranges, ok, ov);
-        radix_sort(st, &ok, &ov, &ok2, &ov2, (uint32_t)F.cap_tiles, nullptr, F.nb_tiles, 16, F.hist, F.scan_tmp, 8);
+        radix_sort(st, &ok, &ov, &ok2, &ov2, (uint32_t)F.cap_tiles, nullptr, (uint32_t)F.cap_tiles, 16, F.hist, 8,
+                   F.counters + CNT_SORT_ERR);
         tm.end(CS_STAGE_ORDER);
         F.order = ov;
     }
@@ -790,10 +792,14 @@ int cs_batch_check(cs_ctx *ctx, const cs_fwd_state *s)
         return fail(CS_EINVAL, "batch state was replaced by a later batched forward");
     CS_HIP(hipSetDevice(ctx->device));
     if (s->owned) {
+        uint32_t err = 0;
+        CS_HIP(hipMemcpyAsync(&err, F->counters + CNT_SORT_ERR, 4, hipMemcpyDeviceToHost, F->st));
         CS_HIP(hipStreamSynchronize(F->st));
+        if (err) return fail(CS_EHIP, "radix sort: a look-back wait exceeded its bound");
         return CS_OK;
     }
     CS_HIP(hipEventSynchronize(F->counters_ev));
+    if (F->h_counters[CNT_SORT_ERR]) return fail(CS_EHIP, "radix sort: a look-back wait exceeded its bound");
     if (F->h_counters[CNT_OVERFLOW]) {
         const size_t m = F->h_counters[CNT_PAIRS];
         CS_HIP(hipStreamSynchronize(F->st));
@@ -952,6 +958,7 @@ int cs_state_stats(cs_ctx *ctx, const cs_fwd_state *s, int64_t *n_pairs, int64_t
     CS_HIP(hipMemcpyAsync(ev, F->evalcount, sizeof(ev), hipMemcpyDeviceToHost, F->st));
     CS_HIP(hipMemcpyAsync(cnt, F->counters, sizeof(cnt), hipMemcpyDeviceToHost, F->st));
     CS_HIP(hipStreamSynchronize(F->st));
+    if (cnt[CNT_SORT_ERR]) return fail(CS_EHIP, "radix sort: a look-back wait exceeded its bound");
     if (n_pairs) *n_pairs = cnt[CNT_PAIRS];
     if (n_evaluated) *n_evaluated = (int64_t)ev[0];
     if (n_full) *n_full = (int64_t)ev[1];
@@ -1001,7 +1008,7 @@ int cs_debug_preprocess(cs_ctx *ctx, const cs_scene *sc, const cs_camera *cam, c
     DebugConvex *dbg = nullptr;
     CS_TRY(F.alloc((void **)&dbg, sizeof(DebugConvex) * (size_t)sc->n));
     launch_preprocess_fwd(st, sc->n, 1, sc->k, sc->sh_degree, sc->points, sc->delta, sc->sigma, sc->opacity, sc->sh,
-                          F.d_frame, ra, F.records, F.keys, F.ids, F.rects, F.counts, F.hullpk, dbg);
+                          F.d_frame, ra, F.records, F.keys, F.ids, F.rects, F.counts, F.tmasks, F.hullpk, dbg);
     CS_HIP(hipGetLastError());
     CS_HIP(hipMemcpyAsync(out, dbg, sizeof(DebugConvex) * (size_t)sc->n, hipMemcpyDeviceToHost, st));
     CS_HIP(hipStreamSynchronize(st));

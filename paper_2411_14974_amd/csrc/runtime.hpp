@@ -32,7 +32,6 @@ struct Frame {
     int n = 0, K = 0, deg = 0, V = 0;
     int tile = 16, longest = 0, digits = 8;
     size_t cap_inst = 0, cap_pairs = 0, cap_tiles = 0, cap_pix = 0;
-    int nb_inst = 1, nb_pairs = 1, nb_tiles = 1;
     uint32_t npairs = 0;
     hipStream_t st = nullptr;
     std::vector<void *> allocs;
@@ -43,13 +42,15 @@ struct Frame {
     uint32_t *keys = nullptr, *ids = nullptr, *keys_alt = nullptr, *ids_alt = nullptr;
     uint32_t *counts = nullptr, *counts_sorted = nullptr, *offsets = nullptr, *hullpk = nullptr;
     uint2 *rects = nullptr;
-    uint32_t *hist = nullptr, *scan_tmp = nullptr;
+    uint64_t *tmasks = nullptr; // kept tiles of small tile rectangles (row-major bits)
+    uint32_t *hist = nullptr; // radix sort temporaries (histograms, tile counters, look-back status)
     uint32_t *pt = nullptr, *pi = nullptr, *pt_alt = nullptr, *pi_alt = nullptr;
     uint2 *ranges = nullptr;
     uint32_t *ord_k = nullptr, *ord_v = nullptr, *ord_k_alt = nullptr, *ord_v_alt = nullptr;
     uint2 *pixstate = nullptr;
     float *acc = nullptr;
-    uint32_t *counters = nullptr;
+    uint32_t *counters = nullptr; // CNT_WORDS counters, then the pair-offset scan's look-back status
+    size_t counter_words = 0;
     unsigned long long *evalcount = nullptr;
     uint32_t *h_counters = nullptr; // pinned read-back of the counters
     hipEvent_t counters_ev = nullptr;

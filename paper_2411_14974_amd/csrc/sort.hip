@@ -1,6 +1,6 @@
-// Tile binning and ordering (gfx950): device-wide exclusive scan, a stable
-// LSD radix sort of (u32 key, u32 value) pairs, (convex, tile) pair emission
-// and per-tile list ranges.
+// Tile binning and ordering (gfx950): the pair-offset scan, a stable LSD
+// radix sort of (u32 key, u32 value) pairs, (convex, tile) pair emission and
+// per-tile list ranges.
 //
 // The front-to-back order within a tile (paper Sec. 3.2: convexes sorted by
 // increasing distance) comes from a two-stage LSD sort of the (tile | depth)
@@ -60,282 +60,400 @@ __device__ uint32_t block_scan_lds(uint32_t *s, uint32_t *s_wave)
     return total;
 }
 
-__global__ __launch_bounds__(SCAN_BLOCK) void scan_reduce_kernel(const uint32_t *__restrict__ in, uint32_t n,
-                                                                  uint32_t *__restrict__ block_sums)
+// Pair counts in depth order and their exclusive scan (the pair offsets), in
+// one pass: each workgroup claims the next tile of SCAN_TILE ranks, gathers
+// counts[sorted_ids[r]], scans them in LDS, publishes the tile's sum and
+// finds its prefix by a decoupled look-back in which one wave reads 64
+// predecessors' 64-bit status words at a time.  The last tile stores the total.
+constexpr uint64_t SS_AGG = 1ull << 62, SS_INC = 2ull << 62, SS_VAL = SS_AGG - 1ull;
+constexpr uint32_t SS_SPIN_LIMIT = 1u << 22;
+
+__device__ __forceinline__ uint64_t ss_load(const uint64_t *p)
 {
-    __shared__ uint32_t s_wave[SCAN_BLOCK / 64];
-    const size_t base = (size_t)blockIdx.x * SCAN_TILE;
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        const size_t i = base + (size_t)k * SCAN_BLOCK + threadIdx.x;
-        if (i < n) sum += in[i];
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
-    if ((threadIdx.x & 63) == 0) s_wave[threadIdx.x >> 6] = sum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t t = 0;
-        for (int w = 0; w < SCAN_BLOCK / 64; ++w) t += s_wave[w];
-        block_sums[blockIdx.x] = t;
-    }
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void ss_store(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One block scans the block sums in place (exclusive) and stores the total.
-__global__ __launch_bounds__(SCAN_BLOCK) void scan_top_kernel(uint32_t *__restrict__ sums, uint32_t nb,
-                                                               uint32_t *__restrict__ total)
+__global__ __launch_bounds__(SCAN_BLOCK) void gather_scan_kernel(
+    uint32_t n, const uint32_t *__restrict__ sorted_ids, const uint32_t *__restrict__ counts,
+    uint32_t *__restrict__ counts_sorted, uint32_t *__restrict__ offsets, uint32_t *__restrict__ counters,
+    uint64_t *__restrict__ status)
 {
     __shared__ uint32_t s[SCAN_TILE + SCAN_TILE / 32];
     __shared__ uint32_t s_wave[SCAN_BLOCK / 64];
-    uint32_t carry = 0;
-    for (uint32_t base = 0; base < nb; base += SCAN_TILE) {
-#pragma unroll
-        for (int k = 0; k < SCAN_ITEMS; ++k) {
-            const uint32_t i = base + k * SCAN_BLOCK + threadIdx.x;
-            s[lds_pad(k * SCAN_BLOCK + threadIdx.x)] = i < nb ? sums[i] : 0u;
-        }
-        __syncthreads();
-        const uint32_t t = block_scan_lds(s, s_wave);
-#pragma unroll
-        for (int k = 0; k < SCAN_ITEMS; ++k) {
-            const uint32_t i = base + k * SCAN_BLOCK + threadIdx.x;
-            if (i < nb) sums[i] = s[lds_pad(k * SCAN_BLOCK + threadIdx.x)] + carry;
-        }
-        carry += t;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && total) *total = carry;
-}
-
-__global__ __launch_bounds__(SCAN_BLOCK) void scan_down_kernel(const uint32_t *__restrict__ in, uint32_t n,
-                                                                const uint32_t *__restrict__ block_offsets,
-                                                                uint32_t *__restrict__ out)
-{
-    __shared__ uint32_t s[SCAN_TILE + SCAN_TILE / 32];
-    __shared__ uint32_t s_wave[SCAN_BLOCK / 64];
-    const size_t base = (size_t)blockIdx.x * SCAN_TILE;
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_excl;
+    const int tid = threadIdx.x, lane = tid & 63;
+    if (tid == 0) s_tile = atomicAdd(&counters[CNT_SCAN_TILE], 1u);
+    __syncthreads();
+    const uint32_t t = s_tile;
+    const size_t base = (size_t)t * SCAN_TILE;
+    if (base >= n) return;
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
-        const size_t i = base + (size_t)k * SCAN_BLOCK + threadIdx.x;
-        s[lds_pad(k * SCAN_BLOCK + threadIdx.x)] = i < n ? in[i] : 0u;
+        const size_t i = base + (size_t)k * SCAN_BLOCK + tid;
+        uint32_t c = 0;
+        if (i < n) {
+            c = counts[sorted_ids[i]];
+            counts_sorted[i] = c;
+        }
+        s[lds_pad(k * SCAN_BLOCK + tid)] = c;
     }
     __syncthreads();
-    block_scan_lds(s, s_wave);
-    const uint32_t off = block_offsets[blockIdx.x];
+    const uint32_t tile_total = block_scan_lds(s, s_wave);
+    if (tid < 64) {
+        if (tid == 0) ss_store(&status[t], (t == 0 ? SS_INC : SS_AGG) | (uint64_t)tile_total);
+        uint64_t excl = 0;
+        if (t > 0) {
+            int64_t j = (int64_t)t - 1; // the window's newest tile
+            uint32_t spins = 0;
+            for (;;) {
+                const int64_t idx = j - lane;
+                const uint64_t sv = idx >= 0 ? ss_load(&status[idx]) : SS_INC; // before tile 0: inclusive 0
+                const uint64_t flag = sv & ~SS_VAL;
+                const uint64_t notready = __ballot(flag == 0ull), inc = __ballot(flag == SS_INC);
+                const int fi = inc ? __builtin_ctzll(inc) : 64; // nearest inclusive prefix in the window
+                const uint64_t need = (fi >= 63) ? ~0ull : ((2ull << fi) - 1ull);
+                if (notready & need) {
+                    if (++spins > SS_SPIN_LIMIT) {
+                        if (lane == 0) atomicOr(&counters[CNT_SORT_ERR], 2u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                uint64_t v = (lane <= fi) ? (sv & SS_VAL) : 0ull;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+                excl += v;
+                if (fi < 64) break;
+                j -= 64;
+            }
+            if (tid == 0) ss_store(&status[t], SS_INC | (excl + tile_total));
+        }
+        if (tid == 0) {
+            s_excl = excl;
+            if (base + SCAN_TILE >= n) counters[CNT_PAIRS] = (uint32_t)(excl + tile_total);
+        }
+    }
+    __syncthreads();
+    const uint32_t ex = (uint32_t)s_excl;
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
-        const size_t i = base + (size_t)k * SCAN_BLOCK + threadIdx.x;
-        if (i < n) out[i] = s[lds_pad(k * SCAN_BLOCK + threadIdx.x)] + off;
+        const size_t i = base + (size_t)k * SCAN_BLOCK + tid;
+        if (i < n) offsets[i] = s[lds_pad(k * SCAN_BLOCK + tid)] + ex;
     }
 }
 
-size_t scan_temp_words(uint32_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+// 32-bit words of the scan's look-back status (u64 per tile of SCAN_TILE ranks).
+size_t scan_status_words(uint32_t n) { return 2 * (((size_t)n + SCAN_TILE - 1) / SCAN_TILE + 1); }
 
-// out[i] = sum_{j<i} in[j]; *total (device) = sum of all.  tmp: scan_temp_words(n) words.
-void scan_exclusive(hipStream_t st, const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *total, uint32_t *tmp)
+// counts_sorted[r] = counts[sorted_ids[r]], offsets = its exclusive scan,
+// counters[CNT_PAIRS] = the total.  counters must hold CNT_WORDS words, zeroed,
+// followed by scan_status_words(n) zeroed words.
+void launch_gather_scan(hipStream_t st, uint32_t n, const uint32_t *sorted_ids, const uint32_t *counts,
+                        uint32_t *counts_sorted, uint32_t *offsets, uint32_t *counters)
 {
-    const uint32_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
-    if (nb == 0) {
-        hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(SCAN_BLOCK), 0, st, tmp, 0u, total);
-        return;
-    }
-    hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(SCAN_BLOCK), 0, st, in, n, tmp);
-    hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(SCAN_BLOCK), 0, st, tmp, nb, total);
-    hipLaunchKernelGGL(scan_down_kernel, dim3(nb), dim3(SCAN_BLOCK), 0, st, in, n, tmp, out);
+    if (n == 0) return;
+    const uint32_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(gather_scan_kernel, dim3(tiles), dim3(SCAN_BLOCK), 0, st, n, sorted_ids, counts,
+                       counts_sorted, offsets, counters, reinterpret_cast<uint64_t *>(counters + CNT_WORDS));
 }
 
 // ----------------------------------------------------------- radix sort ----
+//
+// Stable LSD radix sort of (u32 key, u32 value) pairs with one kernel per
+// digit (single-pass scatter with decoupled look-back, after Merrill and
+// Garland's single-pass prefix scan as used by the "Onesweep" radix sort):
+//  1. one kernel reads the keys once and builds the global digit histograms of
+//     every pass;
+//  2. per pass, each workgroup claims the next tile of OS_TILE elements from an
+//     atomic counter (tiles are claimed in order by running workgroups), ranks
+//     its elements per digit (wave ballots), publishes its per-digit counts,
+//     then walks back over its predecessors' published counts until it meets an
+//     inclusive prefix, publishes its own inclusive prefix, and writes its
+//     elements digit-sorted to their global positions.
+// A predecessor publishes its counts before it waits on anything, so every
+// wait ends; it is still bounded (OS_SPIN_LIMIT), and a wait that runs out
+// sets the caller's error word instead of spinning on.
 
-constexpr int RS_MAX_BITS = 8;
-constexpr int RS_MAX_RADIX = 1 << RS_MAX_BITS;
-constexpr int RS_BLOCK = 256;
-constexpr int RS_WAVES = RS_BLOCK / 64;
-constexpr int RS_ITEMS = 16;
-constexpr int RS_TILE = RS_BLOCK * RS_ITEMS;
+constexpr int OS_BLOCK = 256;
+constexpr int OS_WAVES = OS_BLOCK / 64;
+constexpr int OS_ITEMS = 16;
+constexpr int OS_TILE = OS_BLOCK * OS_ITEMS;
+constexpr int OS_RADIX = 256; // digits of up to 8 bits
+constexpr int OS_MAX_PASSES = 8;
+constexpr uint32_t OS_AGG = 1u << 30, OS_INC = 2u << 30, OS_VAL = OS_AGG - 1u;
+constexpr uint32_t OS_SPIN_LIMIT = 1u << 22;
+constexpr int OS_WINDOW = 8; // predecessors read per look-back round trip
+// temporary layout (words): histograms [P][256] | tile counters [64] | status [P][tiles][256]
+constexpr size_t OS_CTR = (size_t)OS_MAX_PASSES * OS_RADIX, OS_STATUS = OS_CTR + 64;
 
-// Tiles [t0, t1) of block b under an even split of ceil(n / RS_TILE) tiles.
-__device__ __forceinline__ void rs_block_tiles(uint32_t n, int nblocks, uint32_t &t0, uint32_t &t1)
+__host__ __device__ constexpr int os_passes(int end_bit, int digit_bits) { return (end_bit + digit_bits - 1) / digit_bits; }
+
+__device__ __forceinline__ uint32_t os_load(const uint32_t *p)
 {
-    const uint32_t ntiles = (n + RS_TILE - 1) / RS_TILE;
-    const uint32_t per = (ntiles + nblocks - 1) / nblocks;
-    t0 = min(ntiles, blockIdx.x * per);
-    t1 = min(ntiles, t0 + per);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void os_store(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int RS_BITS>
-__global__ __launch_bounds__(RS_BLOCK) void radix_hist_kernel(const uint32_t *__restrict__ keys,
-                                                               const uint32_t *__restrict__ n_dev, uint32_t n_host,
-                                                               int shift, int nblocks, uint32_t *__restrict__ hist)
+// Lanes of the wave holding the same BITS-bit digit (ballot per bit).
+template <int BITS> __device__ __forceinline__ uint64_t digit_peers(uint32_t dg, bool valid)
 {
-    constexpr int RS_RADIX = 1 << RS_BITS;
-    __shared__ uint32_t h[RS_WAVES][RS_RADIX];
-    const uint32_t n = n_dev ? *n_dev : n_host;
-    const int wave = threadIdx.x >> 6;
-    for (int d = threadIdx.x; d < RS_WAVES * RS_RADIX; d += RS_BLOCK) (&h[0][0])[d] = 0;
-    __syncthreads();
-    uint32_t t0, t1;
-    rs_block_tiles(n, nblocks, t0, t1);
-    for (uint32_t t = t0; t < t1; ++t) {
+    uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int i = 0; i < RS_ITEMS; ++i) {
-            const size_t idx = (size_t)t * RS_TILE + i * RS_BLOCK + threadIdx.x;
-            if (idx < n) atomicAdd(&h[wave][(keys[idx] >> shift) & (RS_RADIX - 1)], 1u);
+    for (int b = 0; b < BITS; ++b) {
+        const uint64_t bal = __ballot((dg >> b) & 1u);
+        peers &= ((dg >> b) & 1u) ? bal : ~bal;
+    }
+    return peers;
+}
+
+// Exclusive scan of one value per thread over the workgroup (OS_BLOCK threads).
+__device__ __forceinline__ uint32_t os_block_excl(uint32_t x, uint32_t *s_wsum)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    uint32_t wb = 0;
+    for (int w = 0; w < wave; ++w) wb += s_wsum[w];
+    __syncthreads();
+    return wb + incl - x;
+}
+
+// Global histograms of every pass: hist[p * 256 + digit].  A workgroup takes
+// tiles of OS_TILE keys (grid-stride), loads a tile's 16 keys per thread at
+// once, counts equal digits per wave with ballots (one LDS add per distinct
+// digit), and adds its nonzero bins to the global histogram at the end.
+template <int BITS>
+__global__ __launch_bounds__(OS_BLOCK) void os_hist_kernel(const uint32_t *__restrict__ keys,
+                                                           const uint32_t *__restrict__ n_dev, uint32_t n_host,
+                                                           int end_bit, uint32_t *__restrict__ hist)
+{
+    constexpr int R = 1 << BITS;
+    const int P = os_passes(end_bit, BITS);
+    __shared__ uint32_t h[OS_MAX_PASSES * R];
+    const uint32_t n = n_dev ? *n_dev : n_host;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lower = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (int d = threadIdx.x; d < P * R; d += OS_BLOCK) h[d] = 0;
+    __syncthreads();
+    const uint32_t ntiles = (n + OS_TILE - 1) / OS_TILE;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        uint32_t k[OS_ITEMS];
+#pragma unroll
+        for (int i = 0; i < OS_ITEMS; ++i) {
+            const size_t idx = (size_t)t * OS_TILE + (size_t)i * OS_BLOCK + threadIdx.x;
+            k[i] = idx < n ? keys[idx] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < OS_ITEMS; ++i) {
+            const bool valid = (size_t)t * OS_TILE + (size_t)i * OS_BLOCK + threadIdx.x < n;
+            for (int p = 0; p < P; ++p) {
+                const uint32_t dg = (k[i] >> (p * BITS)) & (R - 1);
+                const uint64_t peers = digit_peers<BITS>(dg, valid);
+                if (valid && (peers & lower) == 0ull) atomicAdd(&h[p * R + dg], (uint32_t)__popcll(peers));
+            }
         }
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < RS_RADIX; d += RS_BLOCK) {
-        uint32_t c = 0;
-#pragma unroll
-        for (int w = 0; w < RS_WAVES; ++w) c += h[w][d];
-        hist[(size_t)d * nblocks + blockIdx.x] = c;
-    }
+    for (int d = threadIdx.x; d < P * R; d += OS_BLOCK)
+        if (h[d]) atomicAdd(&hist[(d / R) * OS_RADIX + d % R], h[d]);
 }
 
-// Stable scatter of one digit of RS_BITS (<= 8) bits.  Within a tile the element order is
-// (wave, item, lane); each wave ranks its elements with ballots over the digit
-// bits, the block places the tile digit-sorted in LDS and writes each digit's
-// run contiguously to its global position.
-template <int RS_BITS>
-__global__ __launch_bounds__(RS_BLOCK) void radix_scatter_kernel(
+template <int BITS>
+__global__ __launch_bounds__(OS_BLOCK) void os_scatter_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
-    uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ n_dev, uint32_t n_host, int shift, int nblocks,
-    const uint32_t *__restrict__ hist_scanned)
+    uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ n_dev, uint32_t n_host, int shift,
+    const uint32_t *__restrict__ hist, uint32_t *__restrict__ tile_counter, uint32_t *__restrict__ status,
+    uint32_t *__restrict__ err)
 {
-    constexpr int RS_RADIX = 1 << RS_BITS;
-    __shared__ uint32_t s_keys[RS_TILE];
-    __shared__ uint32_t s_vals[RS_TILE];
-    __shared__ uint32_t s_wcnt[RS_WAVES][RS_RADIX];
-    __shared__ uint32_t s_dstart[RS_RADIX];
-    __shared__ uint32_t s_total[RS_RADIX];
-    __shared__ uint32_t s_gofs[RS_RADIX];
-    __shared__ uint32_t s_wsum[RS_WAVES];
+    constexpr int R = 1 << BITS;
+    __shared__ uint32_t s_keys[OS_TILE];
+    __shared__ uint32_t s_vals[OS_TILE];
+    __shared__ uint32_t s_wcnt[OS_WAVES][R];
+    __shared__ uint32_t s_dstart[R];
+    __shared__ uint32_t s_gofs[R];
+    __shared__ uint32_t s_wsum[OS_WAVES];
+    __shared__ uint32_t s_tile;
 
     const uint32_t n = n_dev ? *n_dev : n_host;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t t0, t1;
-    rs_block_tiles(n, nblocks, t0, t1);
-    for (int d = tid; d < RS_RADIX; d += RS_BLOCK) s_gofs[d] = hist_scanned[(size_t)d * nblocks + blockIdx.x];
+    if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+    for (int d = tid; d < OS_WAVES * R; d += OS_BLOCK) (&s_wcnt[0][0])[d] = 0;
+    __syncthreads();
+    const uint32_t t = s_tile;
+    const size_t tbase = (size_t)t * OS_TILE;
+    if (tbase >= n) return; // past the data (capacity-sized grids): nobody waits on this tile
 
-    for (uint32_t t = t0; t < t1; ++t) {
-        for (int d = tid; d < RS_WAVES * RS_RADIX; d += RS_BLOCK) (&s_wcnt[0][0])[d] = 0;
-        __syncthreads();
-        uint32_t k[RS_ITEMS], v[RS_ITEMS], off[RS_ITEMS];
-        const size_t wbase = (size_t)t * RS_TILE + (size_t)wave * 64 * RS_ITEMS;
+    // rank: element order within the tile is (wave, item, lane)
+    uint32_t k[OS_ITEMS], v[OS_ITEMS], off[OS_ITEMS];
+    const size_t wbase = tbase + (size_t)wave * 64 * OS_ITEMS;
 #pragma unroll
-        for (int i = 0; i < RS_ITEMS; ++i) {
-            const size_t idx = wbase + i * 64 + lane;
-            const bool valid = idx < n;
-            k[i] = valid ? keys_in[idx] : 0u;
-            v[i] = valid ? vals_in[idx] : 0u;
-            const uint32_t dg = (k[i] >> shift) & (RS_RADIX - 1);
-            uint64_t peers = __ballot(valid);
+    for (int i = 0; i < OS_ITEMS; ++i) {
+        const size_t idx = wbase + i * 64 + lane;
+        const bool valid = idx < n;
+        k[i] = valid ? keys_in[idx] : 0u;
+        v[i] = valid ? vals_in[idx] : 0u;
+    }
 #pragma unroll
-            for (int b = 0; b < RS_BITS; ++b) {
-                const uint64_t bal = __ballot((dg >> b) & 1u);
-                peers &= ((dg >> b) & 1u) ? bal : ~bal;
+    for (int i = 0; i < OS_ITEMS; ++i) {
+        const size_t idx = wbase + i * 64 + lane;
+        const bool valid = idx < n;
+        const uint32_t dg = (k[i] >> shift) & (R - 1);
+        const uint64_t peers = digit_peers<BITS>(dg, valid);
+        const uint32_t rank = __popcll(peers & lt_mask);
+        const uint32_t before = valid ? s_wcnt[wave][dg] : 0u;
+        off[i] = before + rank;
+        if (valid && rank == 0) s_wcnt[wave][dg] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // per digit: exclusive over waves and the tile's count, published at once
+    uint32_t total = 0;
+    if (tid < R) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < OS_WAVES; ++w) {
+            const uint32_t c = s_wcnt[w][tid];
+            s_wcnt[w][tid] = run;
+            run += c;
+        }
+        total = run;
+        os_store(&status[(size_t)t * R + tid], (t == 0 ? OS_INC : OS_AGG) | total);
+    }
+    const uint32_t dstart = os_block_excl(tid < R ? total : 0u, s_wsum);
+    const uint32_t dbase = os_block_excl(tid < R ? hist[tid] : 0u, s_wsum);
+    if (tid < R) {
+        s_dstart[tid] = dstart;
+        uint32_t excl = 0;
+        if (t > 0) {
+            // look back to the nearest inclusive prefix, OS_WINDOW predecessors
+            // per round trip (entries before tile 0 read as inclusive zero)
+            int64_t j = (int64_t)t - 1; // newest predecessor not yet consumed
+            uint32_t spins = 0;
+            for (;;) {
+                uint32_t sv[OS_WINDOW];
+#pragma unroll
+                for (int w = 0; w < OS_WINDOW; ++w)
+                    sv[w] = (j - w >= 0) ? os_load(&status[(size_t)(j - w) * R + tid]) : OS_INC;
+                int used = 0;
+                bool found = false, pending = false;
+#pragma unroll
+                for (int w = 0; w < OS_WINDOW; ++w) {
+                    if (found || pending) continue;
+                    const uint32_t f = sv[w] & ~OS_VAL;
+                    if (f == 0u) { pending = true; continue; } // not published yet: re-read from here
+                    excl += sv[w] & OS_VAL;
+                    ++used;
+                    found = (f == OS_INC);
+                }
+                if (found) break;
+                j -= used;
+                if (pending) {
+                    if (++spins > OS_SPIN_LIMIT) { atomicOr(err, 1u); break; }
+                    __builtin_amdgcn_s_sleep(1);
+                }
             }
-            const uint32_t rank = __popcll(peers & lt_mask);
-            const uint32_t cnt = __popcll(peers);
-            const uint32_t before = valid ? s_wcnt[wave][dg] : 0u;
-            off[i] = before + rank;
-            if (valid && rank == 0) s_wcnt[wave][dg] = before + cnt;
+            os_store(&status[(size_t)t * R + tid], OS_INC | (excl + total));
         }
-        __syncthreads();
-        // per digit: exclusive over waves, and the tile total
-        for (int d = tid; d < RS_RADIX; d += RS_BLOCK) {
-            uint32_t run = 0;
+        s_gofs[tid] = dbase + excl;
+    }
+    __syncthreads();
+    // digit-sorted tile in LDS, then each digit's run to its global position
 #pragma unroll
-            for (int w = 0; w < RS_WAVES; ++w) {
-                const uint32_t c = s_wcnt[w][d];
-                s_wcnt[w][d] = run;
-                run += c;
-            }
-            s_total[d] = run;
+    for (int i = 0; i < OS_ITEMS; ++i) {
+        const size_t idx = wbase + i * 64 + lane;
+        if (idx < n) {
+            const uint32_t dg = (k[i] >> shift) & (R - 1);
+            const uint32_t lp = s_dstart[dg] + s_wcnt[wave][dg] + off[i];
+            s_keys[lp] = k[i];
+            s_vals[lp] = v[i];
         }
-        __syncthreads();
-        // exclusive scan of the digit totals (one digit per thread)
-        {
-            const uint32_t x = tid < RS_RADIX ? s_total[tid] : 0u;
-            uint32_t incl = x;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t y = __shfl_up(incl, o, 64);
-                if (lane >= o) incl += y;
-            }
-            if (lane == 63) s_wsum[wave] = incl;
-            __syncthreads();
-            uint32_t wb = 0;
-            for (int w = 0; w < wave; ++w) wb += s_wsum[w];
-            if (tid < RS_RADIX) s_dstart[tid] = wb + incl - x;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < RS_ITEMS; ++i) {
-            const size_t idx = wbase + i * 64 + lane;
-            if (idx < n) {
-                const uint32_t dg = (k[i] >> shift) & (RS_RADIX - 1);
-                const uint32_t lp = s_dstart[dg] + s_wcnt[wave][dg] + off[i];
-                s_keys[lp] = k[i];
-                s_vals[lp] = v[i];
-            }
-        }
-        __syncthreads();
-        const size_t tbase = (size_t)t * RS_TILE;
-        const uint32_t nvalid = (uint32_t)min((size_t)RS_TILE, (size_t)n - tbase);
-        for (uint32_t j = tid; j < nvalid; j += RS_BLOCK) {
-            const uint32_t kk = s_keys[j];
-            const uint32_t dg = (kk >> shift) & (RS_RADIX - 1);
-            const uint32_t pos = s_gofs[dg] + (j - s_dstart[dg]);
-            keys_out[pos] = kk;
-            vals_out[pos] = s_vals[j];
-        }
-        __syncthreads();
-        for (int d = tid; d < RS_RADIX; d += RS_BLOCK) s_gofs[d] += s_total[d];
-        __syncthreads();
+    }
+    __syncthreads();
+    const uint32_t nvalid = (uint32_t)min((size_t)OS_TILE, (size_t)n - tbase);
+    for (uint32_t j = tid; j < nvalid; j += OS_BLOCK) {
+        const uint32_t kk = s_keys[j];
+        const uint32_t dg = (kk >> shift) & (R - 1);
+        const uint32_t pos = s_gofs[dg] + (j - s_dstart[dg]);
+        keys_out[pos] = kk;
+        vals_out[pos] = s_vals[j];
     }
 }
 
-int radix_blocks(uint32_t n_capacity)
-{
-    const uint32_t tiles = (n_capacity + RS_TILE - 1) / RS_TILE;
-    return (int)std::max<uint32_t>(1u, std::min<uint32_t>(tiles, 1024u));
-}
+__global__ void fill_u32_kernel(uint32_t *__restrict__ p, size_t n, uint32_t v);
 
-size_t radix_hist_words(int nblocks) { return (size_t)nblocks * RS_MAX_RADIX; }
-
-template <int B>
-static void radix_pass(hipStream_t st, const uint32_t *keys, const uint32_t *vals, uint32_t *keys_out,
-                       uint32_t *vals_out, uint32_t n_host, const uint32_t *n_dev, int nblocks, int shift,
-                       uint32_t *hist, uint32_t *scan_tmp)
-{
-    hipLaunchKernelGGL(radix_hist_kernel<B>, dim3(nblocks), dim3(RS_BLOCK), 0, st, keys, n_dev, n_host, shift,
-                       nblocks, hist);
-    scan_exclusive(st, hist, hist, (uint32_t)(nblocks * (1 << B)), nullptr, scan_tmp);
-    hipLaunchKernelGGL(radix_scatter_kernel<B>, dim3(nblocks), dim3(RS_BLOCK), 0, st, keys, vals, keys_out,
-                       vals_out, n_dev, n_host, shift, nblocks, hist);
-}
-
-// Sorts bits [0, end_bit) of the keys in passes of `digit_bits` (4..8; the
-// last pass takes what remains).  On return *keys/*vals point at the sorted
-// arrays (one of the two buffer pairs).  n_dev may be NULL (n_host used); with
-// n_dev the element count is read on the device (graph capture needs no
-// host read-back) and nblocks must cover the capacity.
-void radix_sort(hipStream_t st, uint32_t **keys, uint32_t **vals, uint32_t **keys_alt, uint32_t **vals_alt,
-                uint32_t n_host, const uint32_t *n_dev, int nblocks, int end_bit, uint32_t *hist, uint32_t *scan_tmp,
-                int digit_bits)
+size_t sort_temp_words(uint32_t n_capacity, int end_bit, int digit_bits)
 {
     digit_bits = std::min(8, std::max(4, digit_bits));
-    for (int shift = 0; shift < end_bit; shift += digit_bits) {
+    const size_t tiles = ((size_t)n_capacity + OS_TILE - 1) / OS_TILE;
+    return OS_STATUS + (size_t)os_passes(end_bit, digit_bits) * std::max<size_t>(tiles, 1) * OS_RADIX;
+}
+
+template <int B>
+static void os_launch_hist(hipStream_t st, const uint32_t *keys, uint32_t n_host, const uint32_t *n_dev, int blocks,
+                           int end_bit, uint32_t *hist)
+{
+    hipLaunchKernelGGL(os_hist_kernel<B>, dim3(blocks), dim3(OS_BLOCK), 0, st, keys, n_dev, n_host, end_bit, hist);
+}
+
+template <int B>
+static void os_launch_scatter(hipStream_t st, const uint32_t *keys, const uint32_t *vals, uint32_t *keys_out,
+                              uint32_t *vals_out, uint32_t n_host, const uint32_t *n_dev, int tiles, int shift,
+                              const uint32_t *hist, uint32_t *ctr, uint32_t *status, uint32_t *err)
+{
+    hipLaunchKernelGGL(os_scatter_kernel<B>, dim3(tiles), dim3(OS_BLOCK), 0, st, keys, vals, keys_out, vals_out, n_dev,
+                       n_host, shift, hist, ctr, status, err);
+}
+
+#define OS_DISPATCH(BITS, CALL)                                                                                    \
+    switch (BITS) {                                                                                                \
+    case 4: { constexpr int BB = 4; CALL; } break;                                                                 \
+    case 5: { constexpr int BB = 5; CALL; } break;                                                                 \
+    case 6: { constexpr int BB = 6; CALL; } break;                                                                 \
+    case 7: { constexpr int BB = 7; CALL; } break;                                                                 \
+    default: { constexpr int BB = 8; CALL; } break;                                                                \
+    }
+
+// Sorts bits [0, end_bit) of the keys in passes of `digit_bits` (4..8).  On
+// return *keys/*vals point at the sorted arrays (one of the two buffer pairs).
+// n_dev may be NULL (n_host used); with n_dev the element count is read on the
+// device (graph capture needs no host read-back) and n_capacity bounds it.
+// temp: sort_temp_words(n_capacity, end_bit, digit_bits) words.  *err (device)
+// gets bit 0 set if a look-back wait ran out of its bound.
+void radix_sort(hipStream_t st, uint32_t **keys, uint32_t **vals, uint32_t **keys_alt, uint32_t **vals_alt,
+                uint32_t n_host, const uint32_t *n_dev, uint32_t n_capacity, int end_bit, uint32_t *temp,
+                int digit_bits, uint32_t *err)
+{
+    digit_bits = std::min(8, std::max(4, digit_bits));
+    const uint32_t n_grid = n_dev ? n_capacity : n_host;
+    if (n_grid == 0 || end_bit <= 0) return;
+    const int P = os_passes(end_bit, digit_bits);
+    const int tiles = (int)((n_grid + OS_TILE - 1) / OS_TILE);
+    const size_t words = OS_STATUS + (size_t)P * tiles * OS_RADIX;
+    const size_t fb = std::min<size_t>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)fb), dim3(256), 0, st, temp, words, 0u);
+    const int hb = std::max(1, std::min(tiles, 1024));
+    OS_DISPATCH(digit_bits, os_launch_hist<BB>(st, *keys, n_host, n_dev, hb, end_bit, temp));
+    for (int p = 0; p < P; ++p) {
+        const int shift = p * digit_bits;
         const int b = std::min(digit_bits, end_bit - shift);
-        switch (b) {
-        case 1: case 2: case 3: case 4: radix_pass<4>(st, *keys, *vals, *keys_alt, *vals_alt, n_host, n_dev, nblocks, shift, hist, scan_tmp); break;
-        case 5: radix_pass<5>(st, *keys, *vals, *keys_alt, *vals_alt, n_host, n_dev, nblocks, shift, hist, scan_tmp); break;
-        case 6: radix_pass<6>(st, *keys, *vals, *keys_alt, *vals_alt, n_host, n_dev, nblocks, shift, hist, scan_tmp); break;
-        case 7: radix_pass<7>(st, *keys, *vals, *keys_alt, *vals_alt, n_host, n_dev, nblocks, shift, hist, scan_tmp); break;
-        default: radix_pass<8>(st, *keys, *vals, *keys_alt, *vals_alt, n_host, n_dev, nblocks, shift, hist, scan_tmp); break;
-        }
+        uint32_t *status = temp + OS_STATUS + (size_t)p * tiles * OS_RADIX;
+        OS_DISPATCH(b, os_launch_scatter<BB>(st, *keys, *vals, *keys_alt, *vals_alt, n_host, n_dev, tiles, shift,
+                                             temp + (size_t)p * OS_RADIX, temp + OS_CTR + p, status, err));
         std::swap(*keys, *keys_alt);
         std::swap(*vals, *vals_alt);
     }
@@ -343,36 +461,91 @@ void radix_sort(hipStream_t st, uint32_t **keys, uint32_t **vals, uint32_t **key
 
 // ------------------------------------------------------------- binning ----
 
-__global__ void gather_counts_kernel(uint32_t n, const uint32_t *__restrict__ sorted_ids,
-                                     const uint32_t *__restrict__ counts, uint32_t *__restrict__ out)
+// Pairs of 256 consecutive instances in depth order, written cooperatively:
+// their pair ranges are contiguous ([offsets[r], offsets[r] + counts[r]) in
+// rank order), so the workgroup strides over the whole run with one pair per
+// thread (coalesced stores) and finds each pair's instance by a binary search
+// over the offsets staged in LDS.  Within an instance the pairs run row-major
+// over its tile rectangle (over the kept tiles of a rectangle of at most 64
+// tiles, whose mask the preprocess wrote).  Instance id = view * n_convex + convex; the view's
+// tiles start at its tile_off.
+constexpr int EMIT_BLOCK = 256;
+
+// Position of the q-th set bit of m (q < popcount(m)).
+__device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t q)
 {
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n) out[r] = counts[sorted_ids[r]];
+    uint32_t pos = 0;
+    uint32_t w = (uint32_t)m;
+    const uint32_t c32 = __popc(w);
+    if (q >= c32) { q -= c32; w = (uint32_t)(m >> 32); pos = 32; }
+#pragma unroll
+    for (int half = 16; half >= 1; half >>= 1) {
+        const uint32_t c = __popc(w & ((1u << half) - 1u));
+        if (q >= c) { q -= c; w >>= half; pos += half; }
+    }
+    return pos;
 }
 
-// One thread per (view, convex) instance in depth order: write its (global
-// tile, instance) pairs, row-major over its tile rectangle.  Instance id =
-// view * n_convex + convex; the view's tiles start at its tile_off.
-__global__ void emit_pairs_kernel(uint32_t n, uint32_t n_convex, const uint32_t *__restrict__ sorted_ids,
-                                  const uint32_t *__restrict__ offsets, const uint2 *__restrict__ rects,
-                                  const FrameHeader *__restrict__ frame, uint32_t capacity,
-                                  uint32_t *__restrict__ pair_tiles, uint32_t *__restrict__ pair_ids)
+__global__ __launch_bounds__(EMIT_BLOCK) void emit_pairs_kernel(
+    uint32_t n, uint32_t n_convex, const uint32_t *__restrict__ sorted_ids, const uint32_t *__restrict__ offsets,
+    const uint32_t *__restrict__ counts_sorted, const uint2 *__restrict__ rects, const uint64_t *__restrict__ tmasks,
+    const FrameHeader *__restrict__ frame, uint32_t capacity, uint32_t *__restrict__ pair_tiles,
+    uint32_t *__restrict__ pair_ids)
 {
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    const uint32_t id = sorted_ids[r];
-    const uint2 rc = rects[id];
-    const int tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
-    if (tx0 > tx1 || ty0 > ty1) return;
-    const ViewDesc &vd = reinterpret_cast<const ViewDesc *>(frame + 1)[id / n_convex];
-    const int tiles_x = vd.tiles_x, toff = vd.tile_off;
-    uint32_t off = offsets[r];
-    for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx, ++off)
-            if (off < capacity) {
-                pair_tiles[off] = (uint32_t)(toff + ty * tiles_x + tx);
-                pair_ids[off] = id;
-            }
+    __shared__ uint32_t s_off[EMIT_BLOCK];
+    __shared__ uint32_t s_id[EMIT_BLOCK];
+    __shared__ uint32_t s_x0w[EMIT_BLOCK];  // tx0 | rect width << 16
+    __shared__ uint32_t s_base[EMIT_BLOCK]; // global tile of the rectangle's first row start: toff + ty0 * tiles_x
+    __shared__ uint32_t s_tx[EMIT_BLOCK];   // the view's tiles_x
+    __shared__ uint64_t s_mask[EMIT_BLOCK]; // kept tiles of a rectangle of <= 64 tiles (else unused)
+    __shared__ uint32_t s_small[EMIT_BLOCK];
+    __shared__ uint32_t s_end;
+    const uint32_t r0 = blockIdx.x * EMIT_BLOCK;
+    const int cnt = (int)min((uint32_t)EMIT_BLOCK, n - r0);
+    const int tid = threadIdx.x;
+    const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
+    if (tid < cnt) {
+        const uint32_t r = r0 + tid;
+        const uint32_t id = sorted_ids[r];
+        const uint32_t off = offsets[r];
+        s_off[tid] = off;
+        s_id[tid] = id;
+        uint32_t x0w = 0, base = 0, tx = 1, small = 0;
+        uint64_t mask = 0;
+        if (counts_sorted[r] > 0) {
+            const uint2 rc = rects[id];
+            const uint32_t tx0 = rc.x & 0xFFFFu, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFFu, ty1 = rc.y >> 16;
+            const ViewDesc &vd = views[id / n_convex];
+            tx = (uint32_t)vd.tiles_x;
+            x0w = tx0 | ((tx1 - tx0 + 1) << 16);
+            base = (uint32_t)vd.tile_off + ty0 * tx;
+            small = (tx1 - tx0 + 1) * (ty1 - ty0 + 1) <= 64u;
+            if (small) mask = tmasks[id];
+        }
+        s_x0w[tid] = x0w;
+        s_base[tid] = base;
+        s_tx[tid] = tx;
+        s_mask[tid] = mask;
+        s_small[tid] = small;
+        if (tid == cnt - 1) s_end = off + counts_sorted[r];
+    }
+    __syncthreads();
+    const uint32_t p0 = s_off[0], p1 = min(s_end, capacity);
+    for (uint32_t p = p0 + tid; p < p1; p += EMIT_BLOCK) {
+        // last entry with s_off <= p (entries with no pairs share the next one's offset)
+        int lo = 0, hi = cnt - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= p) lo = mid;
+            else hi = mid - 1;
+        }
+        uint32_t q = p - s_off[lo];
+        if (s_small[lo]) q = nth_set_bit(s_mask[lo], q); // the q-th kept tile of the rectangle
+        const uint32_t x0w = s_x0w[lo], w = x0w >> 16;
+        const uint32_t row = q / w, col = q - row * w;
+        pair_tiles[p] = s_base[lo] + row * s_tx[lo] + (x0w & 0xFFFFu) + col;
+        pair_ids[p] = s_id[lo];
+    }
 }
 
 // Pair count that fits the buffers, and the overflow flag (for fixed-capacity frames).
@@ -421,20 +594,15 @@ void launch_fill_u32(hipStream_t st, uint32_t *p, size_t n, uint32_t v)
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
 }
 
-void launch_gather_counts(hipStream_t st, uint32_t n, const uint32_t *sorted_ids, const uint32_t *counts,
-                          uint32_t *out)
-{
-    if (n == 0) return;
-    hipLaunchKernelGGL(gather_counts_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, sorted_ids, counts, out);
-}
-
 void launch_emit_pairs(hipStream_t st, uint32_t n, uint32_t n_convex, const uint32_t *sorted_ids,
-                       const uint32_t *offsets, const uint2 *rects, const FrameHeader *views, uint32_t capacity,
-                       uint32_t *pair_tiles, uint32_t *pair_ids)
+                       const uint32_t *offsets, const uint32_t *counts_sorted, const uint2 *rects,
+                       const uint64_t *tmasks, const FrameHeader *views, uint32_t capacity, uint32_t *pair_tiles,
+                       uint32_t *pair_ids)
 {
     if (n == 0) return;
-    hipLaunchKernelGGL(emit_pairs_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, n_convex, sorted_ids, offsets,
-                       rects, views, capacity, pair_tiles, pair_ids);
+    hipLaunchKernelGGL(emit_pairs_kernel, dim3((n + EMIT_BLOCK - 1) / EMIT_BLOCK), dim3(EMIT_BLOCK), 0, st, n,
+                       n_convex, sorted_ids, offsets, counts_sorted, rects, tmasks, views, capacity, pair_tiles,
+                       pair_ids);
 }
 
 void launch_clamp_pairs(hipStream_t st, uint32_t *counters, uint32_t capacity)
