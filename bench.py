@@ -13,6 +13,7 @@ Default workload: 1M convexes (K=6, SH degree 3, 64-component mixture) at
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -186,6 +187,28 @@ def bench_serving(rates, duration):
     return out
 
 
+def counter_traffic(stage, workload):
+    """HBM bytes per launch of a stage's kernel from the committed rocprofv3
+    counters (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by what the same
+    counters read for a device copy of known size), or None when there are none
+    for this workload or the kernel's source has changed since they were taken."""
+    if workload != "c3":
+        return None
+    path = os.path.join(ROOT, "profiles", "counters_c3_1M_1080p.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    for name, k in d["kernels"].items():
+        if name.startswith(stage + "_kernel"):
+            with open(os.path.join(ROOT, k["source"]), "rb") as f:
+                if hashlib.sha1(f.read()).hexdigest() != k["source_sha1"]:
+                    return None
+            return (k["fetch_kib"] * d["fetch_scale"] + k["write_kib"] * d["write_scale"]) * 1024.0
+    return None
+
+
 def cpu_baseline(scene, cam, target, sample):
     """The FP64 oracle, as it stands, on a seeded pixel sample of the workload."""
     import oracle
@@ -221,7 +244,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c3")
-    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
     ap.add_argument("--forms", default="plain,batched,serving", help="comma list of plain, batched, serving")
@@ -309,7 +332,7 @@ def main():
         "stages_ms": {s: round(v, 4) for s, v in avg.items()},
         "work": {"pairs": stats["pairs"], "evaluated": stats["evaluated"], "full": stats["full"]},
         "roofline": {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                     "frac": achieved / peak, "traffic": None},
+                     "frac": achieved / peak, "traffic": counter_traffic(dom, args.workload)},
     }
     if args.copy_calibration:
         a = torch.ones(64 << 20, device=dev)
