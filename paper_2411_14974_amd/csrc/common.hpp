@@ -82,6 +82,23 @@ constexpr int MAX_VIEWS = 256;
 constexpr int NUM_QUEUES = 8; // one work queue per XCD
 
 // Device counters of one frame (u32 words).
+// Per-instance binning record (16 bytes): the tile rectangle, tx0 | ty0 << 16
+// and tx1 | ty1 << 16 (empty when tx0 > tx1), and the mask of kept tiles of a
+// rectangle of at most 64 tiles (bit (ty - ty0) * width + (tx - tx0)); larger
+// rectangles keep every tile.
+__host__ __device__ inline uint4 make_bin(int tx0, int ty0, int tx1, int ty1, uint64_t mask)
+{
+    return make_uint4((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16), (uint32_t)mask,
+                      (uint32_t)(mask >> 32));
+}
+__device__ inline uint32_t bin_count(uint4 b)
+{
+    const int tx0 = (int)(b.x & 0xFFFFu), ty0 = (int)(b.x >> 16), tx1 = (int)(b.y & 0xFFFFu), ty1 = (int)(b.y >> 16);
+    if (tx0 > tx1 || ty0 > ty1) return 0u;
+    const uint32_t area = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    return area <= 64u ? (uint32_t)(__popc(b.z) + __popc(b.w)) : area;
+}
+
 // CNT_SORT_ERR: a radix-sort look-back wait ran out of its bound (never expected)
 // CNT_SCAN_TILE: tile claims of the pair-offset scan, whose look-back status
 // words (u64 per tile) follow the CNT_WORDS counters in the same buffer

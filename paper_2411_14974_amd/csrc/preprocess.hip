@@ -47,8 +47,8 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
     int n, int deg, const float *__restrict__ points, const float *__restrict__ delta,
     const float *__restrict__ sigma, const float *__restrict__ opacity, const float *__restrict__ sh,
     const FrameHeader *__restrict__ frame, RenderArgs ra, uint8_t *__restrict__ records, uint32_t *__restrict__ keys,
-    uint32_t *__restrict__ ids, uint2 *__restrict__ rects, uint32_t *__restrict__ counts,
-    uint64_t *__restrict__ tmasks, uint32_t *__restrict__ hullpk, DebugConvex *__restrict__ dbg)
+    uint32_t *__restrict__ ids, uint4 *__restrict__ bins, uint32_t *__restrict__ hullpk,
+    DebugConvex *__restrict__ dbg)
 {
     // the block's points arrive through LDS (coalesced loads; odd row stride)
     constexpr int PS = 3 * K + 1;
@@ -95,7 +95,6 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
     int T = 0;
     int tx0 = 1, tx1 = 0, ty0 = 1, ty1 = 0;
     uint64_t tmask = 0;  // tiles of a rectangle of <= 64 tiles that keep the convex (row-major)
-    int ntiles_kept = 0;
     double dd = 0.0, dp = 0.0, sp = 0.0;
     float rgb[3] = {0.f, 0.f, 0.f};
     int clampmask = 0;
@@ -299,7 +298,6 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
                     // A rectangle one tile wide or high keeps every tile: the
                     // polygon is connected and its bounding box spans the strip.
                     const int tw = tx1 - tx0 + 1, th = ty1 - ty0 + 1;
-                    ntiles_kept = tw * th;
                     tmask = (tw * th < 64) ? ((1ull << (tw * th)) - 1ull) : ~0ull;
                     if (tw >= 2 && th >= 2 && tw * th <= 64) {
                         // the lines as stored, into registers once (slots past T unused)
@@ -330,7 +328,6 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
                             }
                         }
                         tmask = m;
-                        ntiles_kept = __popcll(m);
                     }
                 }
             }
@@ -343,10 +340,7 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
 
     const bool has_tiles = status == ST_VISIBLE && tx0 <= tx1 && ty0 <= ty1;
     keys[inst] = status == ST_VISIBLE ? key : KEY_CULLED;
-    counts[inst] = has_tiles ? (uint32_t)ntiles_kept : 0u;
-    tmasks[inst] = tmask;
-    rects[inst] = has_tiles ? make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16))
-                         : make_uint2(1u, 0u);
+    bins[inst] = has_tiles ? make_bin(tx0, ty0, tx1, ty1, tmask) : make_bin(1, 0, 0, 0, 0);
     hullpk[inst] = (status == ST_VISIBLE || status == ST_FAINT) ? (packed | ((uint32_t)T << 28)) : 0u;
 
     if constexpr (DBG) {
@@ -652,19 +646,18 @@ __global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
 void launch_preprocess_fwd(hipStream_t st, int n, int nviews, int K, int deg, const float *points,
                            const float *delta, const float *sigma, const float *opacity, const float *sh,
                            const FrameHeader *views, const RenderArgs &ra, uint8_t *records, uint32_t *keys,
-                           uint32_t *ids, uint2 *rects, uint32_t *counts, uint64_t *tmasks, uint32_t *hullpk,
-                           DebugConvex *dbg)
+                           uint32_t *ids, uint4 *bins, uint32_t *hullpk, DebugConvex *dbg)
 {
     if (n <= 0 || nviews <= 0) return;
     dim3 grid((n + PF_BLOCK - 1) / PF_BLOCK, nviews), block(PF_BLOCK);
     if (dbg)
         CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_fwd_kernel<KK, true>), grid, block, 0, st, n, deg, points,
-                                            delta, sigma, opacity, sh, views, ra, records, keys, ids, rects, counts,
-                                            tmasks, hullpk, dbg))
+                                            delta, sigma, opacity, sh, views, ra, records, keys, ids, bins, hullpk,
+                                            dbg))
     else
         CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_fwd_kernel<KK, false>), grid, block, 0, st, n, deg, points,
-                                            delta, sigma, opacity, sh, views, ra, records, keys, ids, rects, counts,
-                                            tmasks, hullpk, dbg))
+                                            delta, sigma, opacity, sh, views, ra, records, keys, ids, bins, hullpk,
+                                            dbg))
 }
 
 void launch_preprocess_bwd(hipStream_t st, int n, int nviews, int K, int deg, const float *points,

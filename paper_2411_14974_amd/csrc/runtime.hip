@@ -19,7 +19,7 @@
 namespace cs {
 void launch_preprocess_fwd(hipStream_t, int, int, int, int, const float *, const float *, const float *,
                            const float *, const float *, const FrameHeader *, const RenderArgs &, uint8_t *,
-                           uint32_t *, uint32_t *, uint2 *, uint32_t *, uint64_t *, uint32_t *, DebugConvex *);
+                           uint32_t *, uint32_t *, uint4 *, uint32_t *, DebugConvex *);
 void launch_preprocess_bwd(hipStream_t, int, int, int, int, const float *, const float *, const float *,
                            const float *, const FrameHeader *, const uint8_t *, const uint32_t *, const float *,
                            float *, float *, float *, float *, float *);
@@ -27,11 +27,13 @@ void radix_sort(hipStream_t, uint32_t **, uint32_t **, uint32_t **, uint32_t **,
                 uint32_t *, int, uint32_t *);
 size_t sort_temp_words(uint32_t, int, int);
 size_t scan_status_words(uint32_t);
-void launch_gather_scan(hipStream_t, uint32_t, const uint32_t *, const uint32_t *, uint32_t *, uint32_t *, uint32_t *);
+void launch_gather_scan(hipStream_t, uint32_t, const uint32_t *, const uint4 *, uint4 *, uint32_t *, uint32_t *,
+                        uint32_t *);
 void launch_fill_u32(hipStream_t, uint32_t *, size_t, uint32_t);
 void launch_emit_pairs(hipStream_t, uint32_t, uint32_t, const uint32_t *, const uint32_t *, const uint32_t *,
-                       const uint2 *, const uint64_t *, const FrameHeader *, uint32_t, uint32_t *, uint32_t *);
-void launch_clamp_pairs(hipStream_t, uint32_t *, uint32_t);
+                       const uint4 *, const FrameHeader *, uint32_t, uint32_t *, uint32_t *);
+void launch_prepare_tail(hipStream_t, uint32_t *, uint32_t, uint32_t *, size_t);
+void launch_zero_ranges(hipStream_t, uint32_t *, size_t, uint32_t *, size_t, uint32_t *, size_t);
 void launch_tile_length_keys(hipStream_t, uint32_t, const uint2 *, uint32_t *, uint32_t *);
 void launch_tile_ranges(hipStream_t, const uint32_t *, uint32_t, const uint32_t *, uint32_t, uint2 *);
 void launch_render_fwd(hipStream_t, int, int, const FrameHeader *, const uint32_t *, uint32_t, uint32_t *,
@@ -102,6 +104,7 @@ Frame::~Frame()
     for (void *p : allocs)
         if (p) (void)hipFreeAsync(p, st);
     if (counters_ev) (void)hipEventSynchronize(counters_ev), (void)hipEventDestroy(counters_ev);
+    if (mcount_ev) (void)hipEventSynchronize(mcount_ev), (void)hipEventDestroy(mcount_ev);
     if (h_counters) (void)hipHostFree(h_counters);
     if (ready) (void)hipEventDestroy(ready);
 }
@@ -145,6 +148,8 @@ int Frame::init_async_readback()
 int Frame::init(int n_, int K_, int deg_, int V_, size_t tiles, size_t pix, hipStream_t s, HostRing *r)
 {
     n = n_; K = K_; deg = deg_; V = V_; st = s; ring = r;
+    if (hipEventCreateWithFlags(&mcount_ev, hipEventDisableTiming) != hipSuccess)
+        return fail(CS_EHIP, "event creation failed");
     cap_inst = (size_t)n * V;
     cap_tiles = std::max<size_t>(tiles, 1);
     cap_pix = std::max<size_t>(pix, 1);
@@ -156,12 +161,11 @@ int Frame::init(int n_, int K_, int deg_, int V_, size_t tiles, size_t pix, hipS
     CS_A(ids, cap_inst * 4);
     CS_A(keys_alt, cap_inst * 4);
     CS_A(ids_alt, cap_inst * 4);
-    CS_A(counts, cap_inst * 4);
     CS_A(counts_sorted, cap_inst * 4);
     CS_A(offsets, cap_inst * 4);
     CS_A(hullpk, cap_inst * 4);
-    CS_A(rects, cap_inst * 8);
-    CS_A(tmasks, cap_inst * 8);
+    CS_A(bins, cap_inst * 16);
+    CS_A(bins_sorted, cap_inst * 16);
     CS_A(ranges, cap_tiles * 8);
     CS_A(ord_k, cap_tiles * 4);
     CS_A(ord_v, cap_tiles * 4);
@@ -370,15 +374,59 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
     F.tile = kn.tile;
     F.longest = kn.longest;
     F.digits = kn.digits;
-    launch_fill_u32(st, F.counters, F.counter_words, 0u);
-    launch_fill_u32(st, reinterpret_cast<uint32_t *>(F.evalcount), 4, 0u);
+    launch_zero_ranges(st, F.counters, F.counter_words, reinterpret_cast<uint32_t *>(F.evalcount), 4, nullptr, 0);
     tm.begin();
     launch_preprocess_fwd(st, n, F.V, F.K, F.deg, sc->points, sc->delta, sc->sigma, sc->opacity, sc->sh, F.d_frame,
-                          ra, F.records, F.keys, F.ids, F.rects, F.counts, F.tmasks, F.hullpk, nullptr);
+                          ra, F.records, F.keys, F.ids, F.bins, F.hullpk, nullptr);
     tm.end(CS_STAGE_PREPROCESS);
 
     uint32_t *keys = F.keys, *ids = F.ids, *keys_alt = F.keys_alt, *ids_alt = F.ids_alt;
+    // Everything after the pair count: emission, tile sort, ranges, tile order,
+    // compositing.  m_dev: the device-side pair count clamped to the buffers, or
+    // NULL when the count (M_host) is known here.
+    auto tail = [&](uint32_t M_host, const uint32_t *m_dev) {
+        launch_prepare_tail(st, F.counters, (uint32_t)F.cap_pairs, reinterpret_cast<uint32_t *>(F.ranges),
+                            2 * F.cap_tiles);
+        uint32_t *pt = F.pt, *pi = F.pi, *pt_alt = F.pt_alt, *pi_alt = F.pi_alt;
+        if (ninst > 0) {
+            tm.begin();
+            launch_emit_pairs(st, ninst, (uint32_t)n, ids, F.offsets, F.counts_sorted, F.bins_sorted, F.d_frame,
+                              (uint32_t)F.cap_pairs, pt, pi);
+            tm.end(CS_STAGE_EMIT);
+            const int tile_bits = std::max(1, ilog2_ceil(F.cap_tiles));
+            tm.begin();
+            radix_sort(st, &pt, &pi, &pt_alt, &pi_alt, M_host, m_dev, (uint32_t)F.cap_pairs, tile_bits, F.hist,
+                       kn.digits, F.counters + CNT_SORT_ERR);
+            tm.end(CS_STAGE_TILE_SORT);
+            tm.begin();
+            launch_tile_ranges(st, pt, M_host, m_dev, m_dev ? (uint32_t)F.cap_pairs : M_host, F.ranges);
+            tm.end(CS_STAGE_RANGES);
+        }
+        F.sorted_ids = pi;
+        F.order = nullptr;
+        if (kn.longest) {
+            uint32_t *ok = F.ord_k, *ov = F.ord_v, *ok2 = F.ord_k_alt, *ov2 = F.ord_v_alt;
+            tm.begin();
+            launch_tile_length_keys(st, (uint32_t)F.cap_tiles, F.ranges, ok, ov);
+            radix_sort(st, &ok, &ov, &ok2, &ov2, (uint32_t)F.cap_tiles, nullptr, (uint32_t)F.cap_tiles, 16, F.hist,
+                       8, F.counters + CNT_SORT_ERR);
+            tm.end(CS_STAGE_ORDER);
+            F.order = ov;
+        }
+        tm.begin();
+        launch_render_fwd(st, F.K, kn.tile, F.d_frame, F.order, (uint32_t)F.cap_tiles, F.counters, F.ranges,
+                          F.sorted_ids, F.records, ra, F.pixstate, F.evalcount);
+        tm.end(CS_STAGE_RENDER_FWD);
+    };
+
+    // A frame that already holds pair buffers (a reused one) runs the tail at
+    // once on the device-side count; the host reads the count back while the
+    // GPU works and, in the rare case that it did not fit, grows the buffers
+    // and runs the tail again before returning.  A new frame waits for the
+    // count to size its buffers.
+    const bool speculative = !device_count && ninst > 0 && F.pt != nullptr;
     uint32_t M = 0;
+    uint32_t *hw = F.ring->h_word;
     if (ninst > 0) {
         if (!F.pt) { // first sizing: the sort temporaries come with the pair buffers
             int r = F.ensure_pairs(1);
@@ -388,57 +436,38 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
         radix_sort(st, &keys, &ids, &keys_alt, &ids_alt, ninst, nullptr, ninst, 32, F.hist, 8, F.counters + CNT_SORT_ERR);
         tm.end(CS_STAGE_DEPTH_SORT);
         tm.begin();
-        launch_gather_scan(st, ninst, ids, F.counts, F.counts_sorted, F.offsets, F.counters);
+        launch_gather_scan(st, ninst, ids, F.bins, F.bins_sorted, F.counts_sorted, F.offsets, F.counters);
         tm.end(CS_STAGE_BIN_SCAN);
         if (!device_count) {
-            uint32_t *hw = F.ring->h_word;
             hipError_t e = hipMemcpyAsync(hw, F.counters + CNT_PAIRS, 4, hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e == hipSuccess) e = speculative ? hipEventRecord(F.mcount_ev, st) : hipStreamSynchronize(st);
             if (e != hipSuccess) return fail(CS_EHIP, "pair count read-back: %s", hipGetErrorString(e));
-            M = hw[0];
-            int r = F.ensure_pairs((size_t)std::ceil(M * margin));
-            if (r) return r;
-            F.npairs = M;
+            if (!speculative) {
+                M = hw[0];
+                int r = F.ensure_pairs((size_t)std::ceil(M * margin));
+                if (r) return r;
+                F.npairs = M;
+            }
         }
     }
     if (!F.pt) {
         int r = F.ensure_pairs(1);
         if (r) return r;
     }
-    launch_clamp_pairs(st, F.counters, (uint32_t)F.cap_pairs);
-    const uint32_t *m_dev = device_count ? F.counters + CNT_PAIRS_EFF : nullptr;
-    launch_fill_u32(st, reinterpret_cast<uint32_t *>(F.ranges), 2 * F.cap_tiles, 0u);
-    uint32_t *pt = F.pt, *pi = F.pi, *pt_alt = F.pt_alt, *pi_alt = F.pi_alt;
-    if (ninst > 0) {
-        tm.begin();
-        launch_emit_pairs(st, ninst, (uint32_t)n, ids, F.offsets, F.counts_sorted, F.rects, F.tmasks, F.d_frame,
-                          (uint32_t)F.cap_pairs,
-                          pt, pi);
-        tm.end(CS_STAGE_EMIT);
-        const int tile_bits = std::max(1, ilog2_ceil(F.cap_tiles));
-        tm.begin();
-        radix_sort(st, &pt, &pi, &pt_alt, &pi_alt, M, m_dev, (uint32_t)F.cap_pairs, tile_bits, F.hist, kn.digits,
-                   F.counters + CNT_SORT_ERR);
-        tm.end(CS_STAGE_TILE_SORT);
-        tm.begin();
-        launch_tile_ranges(st, pt, M, m_dev, device_count ? (uint32_t)F.cap_pairs : M, F.ranges);
-        tm.end(CS_STAGE_RANGES);
+    tail(M, (device_count || speculative) ? F.counters + CNT_PAIRS_EFF : nullptr);
+    if (speculative) {
+        hipError_t e = hipEventSynchronize(F.mcount_ev);
+        if (e != hipSuccess) return fail(CS_EHIP, "pair count read-back: %s", hipGetErrorString(e));
+        M = hw[0];
+        F.npairs = M;
+        if (M > F.cap_pairs) { // did not fit: grow, reset the tile queues and counts, run the tail again
+            int r = F.ensure_pairs((size_t)std::ceil(M * margin));
+            if (r) return r;
+            launch_zero_ranges(st, F.counters + CNT_QUEUE, 2 * NUM_QUEUES, reinterpret_cast<uint32_t *>(F.evalcount), 4,
+                               nullptr, 0);
+            tail(M, nullptr);
+        }
     }
-    F.sorted_ids = pi;
-    F.order = nullptr;
-    if (kn.longest) {
-        uint32_t *ok = F.ord_k, *ov = F.ord_v, *ok2 = F.ord_k_alt, *ov2 = F.ord_v_alt;
-        tm.begin();
-        launch_tile_length_keys(st, (uint32_t)F.cap_tiles, F.ranges, ok, ov);
-        radix_sort(st, &ok, &ov, &ok2, &ov2, (uint32_t)F.cap_tiles, nullptr, (uint32_t)F.cap_tiles, 16, F.hist, 8,
-                   F.counters + CNT_SORT_ERR);
-        tm.end(CS_STAGE_ORDER);
-        F.order = ov;
-    }
-    tm.begin();
-    launch_render_fwd(st, F.K, kn.tile, F.d_frame, F.order, (uint32_t)F.cap_tiles, F.counters, F.ranges,
-                      F.sorted_ids, F.records, ra, F.pixstate, F.evalcount);
-    tm.end(CS_STAGE_RENDER_FWD);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(CS_EHIP, "kernel launch: %s", hipGetErrorString(e));
     return CS_OK;
@@ -449,8 +478,8 @@ int enqueue_backward(Frame &F, const cs_scene *sc, const cs_grads *g, const Rend
     hipStream_t st = F.st;
     int r = F.ensure_acc();
     if (r) return r;
-    launch_fill_u32(st, reinterpret_cast<uint32_t *>(F.acc), F.cap_inst * acc_stride(F.K), 0u);
-    launch_fill_u32(st, F.counters + CNT_QUEUE, 2 * NUM_QUEUES, 0u);
+    launch_zero_ranges(st, reinterpret_cast<uint32_t *>(F.acc), F.cap_inst * acc_stride(F.K), F.counters + CNT_QUEUE,
+                       2 * NUM_QUEUES, nullptr, 0);
     tm.begin();
     launch_render_bwd(st, F.K, F.tile, F.d_frame, F.order, (uint32_t)F.cap_tiles, F.counters, F.ranges, F.sorted_ids,
                       F.records, ra, F.pixstate, F.acc);
@@ -663,7 +692,7 @@ int cs_render_forward(cs_ctx *ctx, const cs_scene *sc, const cs_camera *cam, con
     CS_TRY(acquire_frame(ctx, sc->n, sc->k, sc->sh_degree, 1, vp.hdr.total_tiles, (size_t)vp.hdr.total_pix, st, &F));
     int r = F->upload_views(vp.hdr, vp.views.data());
     StageTimer tm(ctx, st, prm && (prm->flags & CS_FLAG_TIMING));
-    if (!r) r = enqueue_forward(ctx, *F, sc, ra, kn, false, 1.0, tm);
+    if (!r) r = enqueue_forward(ctx, *F, sc, ra, kn, false, 1.3, tm);
     if (r) {
         delete F;
         return r;
@@ -727,7 +756,7 @@ int cs_render_forward_batch(cs_ctx *ctx, const cs_scene *sc, int32_t n_views, co
         CS_TRY(acquire_frame(ctx, sc->n, sc->k, sc->sh_degree, n_views, vp.hdr.total_tiles,
                              (size_t)vp.hdr.total_pix, st, &F));
         int r = F->upload_views(vp.hdr, vp.views.data());
-        if (!r) r = enqueue_forward(ctx, *F, sc, ra, kn, false, 1.0, tm);
+        if (!r) r = enqueue_forward(ctx, *F, sc, ra, kn, false, 1.3, tm);
         if (r) { delete F; return r; }
         if (state_out) {
             cs_fwd_state *s = new cs_fwd_state;
@@ -1008,7 +1037,7 @@ int cs_debug_preprocess(cs_ctx *ctx, const cs_scene *sc, const cs_camera *cam, c
     DebugConvex *dbg = nullptr;
     CS_TRY(F.alloc((void **)&dbg, sizeof(DebugConvex) * (size_t)sc->n));
     launch_preprocess_fwd(st, sc->n, 1, sc->k, sc->sh_degree, sc->points, sc->delta, sc->sigma, sc->opacity, sc->sh,
-                          F.d_frame, ra, F.records, F.keys, F.ids, F.rects, F.counts, F.tmasks, F.hullpk, dbg);
+                          F.d_frame, ra, F.records, F.keys, F.ids, F.bins, F.hullpk, dbg);
     CS_HIP(hipGetLastError());
     CS_HIP(hipMemcpyAsync(out, dbg, sizeof(DebugConvex) * (size_t)sc->n, hipMemcpyDeviceToHost, st));
     CS_HIP(hipStreamSynchronize(st));

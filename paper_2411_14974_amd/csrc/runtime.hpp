@@ -40,9 +40,8 @@ struct Frame {
     FrameHeader *d_frame = nullptr; // header + ViewDesc[MAX_VIEWS]
     uint8_t *records = nullptr;
     uint32_t *keys = nullptr, *ids = nullptr, *keys_alt = nullptr, *ids_alt = nullptr;
-    uint32_t *counts = nullptr, *counts_sorted = nullptr, *offsets = nullptr, *hullpk = nullptr;
-    uint2 *rects = nullptr;
-    uint64_t *tmasks = nullptr; // kept tiles of small tile rectangles (row-major bits)
+    uint32_t *counts_sorted = nullptr, *offsets = nullptr, *hullpk = nullptr;
+    uint4 *bins = nullptr, *bins_sorted = nullptr; // binning records by instance / in depth order
     uint32_t *hist = nullptr; // radix sort temporaries (histograms, tile counters, look-back status)
     uint32_t *pt = nullptr, *pi = nullptr, *pt_alt = nullptr, *pi_alt = nullptr;
     uint2 *ranges = nullptr;
@@ -54,6 +53,7 @@ struct Frame {
     unsigned long long *evalcount = nullptr;
     uint32_t *h_counters = nullptr; // pinned read-back of the counters
     hipEvent_t counters_ev = nullptr;
+    hipEvent_t mcount_ev = nullptr; // after the pair count's read-back (reused frames)
 
     // results of the last forward pass (point into the buffers above)
     uint32_t *sorted_ids = nullptr;

@@ -62,7 +62,8 @@ __device__ uint32_t block_scan_lds(uint32_t *s, uint32_t *s_wave)
 
 // Pair counts in depth order and their exclusive scan (the pair offsets), in
 // one pass: each workgroup claims the next tile of SCAN_TILE ranks, gathers
-// counts[sorted_ids[r]], scans them in LDS, publishes the tile's sum and
+// the binning records bins[sorted_ids[r]] (copied out in depth order for the
+// pair emission) and their pair counts, scans the counts in LDS, publishes the tile's sum and
 // finds its prefix by a decoupled look-back in which one wave reads 64
 // predecessors' 64-bit status words at a time.  The last tile stores the total.
 constexpr uint64_t SS_AGG = 1ull << 62, SS_INC = 2ull << 62, SS_VAL = SS_AGG - 1ull;
@@ -78,9 +79,9 @@ __device__ __forceinline__ void ss_store(uint64_t *p, uint64_t v)
 }
 
 __global__ __launch_bounds__(SCAN_BLOCK) void gather_scan_kernel(
-    uint32_t n, const uint32_t *__restrict__ sorted_ids, const uint32_t *__restrict__ counts,
-    uint32_t *__restrict__ counts_sorted, uint32_t *__restrict__ offsets, uint32_t *__restrict__ counters,
-    uint64_t *__restrict__ status)
+    uint32_t n, const uint32_t *__restrict__ sorted_ids, const uint4 *__restrict__ bins,
+    uint4 *__restrict__ bins_sorted, uint32_t *__restrict__ counts_sorted, uint32_t *__restrict__ offsets,
+    uint32_t *__restrict__ counters, uint64_t *__restrict__ status)
 {
     __shared__ uint32_t s[SCAN_TILE + SCAN_TILE / 32];
     __shared__ uint32_t s_wave[SCAN_BLOCK / 64];
@@ -97,7 +98,9 @@ __global__ __launch_bounds__(SCAN_BLOCK) void gather_scan_kernel(
         const size_t i = base + (size_t)k * SCAN_BLOCK + tid;
         uint32_t c = 0;
         if (i < n) {
-            c = counts[sorted_ids[i]];
+            const uint4 b = bins[sorted_ids[i]]; // the one random read per instance
+            c = bin_count(b);
+            bins_sorted[i] = b;
             counts_sorted[i] = c;
         }
         s[lds_pad(k * SCAN_BLOCK + tid)] = c;
@@ -151,15 +154,15 @@ __global__ __launch_bounds__(SCAN_BLOCK) void gather_scan_kernel(
 // 32-bit words of the scan's look-back status (u64 per tile of SCAN_TILE ranks).
 size_t scan_status_words(uint32_t n) { return 2 * (((size_t)n + SCAN_TILE - 1) / SCAN_TILE + 1); }
 
-// counts_sorted[r] = counts[sorted_ids[r]], offsets = its exclusive scan,
-// counters[CNT_PAIRS] = the total.  counters must hold CNT_WORDS words, zeroed,
-// followed by scan_status_words(n) zeroed words.
-void launch_gather_scan(hipStream_t st, uint32_t n, const uint32_t *sorted_ids, const uint32_t *counts,
-                        uint32_t *counts_sorted, uint32_t *offsets, uint32_t *counters)
+// bins_sorted[r] = bins[sorted_ids[r]], counts_sorted[r] its pair count,
+// offsets = their exclusive scan, counters[CNT_PAIRS] = the total.  counters
+// must hold CNT_WORDS words, zeroed, followed by scan_status_words(n) zeroed words.
+void launch_gather_scan(hipStream_t st, uint32_t n, const uint32_t *sorted_ids, const uint4 *bins,
+                        uint4 *bins_sorted, uint32_t *counts_sorted, uint32_t *offsets, uint32_t *counters)
 {
     if (n == 0) return;
     const uint32_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-    hipLaunchKernelGGL(gather_scan_kernel, dim3(tiles), dim3(SCAN_BLOCK), 0, st, n, sorted_ids, counts,
+    hipLaunchKernelGGL(gather_scan_kernel, dim3(tiles), dim3(SCAN_BLOCK), 0, st, n, sorted_ids, bins, bins_sorted,
                        counts_sorted, offsets, counters, reinterpret_cast<uint64_t *>(counters + CNT_WORDS));
 }
 
@@ -235,20 +238,20 @@ __device__ __forceinline__ uint32_t os_block_excl(uint32_t x, uint32_t *s_wsum)
 
 // Global histograms of every pass: hist[p * 256 + digit].  A workgroup takes
 // tiles of OS_TILE keys (grid-stride), loads a tile's 16 keys per thread at
-// once, counts equal digits per wave with ballots (one LDS add per distinct
-// digit), and adds its nonzero bins to the global histogram at the end.
+// once and counts them into per-wave LDS histograms (fewer same-address
+// collisions), then adds its nonzero bins to the global histogram.
 template <int BITS>
 __global__ __launch_bounds__(OS_BLOCK) void os_hist_kernel(const uint32_t *__restrict__ keys,
                                                            const uint32_t *__restrict__ n_dev, uint32_t n_host,
                                                            int end_bit, uint32_t *__restrict__ hist)
 {
     constexpr int R = 1 << BITS;
+    constexpr int HW = 1024; // bins per wave: P * R <= 1024 for keys of up to 32 bits
     const int P = os_passes(end_bit, BITS);
-    __shared__ uint32_t h[OS_MAX_PASSES * R];
+    __shared__ uint32_t h[OS_WAVES][HW];
     const uint32_t n = n_dev ? *n_dev : n_host;
-    const int lane = threadIdx.x & 63;
-    const uint64_t lower = lane ? (~0ull >> (64 - lane)) : 0ull;
-    for (int d = threadIdx.x; d < P * R; d += OS_BLOCK) h[d] = 0;
+    const int wave = threadIdx.x >> 6;
+    for (int d = threadIdx.x; d < OS_WAVES * HW; d += OS_BLOCK) (&h[0][0])[d] = 0;
     __syncthreads();
     const uint32_t ntiles = (n + OS_TILE - 1) / OS_TILE;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -259,18 +262,17 @@ __global__ __launch_bounds__(OS_BLOCK) void os_hist_kernel(const uint32_t *__res
             k[i] = idx < n ? keys[idx] : 0u;
         }
 #pragma unroll
-        for (int i = 0; i < OS_ITEMS; ++i) {
-            const bool valid = (size_t)t * OS_TILE + (size_t)i * OS_BLOCK + threadIdx.x < n;
-            for (int p = 0; p < P; ++p) {
-                const uint32_t dg = (k[i] >> (p * BITS)) & (R - 1);
-                const uint64_t peers = digit_peers<BITS>(dg, valid);
-                if (valid && (peers & lower) == 0ull) atomicAdd(&h[p * R + dg], (uint32_t)__popcll(peers));
-            }
-        }
+        for (int i = 0; i < OS_ITEMS; ++i)
+            if ((size_t)t * OS_TILE + (size_t)i * OS_BLOCK + threadIdx.x < n)
+                for (int p = 0; p < P; ++p) atomicAdd(&h[wave][p * R + ((k[i] >> (p * BITS)) & (R - 1))], 1u);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < P * R; d += OS_BLOCK)
-        if (h[d]) atomicAdd(&hist[(d / R) * OS_RADIX + d % R], h[d]);
+    for (int d = threadIdx.x; d < P * R; d += OS_BLOCK) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < OS_WAVES; ++w) c += h[w][d];
+        if (c) atomicAdd(&hist[(d / R) * OS_RADIX + d % R], c);
+    }
 }
 
 template <int BITS>
@@ -467,7 +469,7 @@ void radix_sort(hipStream_t st, uint32_t **keys, uint32_t **vals, uint32_t **key
 // thread (coalesced stores) and finds each pair's instance by a binary search
 // over the offsets staged in LDS.  Within an instance the pairs run row-major
 // over its tile rectangle (over the kept tiles of a rectangle of at most 64
-// tiles, whose mask the preprocess wrote).  Instance id = view * n_convex + convex; the view's
+// tiles), read from the binning records in depth order.  Instance id = view * n_convex + convex; the view's
 // tiles start at its tile_off.
 constexpr int EMIT_BLOCK = 256;
 
@@ -488,7 +490,7 @@ __device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t q)
 
 __global__ __launch_bounds__(EMIT_BLOCK) void emit_pairs_kernel(
     uint32_t n, uint32_t n_convex, const uint32_t *__restrict__ sorted_ids, const uint32_t *__restrict__ offsets,
-    const uint32_t *__restrict__ counts_sorted, const uint2 *__restrict__ rects, const uint64_t *__restrict__ tmasks,
+    const uint32_t *__restrict__ counts_sorted, const uint4 *__restrict__ bins_sorted,
     const FrameHeader *__restrict__ frame, uint32_t capacity, uint32_t *__restrict__ pair_tiles,
     uint32_t *__restrict__ pair_ids)
 {
@@ -513,14 +515,14 @@ __global__ __launch_bounds__(EMIT_BLOCK) void emit_pairs_kernel(
         uint32_t x0w = 0, base = 0, tx = 1, small = 0;
         uint64_t mask = 0;
         if (counts_sorted[r] > 0) {
-            const uint2 rc = rects[id];
-            const uint32_t tx0 = rc.x & 0xFFFFu, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFFu, ty1 = rc.y >> 16;
+            const uint4 b = bins_sorted[r];
+            const uint32_t tx0 = b.x & 0xFFFFu, ty0 = b.x >> 16, tx1 = b.y & 0xFFFFu, ty1 = b.y >> 16;
             const ViewDesc &vd = views[id / n_convex];
             tx = (uint32_t)vd.tiles_x;
             x0w = tx0 | ((tx1 - tx0 + 1) << 16);
             base = (uint32_t)vd.tile_off + ty0 * tx;
             small = (tx1 - tx0 + 1) * (ty1 - ty0 + 1) <= 64u;
-            if (small) mask = tmasks[id];
+            mask = (uint64_t)b.z | ((uint64_t)b.w << 32);
         }
         s_x0w[tid] = x0w;
         s_base[tid] = base;
@@ -548,16 +550,6 @@ __global__ __launch_bounds__(EMIT_BLOCK) void emit_pairs_kernel(
     }
 }
 
-// Pair count that fits the buffers, and the overflow flag (for fixed-capacity frames).
-__global__ void clamp_pairs_kernel(uint32_t *__restrict__ counters, uint32_t capacity)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        const uint32_t m = counters[CNT_PAIRS];
-        counters[CNT_PAIRS_EFF] = m < capacity ? m : capacity;
-        counters[CNT_OVERFLOW] = m > capacity ? 1u : 0u;
-    }
-}
-
 // Sort keys that put long tile lists first: key = 0xFFFF - min(length, 0xFFFF).
 __global__ void tile_length_keys_kernel(uint32_t ntiles, const uint2 *__restrict__ ranges,
                                         uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
@@ -568,6 +560,33 @@ __global__ void tile_length_keys_kernel(uint32_t ntiles, const uint2 *__restrict
     const uint32_t len = r.y - r.x;
     keys[t] = 0xFFFFu - (len < 0xFFFFu ? len : 0xFFFFu);
     vals[t] = t;
+}
+
+// Zero up to four ranges of words in one launch.
+struct FillRanges {
+    uint32_t *p[4];
+    size_t n[4];
+};
+__global__ void zero_ranges_kernel(FillRanges r)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < r.n[k]; i += stride) r.p[k][i] = 0u;
+}
+
+// The pair count that fits the buffers and the overflow flag, and the tile
+// ranges cleared, in one launch.
+__global__ void prepare_tail_kernel(uint32_t *__restrict__ counters, uint32_t capacity, uint32_t *__restrict__ ranges,
+                                    size_t nwords)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t m = counters[CNT_PAIRS];
+        counters[CNT_PAIRS_EFF] = m < capacity ? m : capacity;
+        counters[CNT_OVERFLOW] = m > capacity ? 1u : 0u;
+    }
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nwords; i += (size_t)gridDim.x * blockDim.x)
+        ranges[i] = 0u;
 }
 
 __global__ void fill_u32_kernel(uint32_t *__restrict__ p, size_t n, uint32_t v)
@@ -595,19 +614,29 @@ void launch_fill_u32(hipStream_t st, uint32_t *p, size_t n, uint32_t v)
 }
 
 void launch_emit_pairs(hipStream_t st, uint32_t n, uint32_t n_convex, const uint32_t *sorted_ids,
-                       const uint32_t *offsets, const uint32_t *counts_sorted, const uint2 *rects,
-                       const uint64_t *tmasks, const FrameHeader *views, uint32_t capacity, uint32_t *pair_tiles,
-                       uint32_t *pair_ids)
+                       const uint32_t *offsets, const uint32_t *counts_sorted, const uint4 *bins_sorted,
+                       const FrameHeader *views, uint32_t capacity, uint32_t *pair_tiles, uint32_t *pair_ids)
 {
     if (n == 0) return;
     hipLaunchKernelGGL(emit_pairs_kernel, dim3((n + EMIT_BLOCK - 1) / EMIT_BLOCK), dim3(EMIT_BLOCK), 0, st, n,
-                       n_convex, sorted_ids, offsets, counts_sorted, rects, tmasks, views, capacity, pair_tiles,
+                       n_convex, sorted_ids, offsets, counts_sorted, bins_sorted, views, capacity, pair_tiles,
                        pair_ids);
 }
 
-void launch_clamp_pairs(hipStream_t st, uint32_t *counters, uint32_t capacity)
+void launch_prepare_tail(hipStream_t st, uint32_t *counters, uint32_t capacity, uint32_t *ranges, size_t nwords)
 {
-    hipLaunchKernelGGL(clamp_pairs_kernel, dim3(1), dim3(64), 0, st, counters, capacity);
+    const size_t blocks = std::max<size_t>(1, std::min<size_t>((nwords + 255) / 256, 1024));
+    hipLaunchKernelGGL(prepare_tail_kernel, dim3((unsigned)blocks), dim3(256), 0, st, counters, capacity, ranges,
+                       nwords);
+}
+
+void launch_zero_ranges(hipStream_t st, uint32_t *p0, size_t n0, uint32_t *p1, size_t n1, uint32_t *p2, size_t n2)
+{
+    FillRanges r = {{p0, p1, p2, p0}, {n0, n1, n2, 0}};
+    const size_t most = std::max(std::max(n0, n1), n2);
+    if (most == 0) return;
+    const size_t blocks = std::min<size_t>((most + 255) / 256, 4096);
+    hipLaunchKernelGGL(zero_ranges_kernel, dim3((unsigned)blocks), dim3(256), 0, st, r);
 }
 
 void launch_tile_length_keys(hipStream_t st, uint32_t ntiles, const uint2 *ranges, uint32_t *keys, uint32_t *vals)

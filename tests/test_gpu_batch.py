@@ -215,3 +215,29 @@ def test_autotune_and_autotuned_batch(R):
     for a, b in zip(outs, ref):
         assert torch.equal(a, b)
     st.release()
+
+
+def test_eager_frame_reuse_with_more_pairs_matches_fresh(R):
+    """A reused frame runs the post-count tail on the device-side count; when
+    the new view needs more pairs than its buffers hold, the tail runs again
+    with grown buffers, and the image equals a fresh renderer's."""
+    from paper_2411_14974_amd.binding import Renderer, make_camera, make_params
+    scene, cams = small_batch(n=20000, views=1, seed=8, res=((256, 160),))
+    ds = dev(scene)
+    near = cams[0]
+    far = make_camera(near)
+    far.t[2] = far.t[2] + 6.0  # few pairs: the cached frame gets small pair buffers
+    R.forward(ds, far, make_params())
+    img, st = R.forward(ds, near, make_params(), want_state=True)  # reuses that frame, overflows
+    torch.cuda.synchronize()
+    fresh = Renderer(0)
+    try:
+        ref, st2 = fresh.forward(ds, near, make_params(), want_state=True)
+        torch.cuda.synchronize()
+        assert torch.equal(img, ref)
+        assert st.stats()["pairs"] == st2.stats()["pairs"]
+        say(f"[reuse] {st.stats()['pairs']} pairs after growing a reused frame: image equals a fresh render")
+        st2.release()
+    finally:
+        fresh.close()
+    st.release()
