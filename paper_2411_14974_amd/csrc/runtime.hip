@@ -365,6 +365,15 @@ int plan_views(int nviews, const cs_camera *cams, int tile, float *const *out, c
 // Forward pass on frame F.  device_count: the pair count stays on the device
 // (fixed capacities, graph capture); otherwise it is read back to size the
 // pair buffers exactly (plus `margin`).
+// Wait for an event by polling it.
+static hipError_t spin_wait(hipEvent_t ev)
+{
+    for (;;) {
+        const hipError_t e = hipEventQuery(ev);
+        if (e != hipErrorNotReady) return e;
+    }
+}
+
 int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs &ra, const Knobs &kn,
                     bool device_count, double margin, StageTimer &tm)
 {
@@ -440,7 +449,9 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
         tm.end(CS_STAGE_BIN_SCAN);
         if (!device_count) {
             hipError_t e = hipMemcpyAsync(hw, F.counters + CNT_PAIRS, 4, hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = speculative ? hipEventRecord(F.mcount_ev, st) : hipStreamSynchronize(st);
+            if (e == hipSuccess) e = hipEventRecord(F.mcount_ev, st);
+            // a new frame waits for its count here (polling: a blocking wait wakes up late and the GPU idles)
+            if (e == hipSuccess && !speculative) e = spin_wait(F.mcount_ev);
             if (e != hipSuccess) return fail(CS_EHIP, "pair count read-back: %s", hipGetErrorString(e));
             if (!speculative) {
                 M = hw[0];
