@@ -31,20 +31,36 @@ namespace cs {
 
 namespace {
 
+// A pixel's (u, y) lies in a record's box (box_u, box_v), outside of which alpha < eps.
+__device__ __forceinline__ bool in_box(uint32_t box_u, uint32_t box_v, int u, int y)
+{
+    return u >= (int)(box_u & 0xFFFFu) && u <= (int)(box_u >> 16) && y >= (int)(box_v & 0xFFFFu) &&
+           y <= (int)(box_v >> 16);
+}
+
 template <int K> struct PairEval {
     float I, omI, alpha, oma, phi2, inv_sum;
     float e[K];  // 2^(x2_j - max)
     float x2[K]; // x2_j rounded to float
 };
 
-// The one evaluation of a (pixel, convex) pair shared by both passes.
-// Returns false when the pair is skipped (alpha < eps_alpha).
+// The one evaluation of a (pixel, convex) pair shared by both passes, called
+// by every lane of the wavefront (live: the pixel still takes convexes).
+// Returns whether the pair contributes: the pixel lies in the record's pixel
+// box (tested), the largest line value passes the skip threshold (full), and
+// alpha >= eps_alpha.  When some lane passes the threshold, every field of pe
+// is computed, and finite, for every lane, so that callers can use them
+// without branches; otherwise the wavefront leaves early.
+//
 // The record (header and all K line slots) is read from LDS in one burst of
 // 16-byte reads with a single wait; slots past T hold stale values and are
 // masked with selects, not branches (a branch per line would serialise the
-// LDS round trips).
+// LDS round trips).  The lines are evaluated in FP64; the exponents are taken
+// as differences of the FP32-rounded values (phi already starts from the
+// rounded maximum, and where the sigmoid is sensitive |x2| is small).
 template <int K>
-__device__ __forceinline__ bool eval_pair(const uint8_t *rec, float pxf, float pyf, float eps, PairEval<K> &pe)
+__device__ __forceinline__ bool eval_pair(const uint8_t *rec, bool live, int u, int y, float pxf, float pyf,
+                                          float eps, PairEval<K> &pe, bool &tested, bool &full)
 {
     const RecHeader h = *reinterpret_cast<const RecHeader *>(rec);
     double L[3 * K + 1]; // one spare slot: odd 3K reads into the record's padding
@@ -56,7 +72,7 @@ __device__ __forceinline__ bool eval_pair(const uint8_t *rec, float pxf, float p
         L[2 * q + 1] = w.y;
     }
     const int T = h.T;
-    pe.inv_sum = 0.0f;
+    tested = live && in_box(h.box_u, h.box_v, u, y);
     const double dx = (double)(pxf - h.ox), dy = (double)(pyf - h.oy);
     double x[K];
     double m = -INFINITY;
@@ -67,27 +83,29 @@ __device__ __forceinline__ bool eval_pair(const uint8_t *rec, float pxf, float p
         m = fmax(m, x[j]);
     }
     // LogSumExp >= its largest term: past thr2 alpha < eps for certain
-    if (!(m <= (double)h.thr2)) return false;
+    full = tested && (m <= (double)h.thr2);
+    if (!__any(full)) return false;
+    const float mf = (float)m;
     float s = 0.0f;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        const float e = (j < T) ? __builtin_amdgcn_exp2f((float)(x[j] - m)) : 0.0f;
+        const float xf = (float)x[j];
+        const float e = (j < T) ? __builtin_amdgcn_exp2f(xf - mf) : 0.0f;
         pe.e[j] = e;
-        pe.x2[j] = (j < T) ? (float)x[j] : 0.0f;
+        pe.x2[j] = (j < T) ? xf : 0.0f;
         s += e;
     }
     pe.inv_sum = __builtin_amdgcn_rcpf(s);
-    const float phi2 = (float)m + __builtin_amdgcn_logf(s);
+    const float phi2 = mf + __builtin_amdgcn_logf(s);
     const float z = h.sigma_p * phi2; // I = 1 / (1 + 2^z)
     const float ez = __builtin_amdgcn_exp2f(-fabsf(z));
     const float r = __builtin_amdgcn_rcpf(1.0f + ez);
     pe.I = z > 0.0f ? ez * r : r;
     pe.omI = z > 0.0f ? r : ez * r;
     pe.alpha = h.opacity * pe.I;
-    if (pe.alpha < eps) return false;
     pe.oma = (1.0f - h.opacity) + h.opacity * pe.omI;
     pe.phi2 = phi2;
-    return true;
+    return full && !(pe.alpha < eps);
 }
 
 // Row sums: after it every lane of each 16-lane row holds that row's sum of
@@ -139,28 +157,6 @@ template <int TILE> __device__ __forceinline__ void tile_pixel(int &dx, int &dy)
     dy = (w / (TILE / 8)) * 8 + (l >> 3);
 }
 
-// A pixel's (u, y) lies in a record's box (box_u, box_v), outside of which alpha < eps.
-__device__ __forceinline__ bool in_box(uint32_t box_u, uint32_t box_v, int u, int y)
-{
-    return u >= (int)(box_u & 0xFFFFu) && u <= (int)(box_u >> 16) && y >= (int)(box_v & 0xFFFFu) &&
-           y <= (int)(box_v >> 16);
-}
-
-// Lane l of each wave holds the pixel box of batch entry l; a record's box is
-// then a readlane away (no LDS round trip per record).
-template <int K, int BATCH>
-__device__ __forceinline__ void lane_boxes(const uint4 *lds, int cnt, uint32_t &bu, uint32_t &bv)
-{
-    constexpr int CH = rec_stride(K) / 16;
-    const int lane = threadIdx.x & 63;
-    bu = 1u; // empty box
-    bv = 1u;
-    if (lane < cnt) {
-        const uint4 c2 = lds[min(lane, BATCH - 1) * CH + 2]; // T, id, box_u, box_v
-        bu = c2.z;
-        bv = c2.w;
-    }
-}
 
 // Can a record reach alpha >= eps_alpha at a pixel centre of the 8x8 square
 // [su, su + 7] x [sv, sv + 7]?  Its pixel box must meet the square, and no
@@ -357,29 +353,25 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4)))
                 const bool meets = lane < cnt && square_meets<K>(reinterpret_cast<const uint8_t *>(&lds[min(lane, BATCH - 1) * CH]), su, sv);
                 M = __ballot(meets);
             }
-            uint32_t lbu, lbv;
-            lane_boxes<K, BATCH>(lds, cnt, lbu, lbv);
             while (M) {
                 const int e = __builtin_ctzll(M);
                 M &= M - 1;
                 const uint8_t *rec = reinterpret_cast<const uint8_t *>(&lds[e * CH]);
-                const uint32_t bu = __builtin_amdgcn_readlane(lbu, e), bv = __builtin_amdgcn_readlane(lbv, e);
-                if (!done && in_box(bu, bv, u, y)) {
-                    PairEval<K> pe;
-                    ++nevals;
-                    const bool hit = eval_pair<K>(rec, pxf, pyf, ra.eps_alpha, pe);
-                    nfull += pe.inv_sum > 0.0f;
-                    if (hit) {
-                        const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
-                        const float w = T * pe.alpha;
-                        C0 = fmaf(w, h.rgb[0], C0);
-                        C1 = fmaf(w, h.rgb[1], C1);
-                        C2 = fmaf(w, h.rgb[2], C2);
-                        Tlast = T;
-                        T = T * pe.oma;
-                        nend = base - start + e + 1;
-                        done = T < ra.t_min;
-                    }
+                PairEval<K> pe;
+                bool tested, full;
+                const bool hit = eval_pair<K>(rec, !done, u, y, pxf, pyf, ra.eps_alpha, pe, tested, full);
+                nevals += tested;
+                nfull += full;
+                if (hit) {
+                    const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
+                    const float w = T * pe.alpha;
+                    C0 = fmaf(w, h.rgb[0], C0);
+                    C1 = fmaf(w, h.rgb[1], C1);
+                    C2 = fmaf(w, h.rgb[2], C2);
+                    Tlast = T;
+                    T = T * pe.oma;
+                    nend = base - start + e + 1;
+                    done = T < ra.t_min;
                 }
                 if (__all(done)) break;
             }
@@ -491,47 +483,45 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
             const bool meets = lane < min(cnt, wmaxn - lo) &&
                                square_meets<K>(reinterpret_cast<const uint8_t *>(&lds[min(lane, BATCH - 1) * CH]), su, sv);
             uint64_t M = __ballot(meets);
-            uint32_t lbu, lbv;
-            lane_boxes<K, BATCH>(lds, cnt, lbu, lbv);
             while (M) {
                 const int e = 63 - __builtin_clzll(M);
                 M &= ~(1ull << e);
                 const int pos = lo + e;
                 const uint8_t *rec = reinterpret_cast<const uint8_t *>(&lds[e * CH]);
-                const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
-                const uint32_t bu = __builtin_amdgcn_readlane(lbu, e), bv = __builtin_amdgcn_readlane(lbv, e);
-                const bool live = pos < nend && in_box(bu, bv, u, y);
-                if (!__any(live)) continue; // wave-uniform
                 PairEval<K> pe;
-                const bool contrib = live && eval_pair<K>(rec, pxf, pyf, ra.eps_alpha, pe);
+                bool tested, full;
+                const bool contrib = eval_pair<K>(rec, pos < nend, u, y, pxf, pyf, ra.eps_alpha, pe, tested, full);
                 if (__ballot(contrib) == 0ull) continue; // wave-uniform
+                const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
+                // branch-free: a lane that does not contribute takes Tn = 0,
+                // which zeroes all of its values (every pe field is finite)
+                const float Tn = contrib ? (first ? Tlast : Tcur * __builtin_amdgcn_rcpf(pe.oma)) : 0.0f;
+                const float dLda = Tn * (g0 * (h.rgb[0] - B0) + g1 * (h.rgb[1] - B1) + g2 * (h.rgb[2] - B2));
+                const float ta = Tn * pe.alpha;
                 float val[NP];
+                val[3 * K + 2] = g0 * ta;
+                val[3 * K + 3] = g1 * ta;
+                val[3 * K + 4] = g2 * ta;
+                val[3 * K + 1] = dLda * pe.I;
+                const float dLdz = -dLda * h.opacity * pe.I * pe.omI; // I = Sigmoid(-z), z = sigma' phi
+                val[3 * K] = dLdz * pe.phi2 * (float)LN2;
+                const float dLdphi2 = dLdz * h.sigma_p * (float)LN2;
+                const float dxf = pxf - h.ox, dyf = pyf - h.oy;
+                float gdl = 0.0f;
 #pragma unroll
-                for (int qv = 0; qv < NP; ++qv) val[qv] = 0.0f;
+                for (int j = 0; j < K; ++j) {
+                    const float gx = dLdphi2 * pe.e[j] * pe.inv_sum;
+                    val[j] = gx * dxf;
+                    val[K + j] = gx * dyf;
+                    val[2 * K + j] = gx;
+                    gdl = fmaf(gx, pe.x2[j], gdl);
+                }
+                val[3 * K + 5] = gdl;
+#pragma unroll
+                for (int qv = NV; qv < NP; ++qv) val[qv] = 0.0f;
                 if (contrib) {
-                    const float Tn = first ? Tlast : Tcur / pe.oma;
                     first = false;
                     Tcur = Tn;
-                    const float dLda = Tn * (g0 * (h.rgb[0] - B0) + g1 * (h.rgb[1] - B1) + g2 * (h.rgb[2] - B2));
-                    const float ta = Tn * pe.alpha;
-                    val[3 * K + 2] = g0 * ta;
-                    val[3 * K + 3] = g1 * ta;
-                    val[3 * K + 4] = g2 * ta;
-                    val[3 * K + 1] = dLda * pe.I;
-                    const float dLdz = -dLda * h.opacity * pe.I * pe.omI; // I = Sigmoid(-z), z = sigma' phi
-                    val[3 * K] = dLdz * pe.phi2 * (float)LN2;
-                    const float dLdphi2 = dLdz * h.sigma_p * (float)LN2;
-                    const float dxf = pxf - h.ox, dyf = pyf - h.oy;
-                    float gdl = 0.0f;
-#pragma unroll
-                    for (int j = 0; j < K; ++j) {
-                        const float gx = dLdphi2 * pe.e[j] * pe.inv_sum;
-                        val[j] = gx * dxf;
-                        val[K + j] = gx * dyf;
-                        val[2 * K + j] = gx;
-                        gdl = fmaf(gx, pe.x2[j], gdl);
-                    }
-                    val[3 * K + 5] = gdl;
                     B0 = fmaf(pe.alpha, h.rgb[0], pe.oma * B0);
                     B1 = fmaf(pe.alpha, h.rgb[1], pe.oma * B1);
                     B2 = fmaf(pe.alpha, h.rgb[2], pe.oma * B2);
