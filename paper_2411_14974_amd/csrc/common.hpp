@@ -29,8 +29,12 @@ struct RecHeader {
     uint32_t box_u;   // pixel columns u0 | u1 << 16 (inclusive) where alpha can reach eps
     uint32_t box_v;   // pixel rows    v0 | v1 << 16
 };
-// the K lines (three doubles each) follow the header
+// the K lines (three doubles each) follow the header; slots past the hull's
+// T lines hold the null line (0, 0, NULL_LINE_C): its value is so negative
+// that it never sets the maximum, its exponential is 0 and its gradient
+// terms vanish, so consumers need no per-slot test against T
 constexpr int REC_HEADER = 48;
+constexpr double NULL_LINE_C = -1e30;
 static_assert(sizeof(RecHeader) == REC_HEADER, "record header is 48 bytes");
 
 __host__ __device__ constexpr int rec_stride(int K) { return (REC_HEADER + 24 * K + 15) & ~15; }

@@ -205,7 +205,17 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
             cur = nxt; cxp = nxp; cyp = nyp;
         }
         (void)prevC; (void)firstC;
-        if (T & 1) lines2[(3 * T - 1) >> 1] = make_double2(carry, 0.0); // the last line's c
+        // null lines in the slots past T (same pairing of doubles)
+        for (int j = T; j < K; ++j) {
+            if ((j & 1) == 0) {
+                lines2[(3 * j) >> 1] = make_double2(0.0, 0.0);
+                carry = NULL_LINE_C;
+            } else {
+                lines2[(3 * j - 1) >> 1] = make_double2(carry, 0.0);
+                lines2[(3 * j + 1) >> 1] = make_double2(0.0, NULL_LINE_C);
+            }
+        }
+        if (K & 1) lines2[(3 * K - 1) >> 1] = make_double2(carry, 0.0); // the last line's c
         if (closed && T >= 3) {
             const double den = 1.0 + prevA * firstA + prevB * firstB;
             if (den < 1e-6) unbounded = true;
@@ -322,8 +332,8 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
                                 const double a1 = (double)min(tx * ra.tile + ra.tile - 1, u1) + 0.5 - ox;
                                 bool keep = true;
 #pragma unroll
-                                for (int j = 0; j < K; ++j)
-                                    keep = keep && !(j < T && fmin(la[j] * a0, la[j] * a1) + rowt[j] > 0.0);
+                                for (int j = 0; j < K; ++j) // null lines never drop a tile
+                                    keep = keep && !(fmin(la[j] * a0, la[j] * a1) + rowt[j] > 0.0);
                                 if (keep) m |= 1ull << ((ty - ty0) * tw + (tx - tx0));
                             }
                         }

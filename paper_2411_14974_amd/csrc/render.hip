@@ -53,9 +53,8 @@ template <int K> struct PairEval {
 // without branches; otherwise the wavefront leaves early.
 //
 // The record (header and all K line slots) is read from LDS in one burst of
-// 16-byte reads with a single wait; slots past T hold stale values and are
-// masked with selects, not branches (a branch per line would serialise the
-// LDS round trips).  The lines are evaluated in FP64; the exponents are taken
+// 16-byte reads with a single wait (a branch per line would serialise the LDS
+// round trips; slots past T hold null lines).  The lines are evaluated in FP64; the exponents are taken
 // as differences of the FP32-rounded values (phi already starts from the
 // rounded maximum, and where the sigmoid is sensitive |x2| is small).
 template <int K>
@@ -71,15 +70,13 @@ __device__ __forceinline__ bool eval_pair(const uint8_t *rec, bool live, int u, 
         L[2 * q] = w.x;
         L[2 * q + 1] = w.y;
     }
-    const int T = h.T;
     tested = live && in_box(h.box_u, h.box_v, u, y);
     const double dx = (double)(pxf - h.ox), dy = (double)(pyf - h.oy);
     double x[K];
     double m = -INFINITY;
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const double v = fma(L[3 * j], dx, fma(L[3 * j + 1], dy, L[3 * j + 2]));
-        x[j] = (j < T) ? v : -INFINITY;
+    for (int j = 0; j < K; ++j) { // slots past T hold null lines: no test against T
+        x[j] = fma(L[3 * j], dx, fma(L[3 * j + 1], dy, L[3 * j + 2]));
         m = fmax(m, x[j]);
     }
     // LogSumExp >= its largest term: past thr2 alpha < eps for certain
@@ -90,9 +87,9 @@ __device__ __forceinline__ bool eval_pair(const uint8_t *rec, bool live, int u, 
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const float xf = (float)x[j];
-        const float e = (j < T) ? __builtin_amdgcn_exp2f(xf - mf) : 0.0f;
+        const float e = __builtin_amdgcn_exp2f(xf - mf);
         pe.e[j] = e;
-        pe.x2[j] = (j < T) ? xf : 0.0f;
+        pe.x2[j] = xf;
         s += e;
     }
     pe.inv_sum = __builtin_amdgcn_rcpf(s);
@@ -185,7 +182,7 @@ template <int K> __device__ __forceinline__ bool square_meets(const uint8_t *rec
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const double mn = L[3 * j + 2] + fmin(L[3 * j] * a0, L[3 * j] * a1) + fmin(L[3 * j + 1] * c0, L[3 * j + 1] * c1);
-        ok = ok && !(j < h.T && mn > lim);
+        ok = ok && !(mn > lim); // null lines never reject
     }
     return ok;
 }
@@ -506,11 +503,12 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
                 const float dLdz = -dLda * h.opacity * pe.I * pe.omI; // I = Sigmoid(-z), z = sigma' phi
                 val[3 * K] = dLdz * pe.phi2 * (float)LN2;
                 const float dLdphi2 = dLdz * h.sigma_p * (float)LN2;
+                const float gs = dLdphi2 * pe.inv_sum; // dL/dx2_j = gs e_j (softmax weights)
                 const float dxf = pxf - h.ox, dyf = pyf - h.oy;
                 float gdl = 0.0f;
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
-                    const float gx = dLdphi2 * pe.e[j] * pe.inv_sum;
+                    const float gx = gs * pe.e[j];
                     val[j] = gx * dxf;
                     val[K + j] = gx * dyf;
                     val[2 * K + j] = gx;
