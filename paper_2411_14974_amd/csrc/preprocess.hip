@@ -320,22 +320,34 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
                             lc[j] = ln[3 * j + 2];
                         }
                         const double lim = (double)h.thr2 + 1e-3;
+                        // per line: la x + lb y + lc <= lim on the kept part; over a
+                        // tile row (pixel-centre rows c0..c1) the line keeps the
+                        // columns with x <= hi_j (la > 0) or x >= lo_j (la < 0), so
+                        // each row keeps one interval of tiles (cost per row, not per tile)
+                        double inv[K];
+#pragma unroll
+                        for (int j = 0; j < K; ++j) inv[j] = la[j] != 0.0 ? 1.0 / la[j] : 0.0;
                         uint64_t m = 0;
                         for (int ty = ty0; ty <= ty1; ++ty) {
                             const double c0 = (double)max(ty * ra.tile, v0) + 0.5 - oy;
                             const double c1 = (double)min(ty * ra.tile + ra.tile - 1, v1) + 0.5 - oy;
-                            double rowt[K]; // the line's constant and row part, less the threshold
+                            double xlo = -INFINITY, xhi = INFINITY; // kept pixel centres, origin-relative
+                            bool none = false;
 #pragma unroll
-                            for (int j = 0; j < K; ++j) rowt[j] = (lc[j] + fmin(lb[j] * c0, lb[j] * c1)) - lim;
-                            for (int tx = tx0; tx <= tx1; ++tx) {
-                                const double a0 = (double)max(tx * ra.tile, u0) + 0.5 - ox;
-                                const double a1 = (double)min(tx * ra.tile + ra.tile - 1, u1) + 0.5 - ox;
-                                bool keep = true;
-#pragma unroll
-                                for (int j = 0; j < K; ++j) // null lines never drop a tile
-                                    keep = keep && !(fmin(la[j] * a0, la[j] * a1) + rowt[j] > 0.0);
-                                if (keep) m |= 1ull << ((ty - ty0) * tw + (tx - tx0));
+                            for (int j = 0; j < K; ++j) { // null lines never drop a tile
+                                const double rest = lim - (lc[j] + fmin(lb[j] * c0, lb[j] * c1));
+                                const double b = rest * inv[j];
+                                if (la[j] > 0.0) xhi = fmin(xhi, b);
+                                else if (la[j] < 0.0) xlo = fmax(xlo, b);
+                                else none = none || rest < 0.0;
                             }
+                            // first and last pixel columns of the box with a centre in [xlo, xhi]
+                            const double ulo = fmax(ceil(xlo + ox - 0.5), (double)u0);
+                            const double uhi = fmin(floor(xhi + ox - 0.5), (double)u1);
+                            if (none || !(ulo <= uhi)) continue;
+                            const int kx0 = (int)ulo / ra.tile - tx0, kx1 = (int)uhi / ra.tile - tx0;
+                            const int nk = kx1 - kx0 + 1;
+                            m |= ((nk == 64) ? ~0ull : ((1ull << nk) - 1ull)) << ((ty - ty0) * tw + kx0);
                         }
                         tmask = m;
                     }
