@@ -183,7 +183,7 @@ void launch_gather_scan(hipStream_t st, uint32_t n, const uint32_t *sorted_ids, 
 // wait ends; it is still bounded (OS_SPIN_LIMIT), and a wait that runs out
 // sets the caller's error word instead of spinning on.
 
-constexpr int OS_BLOCK = 256;
+constexpr int OS_BLOCK = 512;
 constexpr int OS_WAVES = OS_BLOCK / 64;
 constexpr int OS_ITEMS = 16;
 constexpr int OS_TILE = OS_BLOCK * OS_ITEMS;
@@ -196,6 +196,16 @@ constexpr int OS_WINDOW = 8; // predecessors read per look-back round trip
 constexpr size_t OS_CTR = (size_t)OS_MAX_PASSES * OS_RADIX, OS_STATUS = OS_CTR + 64;
 
 __host__ __device__ constexpr int os_passes(int end_bit, int digit_bits) { return (end_bit + digit_bits - 1) / digit_bits; }
+// The end_bit bits are split over the passes as evenly as possible (13 bits in
+// two passes: 7 + 6); pass p covers bits [os_shift, os_shift + os_width).
+__host__ __device__ constexpr int os_width(int end_bit, int passes, int p)
+{
+    return end_bit / passes + (p < end_bit % passes ? 1 : 0);
+}
+__host__ __device__ constexpr int os_shift(int end_bit, int passes, int p)
+{
+    return p * (end_bit / passes) + (p < end_bit % passes ? p : end_bit % passes);
+}
 
 __device__ __forceinline__ uint32_t os_load(const uint32_t *p)
 {
@@ -243,11 +253,10 @@ __device__ __forceinline__ uint32_t os_block_excl(uint32_t x, uint32_t *s_wsum)
 template <int BITS>
 __global__ __launch_bounds__(OS_BLOCK) void os_hist_kernel(const uint32_t *__restrict__ keys,
                                                            const uint32_t *__restrict__ n_dev, uint32_t n_host,
-                                                           int end_bit, uint32_t *__restrict__ hist)
+                                                           int end_bit, int P, uint32_t *__restrict__ hist)
 {
-    constexpr int R = 1 << BITS;
-    constexpr int HW = 1024; // bins per wave: P * R <= 1024 for keys of up to 32 bits
-    const int P = os_passes(end_bit, BITS);
+    constexpr int R = 1 << BITS; // bins per pass (BITS: the widest pass)
+    constexpr int HW = 1024;     // bins per wave: P * R <= 1024 for keys of up to 32 bits
     __shared__ uint32_t h[OS_WAVES][HW];
     const uint32_t n = n_dev ? *n_dev : n_host;
     const int wave = threadIdx.x >> 6;
@@ -264,7 +273,9 @@ __global__ __launch_bounds__(OS_BLOCK) void os_hist_kernel(const uint32_t *__res
 #pragma unroll
         for (int i = 0; i < OS_ITEMS; ++i)
             if ((size_t)t * OS_TILE + (size_t)i * OS_BLOCK + threadIdx.x < n)
-                for (int p = 0; p < P; ++p) atomicAdd(&h[wave][p * R + ((k[i] >> (p * BITS)) & (R - 1))], 1u);
+                for (int p = 0; p < P; ++p)
+                    atomicAdd(&h[wave][p * R + ((k[i] >> os_shift(end_bit, P, p)) & ((1u << os_width(end_bit, P, p)) - 1u))],
+                              1u);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < P * R; d += OS_BLOCK) {
@@ -407,9 +418,9 @@ size_t sort_temp_words(uint32_t n_capacity, int end_bit, int digit_bits)
 
 template <int B>
 static void os_launch_hist(hipStream_t st, const uint32_t *keys, uint32_t n_host, const uint32_t *n_dev, int blocks,
-                           int end_bit, uint32_t *hist)
+                           int end_bit, int P, uint32_t *hist)
 {
-    hipLaunchKernelGGL(os_hist_kernel<B>, dim3(blocks), dim3(OS_BLOCK), 0, st, keys, n_dev, n_host, end_bit, hist);
+    hipLaunchKernelGGL(os_hist_kernel<B>, dim3(blocks), dim3(OS_BLOCK), 0, st, keys, n_dev, n_host, end_bit, P, hist);
 }
 
 template <int B>
@@ -423,6 +434,9 @@ static void os_launch_scatter(hipStream_t st, const uint32_t *keys, const uint32
 
 #define OS_DISPATCH(BITS, CALL)                                                                                    \
     switch (BITS) {                                                                                                \
+    case 1: { constexpr int BB = 1; CALL; } break;                                                                 \
+    case 2: { constexpr int BB = 2; CALL; } break;                                                                 \
+    case 3: { constexpr int BB = 3; CALL; } break;                                                                 \
     case 4: { constexpr int BB = 4; CALL; } break;                                                                 \
     case 5: { constexpr int BB = 5; CALL; } break;                                                                 \
     case 6: { constexpr int BB = 6; CALL; } break;                                                                 \
@@ -430,7 +444,8 @@ static void os_launch_scatter(hipStream_t st, const uint32_t *keys, const uint32
     default: { constexpr int BB = 8; CALL; } break;                                                                \
     }
 
-// Sorts bits [0, end_bit) of the keys in passes of `digit_bits` (4..8).  On
+// Sorts bits [0, end_bit) of the keys in ceil(end_bit / digit_bits) passes
+// (digit_bits in 4..8; the bits are split evenly over the passes).  On
 // return *keys/*vals point at the sorted arrays (one of the two buffer pairs).
 // n_dev may be NULL (n_host used); with n_dev the element count is read on the
 // device (graph capture needs no host read-back) and n_capacity bounds it.
@@ -449,10 +464,11 @@ void radix_sort(hipStream_t st, uint32_t **keys, uint32_t **vals, uint32_t **key
     const size_t fb = std::min<size_t>((words + 255) / 256, 4096);
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)fb), dim3(256), 0, st, temp, words, 0u);
     const int hb = std::max(1, std::min(tiles, 1024));
-    OS_DISPATCH(digit_bits, os_launch_hist<BB>(st, *keys, n_host, n_dev, hb, end_bit, temp));
+    const int widest = os_width(end_bit, P, 0);
+    OS_DISPATCH(widest, os_launch_hist<BB>(st, *keys, n_host, n_dev, hb, end_bit, P, temp));
     for (int p = 0; p < P; ++p) {
-        const int shift = p * digit_bits;
-        const int b = std::min(digit_bits, end_bit - shift);
+        const int shift = os_shift(end_bit, P, p);
+        const int b = os_width(end_bit, P, p);
         uint32_t *status = temp + OS_STATUS + (size_t)p * tiles * OS_RADIX;
         OS_DISPATCH(b, os_launch_scatter<BB>(st, *keys, *vals, *keys_alt, *vals_alt, n_host, n_dev, tiles, shift,
                                              temp + (size_t)p * OS_RADIX, temp + OS_CTR + p, status, err));
