@@ -564,7 +564,7 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
 #define CS_DISPATCH_TILE(TILEV, ...)                                                                               \
     switch (TILEV) {                                                                                               \
     case 8: { constexpr int TT = 8, BF = 32, BBW = 32; __VA_ARGS__; } break;                                       \
-    case 16: { constexpr int TT = 16, BF = 32, BBW = 64; __VA_ARGS__; } break;                                     \
+    case 16: { constexpr int TT = 16, BF = 64, BBW = 64; __VA_ARGS__; } break;                                     \
     case 32: { constexpr int TT = 32, BF = 64, BBW = 64; __VA_ARGS__; } break;                                     \
     default: break;                                                                                                \
     }
