@@ -47,14 +47,14 @@ def stage_work(stage, n, m, K, T_mean, deg, stats, npix):
     """Algorithmic bytes (or VALU lane-ops) of one launch of a stage."""
     nc = (deg + 1) ** 2
     rec = 48 + 24 * T_mean  # header + the T hull lines written
-    if stage == "preprocess":  # read points, delta, sigma, opacity, SH; write record, key, id, rect, count, hull
-        return "hbm", n * (12 * K + 12 + 12 * nc + rec + 4 + 4 + 8 + 4 + 4)
+    if stage == "preprocess":  # read points, delta, sigma, opacity, SH; write record, key, id, binning record, hull
+        return "hbm", n * (12 * K + 12 + 12 * nc + rec + 4 + 4 + 16 + 4)
     if stage == "depth_sort":  # one histogram read (4 B) + 4 passes x (read 8 B + write 8 B)
         return "hbm", n * (4 + 4 * 16)
-    if stage == "bin_scan":  # read id 4 + count 4; write sorted count 4 + offset 4
-        return "hbm", n * 16
-    if stage == "emit":  # per convex: id, offset, rect 16 B; per pair: write 8 B
-        return "hbm", n * 16 + m * 8
+    if stage == "bin_scan":  # read id 4 + binning record 16; write it in depth order 16 + count 4 + offset 4
+        return "hbm", n * 44
+    if stage == "emit":  # per convex: id, offset, binning record 24 B; per pair: write 8 B
+        return "hbm", n * 24 + m * 8
     if stage == "tile_sort":  # one histogram read (4 B) + 2 passes x (read 8 B + write 8 B) over the pairs
         return "hbm", m * (4 + 2 * 16)
     if stage == "ranges":
@@ -244,7 +244,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c3")
-    ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--cpu-sample", type=int, default=163840)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
     ap.add_argument("--forms", default="plain,batched,serving", help="comma list of plain, batched, serving")
