@@ -399,10 +399,10 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
 // forward pass stored its lines); gradients need relative, not absolute,
 // accuracy.
 template <int K>
-__device__ __forceinline__ void view_backward(int deg, const float *px, const float *py, const float *pz, float dl,
-                                              float sg, const float *f, const CamArgs &cam, uint32_t hp,
-                                              const RecHeader &hdr, const float *__restrict__ Ag, float *gp,
-                                              float &gdelta, float &gsigma, float &gopac, float *gsh)
+__device__ __forceinline__ void view_backward(int deg, const float *P, float dl, float sg, const float *f,
+                                              const CamArgs &cam, uint32_t hp, const RecHeader &hdr,
+                                              const float *__restrict__ Ag, float *G, float &gdelta, float &gsigma,
+                                              float &gopac, float *__restrict__ gsh, bool first)
 {
     // the instance's accumulator row, in 16-byte loads
     float A[acc_stride(K)];
@@ -413,6 +413,85 @@ __device__ __forceinline__ void view_backward(int deg, const float *px, const fl
     }
     const int T = (int)(hp >> 28);
     const int nc = (deg + 1) * (deg + 1);
+
+    // colour -> SH coefficients and the view direction (same arithmetic as the
+    // forward pass); first, while few geometry values are live
+    double cxw = 0, cyw = 0, czw = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) { cxw += P[3 * k]; cyw += P[3 * k + 1]; czw += P[3 * k + 2]; }
+    const double wx = cxw / K - cam.campos[0], wy = cyw / K - cam.campos[1], wz = czw / K - cam.campos[2];
+    const double inv = 1.0 / sqrt(wx * wx + wy * wy + wz * wz);
+    const float dx = (float)(wx * inv), dy = (float)(wy * inv), dz = (float)(wz * inv);
+    float Yb[16];
+    sh_eval(deg, dx, dy, dz, Yb);
+    float raw[3] = {0.5f, 0.5f, 0.5f};
+    const float4 *f4 = reinterpret_cast<const float4 *>(f); // degree 3: 192-byte rows, 16-byte loads
+    if (deg == 3) {
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            const float4 w = f4[q];
+            const float wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) raw[(4 * q + t) % 3] = fmaf(Yb[(4 * q + t) / 3], wv[t], raw[(4 * q + t) % 3]);
+        }
+    } else {
+        for (int c = 0; c < nc; ++c) {
+            raw[0] = fmaf(Yb[c], f[3 * c + 0], raw[0]);
+            raw[1] = fmaf(Yb[c], f[3 * c + 1], raw[1]);
+            raw[2] = fmaf(Yb[c], f[3 * c + 2], raw[2]);
+        }
+    }
+    float graw[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) graw[c] = raw[c] > 0.0f ? A[3 * K + 2 + c] : 0.0f;
+    // the SH gradient row of this convex (this thread's alone): stored by the
+    // first view that reaches it, added to by later ones
+    float4 *g4 = reinterpret_cast<float4 *>(gsh);
+    if (deg == 3) {
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            float gv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) gv[t] = graw[(4 * q + t) % 3] * Yb[(4 * q + t) / 3];
+            float4 o = make_float4(gv[0], gv[1], gv[2], gv[3]);
+            if (!first) {
+                const float4 pv = g4[q];
+                o = make_float4(pv.x + o.x, pv.y + o.y, pv.z + o.z, pv.w + o.w);
+            }
+            g4[q] = o;
+        }
+    } else {
+        for (int c = 0; c < nc; ++c)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) gsh[3 * c + t] = (first ? 0.0f : gsh[3 * c + t]) + graw[t] * Yb[c];
+    }
+    float wsum[16];
+    if (deg == 3) {
+        // read the coefficients again (from cache) rather than hold 48 registers across the stores
+        __asm__ volatile("" ::: "memory");
+#pragma unroll
+        for (int c = 0; c < 16; ++c) wsum[c] = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) { // wsum_c = sum_k graw_k f_ck, same order as below
+            const float4 w = f4[q];
+            const float wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int e = 4 * q + t;
+                wsum[e / 3] = (e % 3 == 0) ? graw[0] * wv[t] : wsum[e / 3] + graw[e % 3] * wv[t];
+            }
+        }
+    } else {
+        for (int c = 0; c < nc; ++c)
+            wsum[c] = graw[0] * f[3 * c + 0] + graw[1] * f[3 * c + 1] + graw[2] * f[3 * c + 2];
+    }
+    float gdx = 0.f, gdy = 0.f, gdz = 0.f;
+    sh_grad_dot(deg, dx, dy, dz, wsum, gdx, gdy, gdz);
+    // unit direction -> centre:  (I - dir dir^T) / |centre - campos|, then / K per point
+    const float dot = dx * gdx + dy * gdy + dz * gdz;
+    const float sc = (float)inv / K;
+    const float gcx = (gdx - dx * dot) * sc, gcy = (gdy - dy * dot) * sc, gcz = (gdz - dz * dot) * sc;
+
     const double r0 = cam.R[0], r1 = cam.R[1], r2 = cam.R[2], r3 = cam.R[3], r4 = cam.R[4], r5 = cam.R[5];
     const double r6 = cam.R[6], r7 = cam.R[7], r8 = cam.R[8];
     // per point: projected position relative to the origin, 1/Z, X/Z, Y/Z
@@ -420,7 +499,7 @@ __device__ __forceinline__ void view_backward(int deg, const float *px, const fl
     double zs = 0.0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const double x = px[k], y = py[k], z = pz[k];
+        const double x = P[3 * k], y = P[3 * k + 1], z = P[3 * k + 2];
         const double X = r0 * x + r1 * y + r2 * z + (double)cam.t[0];
         const double Y = r3 * x + r4 * y + r5 * z + (double)cam.t[1];
         const double Z = r6 * x + r7 * y + r8 * z + (double)cam.t[2];
@@ -497,65 +576,6 @@ __device__ __forceinline__ void view_backward(int deg, const float *px, const fl
             if (k == v) { gqx[k] += gvx[j]; gqy[k] += gvy[j]; }
     }
 
-    // colour -> SH coefficients and the view direction (same arithmetic as the forward pass)
-    double cxw = 0, cyw = 0, czw = 0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) { cxw += px[k]; cyw += py[k]; czw += pz[k]; }
-    const double wx = cxw / K - cam.campos[0], wy = cyw / K - cam.campos[1], wz = czw / K - cam.campos[2];
-    const double inv = 1.0 / sqrt(wx * wx + wy * wy + wz * wz);
-    const float dx = (float)(wx * inv), dy = (float)(wy * inv), dz = (float)(wz * inv);
-    float Yb[16];
-    sh_eval(deg, dx, dy, dz, Yb);
-    float raw[3] = {0.5f, 0.5f, 0.5f};
-    const float4 *f4 = reinterpret_cast<const float4 *>(f); // degree 3: 192-byte rows, 16-byte loads
-    if (deg == 3) {
-#pragma unroll
-        for (int q = 0; q < 12; ++q) {
-            const float4 w = f4[q];
-            const float wv[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-            for (int t = 0; t < 4; ++t) raw[(4 * q + t) % 3] = fmaf(Yb[(4 * q + t) / 3], wv[t], raw[(4 * q + t) % 3]);
-        }
-    } else {
-        for (int c = 0; c < nc; ++c) {
-            raw[0] = fmaf(Yb[c], f[3 * c + 0], raw[0]);
-            raw[1] = fmaf(Yb[c], f[3 * c + 1], raw[1]);
-            raw[2] = fmaf(Yb[c], f[3 * c + 2], raw[2]);
-        }
-    }
-    float graw[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) graw[c] = raw[c] > 0.0f ? A[3 * K + 2 + c] : 0.0f;
-    float wsum[16];
-    for (int c = 0; c < nc; ++c) {
-        gsh[3 * c + 0] += graw[0] * Yb[c];
-        gsh[3 * c + 1] += graw[1] * Yb[c];
-        gsh[3 * c + 2] += graw[2] * Yb[c];
-    }
-    if (deg == 3) {
-#pragma unroll
-        for (int c = 0; c < 16; ++c) wsum[c] = 0.0f;
-#pragma unroll
-        for (int q = 0; q < 12; ++q) { // wsum_c = sum_k graw_k f_ck, same order as below
-            const float4 w = f4[q];
-            const float wv[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int e = 4 * q + t;
-                wsum[e / 3] = (e % 3 == 0) ? graw[0] * wv[t] : wsum[e / 3] + graw[e % 3] * wv[t];
-            }
-        }
-    } else {
-        for (int c = 0; c < nc; ++c)
-            wsum[c] = graw[0] * f[3 * c + 0] + graw[1] * f[3 * c + 1] + graw[2] * f[3 * c + 2];
-    }
-    float gdx = 0.f, gdy = 0.f, gdz = 0.f;
-    sh_grad_dot(deg, dx, dy, dz, wsum, gdx, gdy, gdz);
-    // unit direction -> centre:  (I - dir dir^T) / |centre - campos|, then / K per point
-    const float dot = dx * gdx + dy * gdy + dz * gdz;
-    const float sc = (float)inv / K;
-    const float gcx = (gdx - dx * dot) * sc, gcy = (gdy - dy * dot) * sc, gcz = (gdz - dz * dot) * sc;
-
     // projection and depth -> camera space -> world (R^T)
     const float fx = cam.fx, fy = cam.fy;
     const float R0 = cam.R[0], R1 = cam.R[1], R2 = cam.R[2], R3 = cam.R[3], R4 = cam.R[4], R5 = cam.R[5];
@@ -564,15 +584,13 @@ __device__ __forceinline__ void view_backward(int deg, const float *px, const fl
     for (int k = 0; k < K; ++k) {
         const float gX = gqx[k] * fx * iz[k], gY = gqy[k] * fy * iz[k];
         const float gZ = -(gX * xz[k] + gY * yz[k]) + gd / K;
-        gp[3 * k + 0] += R0 * gX + R3 * gY + R6 * gZ + gcx;
-        gp[3 * k + 1] += R1 * gX + R4 * gY + R7 * gZ + gcy;
-        gp[3 * k + 2] += R2 * gX + R5 * gY + R8 * gZ + gcz;
+        G[3 * k + 0] += R0 * gX + R3 * gY + R6 * gZ + gcx;
+        G[3 * k + 1] += R1 * gX + R4 * gY + R7 * gZ + gcy;
+        G[3 * k + 2] += R2 * gX + R5 * gY + R8 * gZ + gcz;
     }
 }
 
 constexpr int PB_BLOCK = 128;
-constexpr int PB_SH_STRIDE = 49; // odd LDS row strides keep per-thread rows conflict-free
-
 // Block-cooperative, coalesced copies between a contiguous global run of
 // `rows` rows of W floats and LDS rows of stride S.
 template <int W, int S> __device__ __forceinline__ void rows_to_lds(float *lds, const float *g, int rows)
@@ -583,19 +601,10 @@ template <int W, int S> __device__ __forceinline__ void rows_from_lds(float *g, 
 {
     for (int j = threadIdx.x; j < rows * W; j += PB_BLOCK) g[j] = lds[(j / W) * S + j % W];
 }
-__device__ __forceinline__ void sh_rows(bool to_lds, int deg, float *lds, float *g, int rows)
-{
-    switch (deg) {
-    case 0: to_lds ? rows_to_lds<3, PB_SH_STRIDE>(lds, g, rows) : rows_from_lds<3, PB_SH_STRIDE>(g, lds, rows); break;
-    case 1: to_lds ? rows_to_lds<12, PB_SH_STRIDE>(lds, g, rows) : rows_from_lds<12, PB_SH_STRIDE>(g, lds, rows); break;
-    case 2: to_lds ? rows_to_lds<27, PB_SH_STRIDE>(lds, g, rows) : rows_from_lds<27, PB_SH_STRIDE>(g, lds, rows); break;
-    default: to_lds ? rows_to_lds<48, PB_SH_STRIDE>(lds, g, rows) : rows_from_lds<48, PB_SH_STRIDE>(g, lds, rows); break;
-    }
-}
-
-// One thread per convex, 128 convexes per workgroup.  Points are staged
-// through LDS with coalesced loads, the SH gradient is accumulated over the
-// views in LDS, and all gradients leave through LDS as coalesced stores.
+// One thread per convex, 128 convexes per workgroup.  Points arrive and their
+// gradients leave through LDS as coalesced rows (the point gradients are
+// summed over the views in LDS); each thread keeps its convex's SH gradient
+// row in global memory itself.
 template <int K>
 __global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
     int n, int nviews, int deg, const float *__restrict__ points, const float *__restrict__ delta,
@@ -606,50 +615,40 @@ __global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
 {
     constexpr int PS = 3 * K + 1;
     __shared__ float s_pts[PB_BLOCK * PS];
-    __shared__ float s_gsh[PB_BLOCK * PB_SH_STRIDE];
+    __shared__ float s_gp[PB_BLOCK * PS];
     const int base = blockIdx.x * PB_BLOCK;
     const int cnt = min(PB_BLOCK, n - base);
     const int tid = threadIdx.x;
     const int nc = (deg + 1) * (deg + 1);
     rows_to_lds<3 * K, PS>(s_pts, points + (size_t)base * 3 * K, cnt);
-    for (int j = tid; j < PB_BLOCK * PB_SH_STRIDE; j += PB_BLOCK) s_gsh[j] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) s_gp[tid * PS + k] = 0.0f;
     __syncthreads();
 
     const int i = base + tid;
-    float gp[3 * K];
-#pragma unroll
-    for (int k = 0; k < 3 * K; ++k) gp[k] = 0.0f;
-    float gdelta = 0.0f, gsigma = 0.0f, gopac = 0.0f;
     if (tid < cnt) {
-        float px[K], py[K], pz[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            px[k] = s_pts[tid * PS + 3 * k];
-            py[k] = s_pts[tid * PS + 3 * k + 1];
-            pz[k] = s_pts[tid * PS + 3 * k + 2];
-        }
+        float gdelta = 0.0f, gsigma = 0.0f, gopac = 0.0f;
         const float dl = delta[i], sg = sigma[i];
         const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
+        float *gsh = g_sh + (size_t)i * 3 * nc;
+        bool first = true;
         for (int v = 0; v < nviews; ++v) {
             const size_t inst = (size_t)v * n + i;
             const uint32_t hp = hullpk[inst];
             if ((int)(hp >> 28) < 3) continue; // dropped in this view: no gradient
             const RecHeader hdr = *reinterpret_cast<const RecHeader *>(records + inst * rec_stride(K));
-            view_backward<K>(deg, px, py, pz, dl, sg, sh + (size_t)i * 3 * nc, views[v].cam, hp, hdr,
-                             acc + inst * acc_stride(K), gp, gdelta, gsigma, gopac, &s_gsh[tid * PB_SH_STRIDE]);
+            view_backward<K>(deg, &s_pts[tid * PS], dl, sg, sh + (size_t)i * 3 * nc, views[v].cam, hp, hdr,
+                             acc + inst * acc_stride(K), &s_gp[tid * PS], gdelta, gsigma, gopac, gsh, first);
+            first = false;
         }
-    }
-    __syncthreads();
-    if (tid < cnt) {
-#pragma unroll
-        for (int k = 0; k < 3 * K; ++k) s_pts[tid * PS + k] = gp[k];
+        if (first) // no view reached the convex
+            for (int c = 0; c < 3 * nc; ++c) gsh[c] = 0.0f;
         g_delta[i] = gdelta;
         g_sigma[i] = gsigma;
         g_opacity[i] = gopac;
     }
     __syncthreads();
-    rows_from_lds<3 * K, PS>(g_points + (size_t)base * 3 * K, s_pts, cnt);
-    sh_rows(false, deg, s_gsh, g_sh + (size_t)base * 3 * nc, cnt);
+    rows_from_lds<3 * K, PS>(g_points + (size_t)base * 3 * K, s_gp, cnt);
 }
 
 // ------------------------------------------------------------- launchers ---
