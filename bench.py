@@ -187,6 +187,54 @@ def bench_serving(rates, duration):
     return out
 
 
+def bench_light(scene, cam, target, steps, warmup, ms_f32):
+    """The same fwd+bwd step with the scene stored in 16-bit floats (the paper's
+    light model, Sec. 4.2): IEEE half storage, float32 arithmetic, float32 gradients."""
+    import torch
+
+    from paper_2411_14974_amd.binding import FLAG_TIMING, DeviceScene, Renderer, make_params
+    dev = torch.device("cuda:0")
+    R = Renderer(0)
+    ds = DeviceScene.from_scene(scene, dev, dtype=torch.float16)
+    tgt = torch.from_numpy(target).to(dev)
+    H, W = tgt.shape[:2]
+    rgb = torch.empty((H, W, 3), device=dev)
+    dl = torch.empty_like(rgb)
+    grads = {k: torch.empty_like(getattr(ds, k), dtype=torch.float32) for k in ("points", "delta", "sigma", "opacity", "sh")}
+
+    def step(params):
+        out, st = R.forward(ds, cam, params, want_state=True, out=rgb)
+        R.l1_loss_grad(out, tgt, grad=dl)
+        R.backward(st, dl, grads=grads)
+        return st
+
+    def run(params, n):
+        held = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            held.append(step(params))
+            if len(held) > 2:
+                held.pop(0).release()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for s in held:
+            s.release()
+        return (t1 - t0) * 1e3 / n
+
+    run(make_params(), max(warmup, 3))
+    ms = run(make_params(), steps)
+    R.timing(reset=True)
+    run(make_params(flags=FLAG_TIMING), steps)
+    tm = R.timing(reset=True)
+    R.close()
+    scene_bytes = sum(getattr(ds, k).numel() * 2 for k in ("points", "delta", "sigma", "opacity", "sh"))
+    return {"storage": "float16 scene arrays, float32 arithmetic and gradients", "ms_per_step": ms,
+            "mpixels_per_s": W * H / (ms / 1e3) / 1e6, "speedup_vs_f32": ms_f32 / ms,
+            "scene_mb": scene_bytes / 1e6,
+            "stages_ms": {k: round(t / c, 4) for k, (t, c) in tm.items() if c and k.startswith("preprocess")}}
+
+
 def counter_traffic(stage, workload):
     """HBM bytes per launch of a stage's kernel from the committed rocprofv3
     counters (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by what the same
@@ -247,7 +295,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=163840)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
-    ap.add_argument("--forms", default="plain,batched,serving", help="comma list of plain, batched, serving")
+    ap.add_argument("--forms", default="plain,light,batched,serving",
+                    help="comma list of plain, light (16-bit scene), batched, serving")
     ap.add_argument("--serve-rates", default="50,200,800", help="request rates (req/s) of the serving sweep")
     ap.add_argument("--serve-seconds", type=float, default=1.5)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -353,6 +402,8 @@ def main():
         torch.cuda.synchronize()
     R.close()
     forms = set(args.forms.split(","))
+    if "light" in forms:
+        line["light_16bit"] = bench_light(scene, cam, target, args.steps, args.warmup, ms)
     if "batched" in forms:
         line["batched"] = bench_batched(max(3, args.steps // 4), 2)
     if "serving" in forms:

@@ -6,7 +6,8 @@
  *   - Pointers to scene, image and gradient arrays are DEVICE pointers (HBM of
  *     the context's GPU); structs (cs_scene, cs_camera, cs_params, cs_grads)
  *     themselves live in host memory and are read during the call only.
- *   - All arrays are dense, row-major, float32, with the shapes stated below.
+ *   - All arrays are dense, row-major, with the shapes stated below; float32,
+ *     except the scene arrays, which may also hold 16-bit values (cs_scene.dtype).
  *   - The caller owns every scene, image and gradient buffer; the library never
  *     frees them.  The library owns cs_ctx, cs_fwd_state and their workspace.
  *   - Work is enqueued on `hip_stream` (a hipStream_t; NULL = the null stream)
@@ -44,6 +45,16 @@ extern "C" {
 #define CS_MAX_K 8
 #define CS_MAX_SH_DEGREE 3
 
+/* Storage formats of the scene arrays (cs_scene.dtype).  The paper's light
+ * model stores its convex parameters in 16-bit precision (Sec. 4.2,
+ * Experimental Setup; Supp. Initialization & Hyperparameters); the kernels convert
+ * every loaded value to float32 (exactly: both 16-bit formats are subsets of
+ * float32) and compute as for float32 scenes, so a 16-bit scene renders
+ * exactly like the float32 scene of the same values.  Gradients stay float32. */
+#define CS_DTYPE_F32 0  /* IEEE binary32 */
+#define CS_DTYPE_F16 1  /* IEEE binary16 */
+#define CS_DTYPE_BF16 2 /* bfloat16: the upper half of a binary32 */
+
 typedef struct cs_ctx cs_ctx;             /* device, workspace, tuning and serving state */
 typedef struct cs_fwd_state cs_fwd_state; /* what the backward pass needs from a forward pass */
 
@@ -59,19 +70,23 @@ typedef struct {
     float znear;
 } cs_camera;
 
-/* Scene (paper Sec. 3.2 point-set convexes; Sec. 3.3 optimised parameters). */
+/* Scene (paper Sec. 3.2 point-set convexes; Sec. 3.3 optimised parameters).
+ * The five arrays hold elements of the format `dtype` (CS_DTYPE_*), aligned
+ * to their element size. */
 typedef struct {
     int32_t n;          /* number of convexes, >= 0 */
     int32_t k;          /* points per convex, 3 <= k <= 8 */
     int32_t sh_degree;  /* 0 <= sh_degree <= 3 */
-    const float *points;  /* [n][k][3] world space */
-    const float *delta;   /* [n] smoothness, activated, > 0 */
-    const float *sigma;   /* [n] sharpness, activated, > 0 */
-    const float *opacity; /* [n] in [0, 1] */
-    const float *sh;      /* [n][(sh_degree+1)^2][3] */
+    const void *points;  /* [n][k][3] world space */
+    const void *delta;   /* [n] smoothness, activated, > 0 */
+    const void *sigma;   /* [n] sharpness, activated, > 0 */
+    const void *opacity; /* [n] in [0, 1] */
+    const void *sh;      /* [n][(sh_degree+1)^2][3] */
+    int32_t dtype;       /* CS_DTYPE_F32 (0), CS_DTYPE_F16 or CS_DTYPE_BF16 */
 } cs_scene;
 
-/* Gradients, same shapes as the scene arrays; OVERWRITTEN by the backward call. */
+/* Gradients, same shapes as the scene arrays, float32 whatever the scene's
+ * dtype; OVERWRITTEN by the backward call. */
 typedef struct {
     float *points, *delta, *sigma, *opacity, *sh;
 } cs_grads;

@@ -21,6 +21,7 @@ MODE_EXACT = 0
 MODE_MATCHED = 1
 EPS_ALPHA = 1e-6
 T_MIN = 1e-5
+DEGENERATE = 256  # or-ed into Convex.status: a near-collinear point triple makes the hull ill-posed
 
 
 def build(force: bool = True) -> str:

@@ -13,8 +13,11 @@ from .binding import DeviceScene, Renderer, make_camera, make_params
 class ConvexRender(torch.autograd.Function):
     @staticmethod
     def forward(ctx, points, delta, sigma, opacity, sh, renderer: Renderer, cam, params):
+        # 16-bit parameters (the light model) are rendered from their own
+        # storage; autograd casts the float32 gradients back to their dtype
+        dtype = points.dtype if points.dtype in (torch.float16, torch.bfloat16) else torch.float32
         scene = DeviceScene(points.detach(), delta.detach(), sigma.detach(), opacity.detach(), sh.detach(),
-                            device=points.device)
+                            device=points.device, dtype=dtype)
         rgb, state = renderer.forward(scene, cam, params, want_state=True)
         ctx.renderer, ctx.state = renderer, state
         return rgb

@@ -26,6 +26,10 @@ EXPORTED = (
     "cs_serve_start", "cs_serve_resume", "cs_serve_stop", "cs_scene_register", "cs_scene_unregister",
     "cs_serve_submit", "cs_serve_wait", "cs_serve_get_stats",
 )
+# storage formats of the scene arrays (cs_scene.dtype)
+DTYPE_F32, DTYPE_F16, DTYPE_BF16 = 0, 1, 2
+_DTYPES = {torch.float32: DTYPE_F32, torch.float16: DTYPE_F16, torch.bfloat16: DTYPE_BF16}
+
 FLAG_TIMING = 1
 FLAG_LONGEST_FIRST = 2
 FLAG_GRAPH = 4
@@ -54,7 +58,8 @@ class Camera(C.Structure):
 
 class SceneS(C.Structure):
     _fields_ = [("n", C.c_int32), ("k", C.c_int32), ("sh_degree", C.c_int32), ("points", C.c_void_p),
-                ("delta", C.c_void_p), ("sigma", C.c_void_p), ("opacity", C.c_void_p), ("sh", C.c_void_p)]
+                ("delta", C.c_void_p), ("sigma", C.c_void_p), ("opacity", C.c_void_p), ("sh", C.c_void_p),
+                ("dtype", C.c_int32)]
 
 
 class GradsS(C.Structure):
@@ -163,17 +168,21 @@ def make_params(eps_alpha=1e-6, t_min=1e-5, background=(0.0, 0.0, 0.0), tile=0, 
 
 
 class DeviceScene:
-    """Scene arrays resident on the GPU (float32, contiguous)."""
+    """Scene arrays resident on the GPU, contiguous, all of one storage dtype:
+    float32, or float16 / bfloat16 (the light model's 16-bit parameters)."""
 
-    def __init__(self, points, delta, sigma, opacity, sh, device="cuda"):
+    def __init__(self, points, delta, sigma, opacity, sh, device="cuda", dtype=torch.float32):
+        if dtype not in _DTYPES:
+            raise ValueError(f"scene dtype {dtype} is not float32, float16 or bfloat16")
         t = lambda a: (a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a))).to(
-            device=device, dtype=torch.float32).contiguous()
+            device=device, dtype=dtype).contiguous()
         self.points, self.delta, self.sigma, self.opacity, self.sh = t(points), t(delta), t(sigma), t(opacity), t(sh)
+        self.dtype = dtype
         self._validate()
 
     @classmethod
-    def from_scene(cls, scene, device="cuda"):
-        return cls(scene.points, scene.delta, scene.sigma, scene.opacity, scene.sh, device)
+    def from_scene(cls, scene, device="cuda", dtype=torch.float32):
+        return cls(scene.points, scene.delta, scene.sigma, scene.opacity, scene.sh, device, dtype)
 
     def _validate(self):
         n, k = self.points.shape[:2]
@@ -201,7 +210,7 @@ class DeviceScene:
 
     def struct(self) -> SceneS:
         return SceneS(self.n, self.k, self.deg, self.points.data_ptr(), self.delta.data_ptr(),
-                      self.sigma.data_ptr(), self.opacity.data_ptr(), self.sh.data_ptr())
+                      self.sigma.data_ptr(), self.opacity.data_ptr(), self.sh.data_ptr(), _DTYPES[self.dtype])
 
 
 class FwdState:
@@ -275,7 +284,8 @@ class Renderer:
         scene = state.scene
         dl = dl_drgb.contiguous()
         if grads is None:
-            grads = {k: torch.empty_like(getattr(scene, k)) for k in ("points", "delta", "sigma", "opacity", "sh")}
+            grads = {k: torch.empty_like(getattr(scene, k), dtype=torch.float32)
+                     for k in ("points", "delta", "sigma", "opacity", "sh")}
         gS = GradsS(grads["points"].data_ptr(), grads["delta"].data_ptr(), grads["sigma"].data_ptr(),
                     grads["opacity"].data_ptr(), grads["sh"].data_ptr())
         sS = scene.struct()
@@ -314,7 +324,8 @@ class Renderer:
         dls = [d.contiguous() for d in dl_drgb_list]
         ptrs = (C.c_void_p * len(dls))(*[d.data_ptr() for d in dls])
         if grads is None:
-            grads = {k: torch.empty_like(getattr(scene, k)) for k in ("points", "delta", "sigma", "opacity", "sh")}
+            grads = {k: torch.empty_like(getattr(scene, k), dtype=torch.float32)
+                     for k in ("points", "delta", "sigma", "opacity", "sh")}
         gS = GradsS(grads["points"].data_ptr(), grads["delta"].data_ptr(), grads["sigma"].data_ptr(),
                     grads["opacity"].data_ptr(), grads["sh"].data_ptr())
         sS = scene.struct()

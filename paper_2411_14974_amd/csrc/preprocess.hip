@@ -14,6 +14,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "convexsplat.h"
 #include "sh.hpp"
 
 namespace cs {
@@ -23,6 +24,28 @@ namespace {
 __device__ __forceinline__ double orient(double ax, double ay, double bx, double by, double cx, double cy)
 {
     return (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
+}
+
+// Storage formats of the scene parameters: float32, or the 16-bit formats of
+// the light model (IEEE half, bfloat16).  Every load converts to float32
+// (exactly), and all arithmetic after it is the float32 path's.
+struct Half { uint16_t b; };
+struct BHalf { uint16_t b; };
+__device__ __forceinline__ float to_f32(float v) { return v; }
+__device__ __forceinline__ float to_f32(Half v) { return (float)__builtin_bit_cast(_Float16, v.b); }
+__device__ __forceinline__ float to_f32(BHalf v) { return __uint_as_float((uint32_t)v.b << 16); }
+template <typename P> __device__ __forceinline__ float ld(const P *p, size_t i) { return to_f32(p[i]); }
+// Values 4q .. 4q+3 of a row: one 16-byte load for float32, one 8-byte load
+// for the 16-bit formats (little-endian: element 4q is the low half of x).
+template <typename P> __device__ __forceinline__ float4 ld4(const P *p, int q)
+{
+    if constexpr (sizeof(P) == 4) {
+        return reinterpret_cast<const float4 *>(p)[q];
+    } else {
+        const uint2 w = reinterpret_cast<const uint2 *>(p)[q];
+        return make_float4(to_f32(P{(uint16_t)(w.x & 0xFFFFu)}), to_f32(P{(uint16_t)(w.x >> 16)}),
+                           to_f32(P{(uint16_t)(w.y & 0xFFFFu)}), to_f32(P{(uint16_t)(w.y >> 16)}));
+    }
 }
 
 // Inclusive pixel range [lo, hi] whose centres (u + 0.5) fall in [a, b], clamped to [0, n).
@@ -42,10 +65,10 @@ constexpr int PF_BLOCK = 256;
 
 // DBG: also fill the per-instance debug record (a separate instantiation, so
 // that the debug copies of the lines cost no registers in the plain one).
-template <int K, bool DBG>
+template <int K, bool DBG, typename P>
 __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
-    int n, int deg, const float *__restrict__ points, const float *__restrict__ delta,
-    const float *__restrict__ sigma, const float *__restrict__ opacity, const float *__restrict__ sh,
+    int n, int deg, const P *__restrict__ points, const P *__restrict__ delta,
+    const P *__restrict__ sigma, const P *__restrict__ opacity, const P *__restrict__ sh,
     const FrameHeader *__restrict__ frame, RenderArgs ra, uint8_t *__restrict__ records, uint32_t *__restrict__ keys,
     uint32_t *__restrict__ ids, uint4 *__restrict__ bins, uint32_t *__restrict__ hullpk,
     DebugConvex *__restrict__ dbg)
@@ -56,8 +79,8 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
     const int base = blockIdx.x * PF_BLOCK;
     const int cnt = min(PF_BLOCK, n - base);
     {
-        const float *g = points + (size_t)base * 3 * K;
-        for (int j = threadIdx.x; j < cnt * 3 * K; j += PF_BLOCK) s_pts[(j / (3 * K)) * PS + j % (3 * K)] = g[j];
+        const P *g = points + (size_t)base * 3 * K;
+        for (int j = threadIdx.x; j < cnt * 3 * K; j += PF_BLOCK) s_pts[(j / (3 * K)) * PS + j % (3 * K)] = ld(g, j);
     }
     __syncthreads();
     const int i = base + threadIdx.x;
@@ -120,9 +143,9 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
             zs += Z[k];
         }
         dd = zs / K;
-        dp = dd * (double)delta[i];
-        sp = dd * (double)sigma[i];
-        const double o = (double)opacity[i];
+        dp = dd * (double)ld(delta, i);
+        sp = dd * (double)ld(sigma, i);
+        const double o = (double)ld(opacity, i);
 
         // start at the point with the smallest (y, x)
         int start = 0;
@@ -234,13 +257,12 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
             float Yb[16];
             sh_eval(deg, (float)(vx * inv), (float)(vy * inv), (float)(vz * inv), Yb);
             const int nc = (deg + 1) * (deg + 1);
-            const float *f = sh + (size_t)i * nc * 3;
+            const P *f = sh + (size_t)i * nc * 3;
             float raw[3] = {0.5f, 0.5f, 0.5f};
-            if (deg == 3) { // 192-byte rows: 16-byte loads, same summation order
-                const float4 *f4 = reinterpret_cast<const float4 *>(f);
+            if (deg == 3) { // 48-value rows: 4 values per load, same summation order
 #pragma unroll
                 for (int q = 0; q < 12; ++q) {
-                    const float4 w = f4[q];
+                    const float4 w = ld4(f, q);
                     const float wv[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
@@ -250,9 +272,9 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
                 }
             } else {
                 for (int c = 0; c < nc; ++c) {
-                    raw[0] = fmaf(Yb[c], f[3 * c + 0], raw[0]);
-                    raw[1] = fmaf(Yb[c], f[3 * c + 1], raw[1]);
-                    raw[2] = fmaf(Yb[c], f[3 * c + 2], raw[2]);
+                    raw[0] = fmaf(Yb[c], ld(f, 3 * c + 0), raw[0]);
+                    raw[1] = fmaf(Yb[c], ld(f, 3 * c + 1), raw[1]);
+                    raw[2] = fmaf(Yb[c], ld(f, 3 * c + 2), raw[2]);
                 }
             }
 #pragma unroll
@@ -398,8 +420,8 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
 // pixel coordinates relative to the record's origin, the frame in which the
 // forward pass stored its lines); gradients need relative, not absolute,
 // accuracy.
-template <int K>
-__device__ __forceinline__ void view_backward(int deg, const float *P, float dl, float sg, const float *f,
+template <int K, typename SP>
+__device__ __forceinline__ void view_backward(int deg, const float *P, float dl, float sg, const SP *f,
                                               const CamArgs &cam, uint32_t hp, const RecHeader &hdr,
                                               const float *__restrict__ Ag, float *G, float &gdelta, float &gsigma,
                                               float &gopac, float *__restrict__ gsh, bool first)
@@ -425,20 +447,19 @@ __device__ __forceinline__ void view_backward(int deg, const float *P, float dl,
     float Yb[16];
     sh_eval(deg, dx, dy, dz, Yb);
     float raw[3] = {0.5f, 0.5f, 0.5f};
-    const float4 *f4 = reinterpret_cast<const float4 *>(f); // degree 3: 192-byte rows, 16-byte loads
-    if (deg == 3) {
+    if (deg == 3) { // 48-value rows: 4 values per load
 #pragma unroll
         for (int q = 0; q < 12; ++q) {
-            const float4 w = f4[q];
+            const float4 w = ld4(f, q);
             const float wv[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
             for (int t = 0; t < 4; ++t) raw[(4 * q + t) % 3] = fmaf(Yb[(4 * q + t) / 3], wv[t], raw[(4 * q + t) % 3]);
         }
     } else {
         for (int c = 0; c < nc; ++c) {
-            raw[0] = fmaf(Yb[c], f[3 * c + 0], raw[0]);
-            raw[1] = fmaf(Yb[c], f[3 * c + 1], raw[1]);
-            raw[2] = fmaf(Yb[c], f[3 * c + 2], raw[2]);
+            raw[0] = fmaf(Yb[c], ld(f, 3 * c + 0), raw[0]);
+            raw[1] = fmaf(Yb[c], ld(f, 3 * c + 1), raw[1]);
+            raw[2] = fmaf(Yb[c], ld(f, 3 * c + 2), raw[2]);
         }
     }
     float graw[3];
@@ -473,7 +494,7 @@ __device__ __forceinline__ void view_backward(int deg, const float *P, float dl,
         for (int c = 0; c < 16; ++c) wsum[c] = 0.0f;
 #pragma unroll
         for (int q = 0; q < 12; ++q) { // wsum_c = sum_k graw_k f_ck, same order as below
-            const float4 w = f4[q];
+            const float4 w = ld4(f, q);
             const float wv[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
@@ -483,7 +504,7 @@ __device__ __forceinline__ void view_backward(int deg, const float *P, float dl,
         }
     } else {
         for (int c = 0; c < nc; ++c)
-            wsum[c] = graw[0] * f[3 * c + 0] + graw[1] * f[3 * c + 1] + graw[2] * f[3 * c + 2];
+            wsum[c] = graw[0] * ld(f, 3 * c + 0) + graw[1] * ld(f, 3 * c + 1) + graw[2] * ld(f, 3 * c + 2);
     }
     float gdx = 0.f, gdy = 0.f, gdz = 0.f;
     sh_grad_dot(deg, dx, dy, dz, wsum, gdx, gdy, gdz);
@@ -593,9 +614,9 @@ __device__ __forceinline__ void view_backward(int deg, const float *P, float dl,
 constexpr int PB_BLOCK = 128;
 // Block-cooperative, coalesced copies between a contiguous global run of
 // `rows` rows of W floats and LDS rows of stride S.
-template <int W, int S> __device__ __forceinline__ void rows_to_lds(float *lds, const float *g, int rows)
+template <int W, int S, typename P> __device__ __forceinline__ void rows_to_lds(float *lds, const P *g, int rows)
 {
-    for (int j = threadIdx.x; j < rows * W; j += PB_BLOCK) lds[(j / W) * S + j % W] = g[j];
+    for (int j = threadIdx.x; j < rows * W; j += PB_BLOCK) lds[(j / W) * S + j % W] = ld(g, j);
 }
 template <int W, int S> __device__ __forceinline__ void rows_from_lds(float *g, const float *lds, int rows)
 {
@@ -605,10 +626,10 @@ template <int W, int S> __device__ __forceinline__ void rows_from_lds(float *g, 
 // gradients leave through LDS as coalesced rows (the point gradients are
 // summed over the views in LDS); each thread keeps its convex's SH gradient
 // row in global memory itself.
-template <int K>
+template <int K, typename P>
 __global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
-    int n, int nviews, int deg, const float *__restrict__ points, const float *__restrict__ delta,
-    const float *__restrict__ sigma, const float *__restrict__ sh, const FrameHeader *__restrict__ frame,
+    int n, int nviews, int deg, const P *__restrict__ points, const P *__restrict__ delta,
+    const P *__restrict__ sigma, const P *__restrict__ sh, const FrameHeader *__restrict__ frame,
     const uint8_t *__restrict__ records, const uint32_t *__restrict__ hullpk, const float *__restrict__ acc,
     float *__restrict__ g_points, float *__restrict__ g_delta, float *__restrict__ g_sigma,
     float *__restrict__ g_opacity, float *__restrict__ g_sh)
@@ -628,7 +649,7 @@ __global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
     const int i = base + tid;
     if (tid < cnt) {
         float gdelta = 0.0f, gsigma = 0.0f, gopac = 0.0f;
-        const float dl = delta[i], sg = sigma[i];
+        const float dl = ld(delta, i), sg = ld(sigma, i);
         const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
         float *gsh = g_sh + (size_t)i * 3 * nc;
         bool first = true;
@@ -664,33 +685,44 @@ __global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
     default: break;                                                                                                \
     }
 
-void launch_preprocess_fwd(hipStream_t st, int n, int nviews, int K, int deg, const float *points,
-                           const float *delta, const float *sigma, const float *opacity, const float *sh,
+#define CS_DISPATCH_P(DT, ...)                                                                                     \
+    switch (DT) {                                                                                                  \
+    case CS_DTYPE_F32: { using PP = float; __VA_ARGS__; } break;                                                   \
+    case CS_DTYPE_F16: { using PP = Half; __VA_ARGS__; } break;                                                    \
+    case CS_DTYPE_BF16: { using PP = BHalf; __VA_ARGS__; } break;                                                  \
+    default: break;                                                                                                \
+    }
+
+void launch_preprocess_fwd(hipStream_t st, int n, int nviews, int K, int deg, int dtype, const void *points,
+                           const void *delta, const void *sigma, const void *opacity, const void *sh,
                            const FrameHeader *views, const RenderArgs &ra, uint8_t *records, uint32_t *keys,
                            uint32_t *ids, uint4 *bins, uint32_t *hullpk, DebugConvex *dbg)
 {
     if (n <= 0 || nviews <= 0) return;
     dim3 grid((n + PF_BLOCK - 1) / PF_BLOCK, nviews), block(PF_BLOCK);
     if (dbg)
-        CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_fwd_kernel<KK, true>), grid, block, 0, st, n, deg, points,
-                                            delta, sigma, opacity, sh, views, ra, records, keys, ids, bins, hullpk,
-                                            dbg))
+        CS_DISPATCH_P(dtype, CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_fwd_kernel<KK, true, PP>), grid, block, 0, st, n,
+                                                             deg, (const PP *)points, (const PP *)delta,
+                                                             (const PP *)sigma, (const PP *)opacity, (const PP *)sh,
+                                                             views, ra, records, keys, ids, bins, hullpk, dbg)))
     else
-        CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_fwd_kernel<KK, false>), grid, block, 0, st, n, deg, points,
-                                            delta, sigma, opacity, sh, views, ra, records, keys, ids, bins, hullpk,
-                                            dbg))
+        CS_DISPATCH_P(dtype, CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_fwd_kernel<KK, false, PP>), grid, block, 0, st,
+                                                             n, deg, (const PP *)points, (const PP *)delta,
+                                                             (const PP *)sigma, (const PP *)opacity, (const PP *)sh,
+                                                             views, ra, records, keys, ids, bins, hullpk, dbg)))
 }
 
-void launch_preprocess_bwd(hipStream_t st, int n, int nviews, int K, int deg, const float *points,
-                           const float *delta, const float *sigma, const float *sh, const FrameHeader *views,
+void launch_preprocess_bwd(hipStream_t st, int n, int nviews, int K, int deg, int dtype, const void *points,
+                           const void *delta, const void *sigma, const void *sh, const FrameHeader *views,
                            const uint8_t *records, const uint32_t *hullpk, const float *acc, float *g_points, float *g_delta,
                            float *g_sigma, float *g_opacity, float *g_sh)
 {
     if (n <= 0) return;
     dim3 grid((n + PB_BLOCK - 1) / PB_BLOCK), block(PB_BLOCK);
-    CS_DISPATCH_K(K, hipLaunchKernelGGL(preprocess_bwd_kernel<KK>, grid, block, 0, st, n, nviews, deg, points, delta,
-                                        sigma, sh, views, records, hullpk, acc, g_points, g_delta, g_sigma,
-                                        g_opacity, g_sh));
+    CS_DISPATCH_P(dtype, CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_bwd_kernel<KK, PP>), grid, block, 0, st, n,
+                                                         nviews, deg, (const PP *)points, (const PP *)delta,
+                                                         (const PP *)sigma, (const PP *)sh, views, records, hullpk,
+                                                         acc, g_points, g_delta, g_sigma, g_opacity, g_sh)));
 }
 
 } // namespace cs

@@ -17,11 +17,11 @@
 #include "runtime.hpp"
 
 namespace cs {
-void launch_preprocess_fwd(hipStream_t, int, int, int, int, const float *, const float *, const float *,
-                           const float *, const float *, const FrameHeader *, const RenderArgs &, uint8_t *,
+void launch_preprocess_fwd(hipStream_t, int, int, int, int, int, const void *, const void *, const void *,
+                           const void *, const void *, const FrameHeader *, const RenderArgs &, uint8_t *,
                            uint32_t *, uint32_t *, uint4 *, uint32_t *, DebugConvex *);
-void launch_preprocess_bwd(hipStream_t, int, int, int, int, const float *, const float *, const float *,
-                           const float *, const FrameHeader *, const uint8_t *, const uint32_t *, const float *,
+void launch_preprocess_bwd(hipStream_t, int, int, int, int, int, const void *, const void *, const void *,
+                           const void *, const FrameHeader *, const uint8_t *, const uint32_t *, const float *,
                            float *, float *, float *, float *, float *);
 void radix_sort(hipStream_t, uint32_t **, uint32_t **, uint32_t **, uint32_t **, uint32_t, const uint32_t *, uint32_t, int,
                 uint32_t *, int, uint32_t *);
@@ -275,6 +275,8 @@ int check_scene(const cs_scene *s)
         return fail(CS_EINVAL, "scene.sh_degree = %d outside [0, 3]", s->sh_degree);
     if (s->n > 0 && (!s->points || !s->delta || !s->sigma || !s->opacity || !s->sh))
         return fail(CS_EINVAL, "scene array pointer is NULL");
+    if (s->dtype != CS_DTYPE_F32 && s->dtype != CS_DTYPE_F16 && s->dtype != CS_DTYPE_BF16)
+        return fail(CS_EINVAL, "scene.dtype = %d is not a CS_DTYPE_*", s->dtype);
     if ((int64_t)s->n * s->k > (1ll << 30)) return fail(CS_EINVAL, "scene too large");
     return CS_OK;
 }
@@ -385,7 +387,7 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
     F.digits = kn.digits;
     launch_zero_ranges(st, F.counters, F.counter_words, reinterpret_cast<uint32_t *>(F.evalcount), 4, nullptr, 0);
     tm.begin();
-    launch_preprocess_fwd(st, n, F.V, F.K, F.deg, sc->points, sc->delta, sc->sigma, sc->opacity, sc->sh, F.d_frame,
+    launch_preprocess_fwd(st, n, F.V, F.K, F.deg, sc->dtype, sc->points, sc->delta, sc->sigma, sc->opacity, sc->sh, F.d_frame,
                           ra, F.records, F.keys, F.ids, F.bins, F.hullpk, nullptr);
     tm.end(CS_STAGE_PREPROCESS);
 
@@ -496,7 +498,7 @@ int enqueue_backward(Frame &F, const cs_scene *sc, const cs_grads *g, const Rend
                       F.records, ra, F.pixstate, F.acc);
     tm.end(CS_STAGE_RENDER_BWD);
     tm.begin();
-    launch_preprocess_bwd(st, sc->n, F.V, F.K, F.deg, sc->points, sc->delta, sc->sigma, sc->sh, F.d_frame, F.records,
+    launch_preprocess_bwd(st, sc->n, F.V, F.K, F.deg, sc->dtype, sc->points, sc->delta, sc->sigma, sc->sh, F.d_frame, F.records,
                           F.hullpk, F.acc, g->points, g->delta, g->sigma, g->opacity, g->sh);
     tm.end(CS_STAGE_PREPROCESS_BWD);
     hipError_t e = hipGetLastError();
@@ -538,7 +540,7 @@ uint64_t mix(uint64_t h, uint64_t v) { return (h ^ (v + 0x9e3779b97f4a7c15ull + 
 uint64_t scene_key(const cs_scene *sc, int V, const Knobs &kn, const RenderArgs &ra)
 {
     uint64_t h = 1469598103934665603ull;
-    for (uint64_t v : {(uint64_t)sc->n, (uint64_t)sc->k, (uint64_t)sc->sh_degree, (uint64_t)V,
+    for (uint64_t v : {(uint64_t)sc->n, (uint64_t)sc->k, (uint64_t)sc->sh_degree, (uint64_t)sc->dtype, (uint64_t)V,
                        (uint64_t)(uintptr_t)sc->points, (uint64_t)(uintptr_t)sc->delta, (uint64_t)(uintptr_t)sc->sigma,
                        (uint64_t)(uintptr_t)sc->opacity, (uint64_t)(uintptr_t)sc->sh, (uint64_t)kn.tile,
                        (uint64_t)kn.longest, (uint64_t)kn.digits})
@@ -618,7 +620,7 @@ int check_grads(const cs_scene *sc, const cs_grads *g)
 
 extern "C" {
 
-int cs_version(void) { return 200; }
+int cs_version(void) { return 300; }
 
 const char *cs_last_error(void) { return g_err.c_str(); }
 
@@ -1047,7 +1049,7 @@ int cs_debug_preprocess(cs_ctx *ctx, const cs_scene *sc, const cs_camera *cam, c
     CS_TRY(F.upload_views(vp.hdr, vp.views.data()));
     DebugConvex *dbg = nullptr;
     CS_TRY(F.alloc((void **)&dbg, sizeof(DebugConvex) * (size_t)sc->n));
-    launch_preprocess_fwd(st, sc->n, 1, sc->k, sc->sh_degree, sc->points, sc->delta, sc->sigma, sc->opacity, sc->sh,
+    launch_preprocess_fwd(st, sc->n, 1, sc->k, sc->sh_degree, sc->dtype, sc->points, sc->delta, sc->sigma, sc->opacity, sc->sh,
                           F.d_frame, ra, F.records, F.keys, F.ids, F.bins, F.hullpk, dbg);
     CS_HIP(hipGetLastError());
     CS_HIP(hipMemcpyAsync(out, dbg, sizeof(DebugConvex) * (size_t)sc->n, hipMemcpyDeviceToHost, st));

@@ -17,6 +17,9 @@ Scene arrays are float32:
     sigma   [N]         sharpness   (> 0, activated)
     opacity [N]         in [0, 1]   (activated)
     sh      [N][(D+1)^2][3]
+The light model (paper Sec. 4.2) stores the same parameters in 16-bit
+precision; ``Scene.stored`` gives the float32 values such a scene holds
+(round to nearest even), which the oracle and a float32 render read.
 Camera: pinhole, world->camera rotation R (rows = camera x right, y down,
 z forward) and translation t, focal lengths and principal point in pixels.
 """
@@ -55,6 +58,27 @@ class Scene:
     def subset(self, idx) -> "Scene":
         return Scene(*(np.ascontiguousarray(a[idx]) for a in
                        (self.points, self.delta, self.sigma, self.opacity, self.sh)))
+
+    def stored(self, fmt: str) -> "Scene":
+        """The scene as a 16-bit storage format holds it ('f16' or 'bf16'),
+        as float32 arrays; 'f32' returns the scene itself."""
+        if fmt == "f32":
+            return self
+        return Scene(*(round_to(a, fmt) for a in (self.points, self.delta, self.sigma, self.opacity, self.sh)))
+
+
+def round_to(a, fmt: str) -> np.ndarray:
+    """float32 values of `a` rounded to nearest, ties to even, in a 16-bit
+    storage format: 'f16' (IEEE binary16) or 'bf16' (bfloat16, the upper half
+    of a binary32).  Finite inputs within the format's range."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if fmt == "f16":
+        return a.astype(np.float16).astype(np.float32)
+    if fmt == "bf16":
+        u = a.view(np.uint32).astype(np.uint64)
+        r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+        return r.astype(np.uint32).view(np.float32)
+    raise ValueError(f"unknown storage format {fmt!r}")
 
 
 @dataclass

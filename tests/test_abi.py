@@ -76,3 +76,44 @@ def test_create_without_device_reports_enodev():
     rc = L.cs_create(0, 0, C.byref(h))
     assert rc == binding.CS_ENODEV
     assert not h.value
+
+
+def test_bad_scene_dtype_is_rejected():
+    L = binding.lib()
+    cam = binding.Camera()
+    cam.width, cam.height, cam.fx, cam.fy, cam.znear = 64, 64, 50.0, 50.0, 0.1
+    dummy = (C.c_char * 64)()
+    bad = binding.SceneS(10, 6, 3, 1, 1, 1, 1, 1, 3)
+    assert L.cs_render_forward(dummy, C.byref(bad), C.byref(cam), None, 1, None, None) == binding.CS_EINVAL
+    assert b"dtype" in L.cs_last_error()
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structs have the C compiler's sizes and offsets
+    for the header's structs (a C probe compiled with gcc prints them)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"cs_scene": binding.SceneS, "cs_camera": binding.Camera, "cs_grads": binding.GradsS,
+               "cs_params": binding.Params, "cs_serve_config": binding.ServeConfig,
+               "cs_serve_stats": binding.ServeStats, "cs_tuning": binding.Tuning,
+               "cs_debug_convex": binding.DebugConvex}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "convexsplat.h"', "int main(void) {"]
+    for name, S in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in S._fields_:
+            lines.append(f'printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        name, field, v = ln.split()
+        got[(name, field)] = int(v)
+    for name, S in structs.items():
+        assert got[(name, "size")] == C.sizeof(S), name
+        for f, _ in S._fields_:
+            assert got[(name, f)] == getattr(S, f).offset, (name, f)

@@ -50,3 +50,25 @@ def test_mixture_and_serving_shapes():
     assert 60 < len(reqs) < 140
     assert all(0 <= sid < 4 for _, sid, _ in reqs)
     assert all(r[0] < 1.0 for r in reqs) and all(reqs[i][0] < reqs[i + 1][0] for i in range(len(reqs) - 1))
+
+
+def test_16bit_storage_rounding_matches_torch():
+    """round_to is IEEE round-to-nearest-even into binary16 / bfloat16, bit for
+    bit as torch converts (ties and signed zeros included)."""
+    import torch
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.normal(0, 3, 50000), rng.uniform(-60, 60, 50000),
+                        [1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -9, -1 - 2 ** -8, 1 + 2 ** -11, 1 + 3 * 2 ** -11,
+                         0.0, -0.0, 50.0, 1e-30]]).astype(np.float32)
+    for fmt, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
+        a = scenes.round_to(x, fmt)
+        b = torch.from_numpy(x).to(dt).float().numpy()
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), fmt
+    # representable values are kept; a tie goes to the even neighbour
+    assert scenes.round_to(np.float32(1 + 2 ** -7), "bf16") == np.float32(1 + 2 ** -7)
+    assert scenes.round_to(np.float32(1 + 2 ** -8), "bf16") == np.float32(1.0)
+    assert scenes.round_to(np.float32(1 + 3 * 2 ** -8), "bf16") == np.float32(1 + 2 ** -6)
+    s, _ = scenes.config1()
+    assert s.stored("f32") is s
+    h = s.stored("f16")
+    assert np.array_equal(h.points, s.points.astype(np.float16).astype(np.float32))
