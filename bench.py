@@ -235,6 +235,38 @@ def bench_light(scene, cam, target, steps, warmup, ms_f32):
             "stages_ms": {k: round(t / c, 4) for k, (t, c) in tm.items() if c and k.startswith("preprocess")}}
 
 
+def bench_densify(scene, steps):
+    """One split / prune step (paper Sec. 3.3) over the workload's scene: 5 % of
+    the convexes split, those below opacity 0.03 pruned (about 2.5 % of this
+    scene), the size limit at the radius distribution's upper tail."""
+    import torch
+
+    from paper_2411_14974_amd.binding import DeviceScene, Renderer, make_densify_params
+    dev = torch.device("cuda:0")
+    R = Renderer(0)
+    ds = DeviceScene.from_scene(scene, dev)
+    rng = np.random.default_rng(77)
+    n = scene.n
+    denom = torch.from_numpy(rng.integers(1, 4, n).astype(np.float32)).to(dev)
+    mean = np.where(rng.random(n) < 0.05, 1e-5, 1e-6).astype(np.float32)
+    accum = denom * torch.from_numpy(mean).to(dev)
+    p = make_densify_params(size_max=0.2)
+    cap = 2 * n
+    out, src = R.densify(ds, accum, denom, p, capacity=cap)  # warm-up, sizes the outputs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out, src = R.densify(ds, accum, denom, p, capacity=cap)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    row = 4 * (3 * scene.k + 3 + 3 * (scene.deg + 1) ** 2)
+    moved = n * (2 * row + 8) + out.n * (row + 4)  # read (classify + scatter) + statistic; write outputs
+    R.close()
+    return {"workload": f"split/prune of the {n}-convex scene", "convexes_out": out.n, "ms": ms,
+            "gb_per_s": moved / (ms / 1e3) / 1e9,
+            "note": "host-timed call, including the 8-byte count read-back and the binding's output allocation"}
+
+
 def counter_traffic(stage, workload):
     """HBM bytes per launch of a stage's kernel from the committed rocprofv3
     counters (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by what the same
@@ -295,8 +327,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=163840)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
-    ap.add_argument("--forms", default="plain,light,batched,serving",
-                    help="comma list of plain, light (16-bit scene), batched, serving")
+    ap.add_argument("--forms", default="plain,light,densify,batched,serving",
+                    help="comma list of plain, light (16-bit scene), densify, batched, serving")
     ap.add_argument("--serve-rates", default="50,200,800", help="request rates (req/s) of the serving sweep")
     ap.add_argument("--serve-seconds", type=float, default=1.5)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -404,6 +436,8 @@ def main():
     forms = set(args.forms.split(","))
     if "light" in forms:
         line["light_16bit"] = bench_light(scene, cam, target, args.steps, args.warmup, ms)
+    if "densify" in forms:
+        line["densify"] = bench_densify(scene, args.steps)
     if "batched" in forms:
         line["batched"] = bench_batched(max(3, args.steps // 4), 2)
     if "serving" in forms:

@@ -288,6 +288,53 @@ int cs_timing_read(cs_ctx *ctx, double *ms, int64_t *count, int reset);
 int cs_l1_loss_grad(cs_ctx *ctx, const float *rgb, const float *target, int32_t width, int32_t height,
                     float *dl_drgb, float *loss, void *hip_stream);
 
+/* ------------------------------------------------ adaptive density control --
+ * Splitting and pruning of the convex set between optimisation steps (paper
+ * Sec. 3.3, "Adaptive convex shape refinement"; Supp. Initialization &
+ * Hyperparameters).  The paper splits a convex whose sharpness-gradient
+ * statistic ("loss of sigma") passes a threshold into K children, one centred
+ * at each of its points, scaled down, with sigma raised and opacity lowered
+ * (delta kept), and prunes convexes that are nearly transparent or too large.
+ * Values marked "not stated" are not given by the paper: the caller chooses. */
+typedef struct {
+    float opacity_min;         /* prune when opacity < opacity_min (paper: 0.03) */
+    float size_max;            /* prune when the radius max_k |p_k - c| > size_max, c the point mean
+                                  (paper: 0.3 x the scene size) */
+    float split_threshold;     /* split when accum / denom > split_threshold (denom > 0; paper: 4e-6) */
+    float child_scale;         /* child k: points p_k + child_scale (p_j - c) (paper: 0.7 indoor, 0.6 outdoor) */
+    float child_sigma_scale;   /* child sigma = sigma x this (paper: higher; factor not stated) */
+    float child_opacity_scale; /* child opacity = opacity x this (paper: lower; factor not stated) */
+} cs_densify_params;
+
+/* Output arrays of cs_densify (DEVICE, float32, `capacity` convexes each, the
+ * scene's shapes) and src[capacity] (int32): the input convex each output
+ * convex comes from. */
+typedef struct {
+    float *points, *delta, *sigma, *opacity, *sh;
+    int32_t *src;
+} cs_scene_out;
+
+/* After a backward pass: for every convex that reached at least one tile in
+ * some view of `state`, accum[i] += |g_sigma[i]| and denom[i] += the number of
+ * such views (DEVICE float arrays [n], caller-owned; the sharpness-gradient
+ * statistic of the split criterion).  g_sigma: the gradient the caller's
+ * optimiser sees for sigma (e.g. cs_grads.sigma, or its chain to a raw
+ * parameter). */
+int cs_densify_accumulate(cs_ctx *ctx, const cs_fwd_state *state, const float *g_sigma, float *accum, float *denom,
+                          void *hip_stream);
+
+/* Split and prune a float32 scene into `out`.  Decisions (in float32, in a
+ * fixed order): prune if opacity < opacity_min or radius^2 > size_max^2;
+ * else split if denom > 0 and accum / denom > split_threshold; else keep.
+ * Output order: kept convexes in input order, then the K children of each
+ * split convex in input order, child k centred at point k.  *n_out (host) is
+ * the output count; when it exceeds `capacity` nothing is written and
+ * CS_EOVERFLOW is returned (call again with capacity >= *n_out).  Synchronises
+ * the stream once (the 8-byte count read-back).  CS_EINVAL for a 16-bit scene. */
+int cs_densify(cs_ctx *ctx, const cs_scene *scene, const float *accum, const float *denom,
+               const cs_densify_params *params, int64_t capacity, const cs_scene_out *out, int64_t *n_out,
+               void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

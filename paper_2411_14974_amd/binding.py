@@ -24,7 +24,7 @@ EXPORTED = (
     "cs_state_release", "cs_state_stats", "cs_debug_preprocess", "cs_debug_tile_lists", "cs_l1_loss_grad",
     "cs_timing_read", "cs_render_forward_batch", "cs_render_backward_batch", "cs_batch_check", "cs_autotune",
     "cs_serve_start", "cs_serve_resume", "cs_serve_stop", "cs_scene_register", "cs_scene_unregister",
-    "cs_serve_submit", "cs_serve_wait", "cs_serve_get_stats",
+    "cs_serve_submit", "cs_serve_wait", "cs_serve_get_stats", "cs_densify_accumulate", "cs_densify",
 )
 # storage formats of the scene arrays (cs_scene.dtype)
 DTYPE_F32, DTYPE_F16, DTYPE_BF16 = 0, 1, 2
@@ -70,6 +70,27 @@ class GradsS(C.Structure):
 class Params(C.Structure):
     _fields_ = [("eps_alpha", C.c_float), ("t_min", C.c_float), ("background", C.c_float * 3),
                 ("tile", C.c_int32), ("flags", C.c_int32)]
+
+
+class DensifyParams(C.Structure):
+    _fields_ = [("opacity_min", C.c_float), ("size_max", C.c_float), ("split_threshold", C.c_float),
+                ("child_scale", C.c_float), ("child_sigma_scale", C.c_float), ("child_opacity_scale", C.c_float)]
+
+
+class SceneOut(C.Structure):
+    _fields_ = [("points", C.c_void_p), ("delta", C.c_void_p), ("sigma", C.c_void_p), ("opacity", C.c_void_p),
+                ("sh", C.c_void_p), ("src", C.c_void_p)]
+
+
+def make_densify_params(opacity_min=0.03, size_max=0.3 * 4.0, split_threshold=4e-6, child_scale=0.7,
+                        child_sigma_scale=1.5, child_opacity_scale=0.5) -> DensifyParams:
+    """Defaults: opacity_min, split_threshold and child_scale (indoor) are the
+    paper's (Supp. Initialization & Hyperparameters); size_max is 0.3 x a scene
+    size of 4 (the orbit radius of the synthetic cameras); the paper states no
+    factors for the children's sigma and opacity: 1.5 and 0.5 are this
+    binding's choice."""
+    return DensifyParams(opacity_min, size_max, split_threshold, child_scale, child_sigma_scale,
+                         child_opacity_scale)
 
 
 class ServeConfig(C.Structure):
@@ -130,6 +151,8 @@ def lib():
         L.cs_serve_submit.argtypes = [vp, i32, vp, vp, C.POINTER(C.c_uint64)]
         L.cs_serve_wait.argtypes = [vp, C.c_uint64, C.POINTER(C.c_double)]
         L.cs_serve_get_stats.argtypes = [vp, vp]
+        L.cs_densify_accumulate.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.cs_densify.argtypes = [vp, vp, vp, vp, vp, i64, vp, C.POINTER(i64), vp]
         _lib = L
     return _lib
 
@@ -400,6 +423,37 @@ class Renderer:
         cnt = (C.c_int64 * len(STAGES))()
         _check(lib().cs_timing_read(self.ctx, ms, cnt, int(reset)))
         return {s: (ms[i], cnt[i]) for i, s in enumerate(STAGES)}
+
+    def densify_accumulate(self, state: "FwdState", g_sigma: torch.Tensor, accum: torch.Tensor, denom: torch.Tensor):
+        """accum += |g_sigma| and denom += views, for the convexes the state's views reached."""
+        _check(lib().cs_densify_accumulate(self.ctx, state.handle, g_sigma.data_ptr(), accum.data_ptr(),
+                                           denom.data_ptr(), _stream_handle(accum.device)))
+
+    def densify(self, scene: DeviceScene, accum: torch.Tensor, denom: torch.Tensor, params: DensifyParams = None,
+                capacity: int = None):
+        """Split and prune a float32 scene: returns (new DeviceScene, src index of each new convex)."""
+        params = params or make_densify_params()
+        dev = scene.points.device
+        n, k, nc = scene.n, scene.k, scene.sh.shape[1]
+        cap = n * k if capacity is None else capacity
+        f32 = dict(device=dev, dtype=torch.float32)
+        for _ in range(2):
+            out = {"points": torch.empty((cap, k, 3), **f32), "delta": torch.empty(cap, **f32),
+                   "sigma": torch.empty(cap, **f32), "opacity": torch.empty(cap, **f32),
+                   "sh": torch.empty((cap, nc, 3), **f32), "src": torch.empty(cap, device=dev, dtype=torch.int32)}
+            so = SceneOut(*(out[f].data_ptr() for f in ("points", "delta", "sigma", "opacity", "sh", "src")))
+            n_out = C.c_int64()
+            rc = lib().cs_densify(self.ctx, C.byref(scene.struct()), accum.data_ptr(), denom.data_ptr(),
+                                  C.byref(params), cap, C.byref(so), C.byref(n_out), _stream_handle(dev))
+            if rc == CS_EOVERFLOW:
+                cap = n_out.value
+                continue
+            _check(rc)
+            m = n_out.value
+            ns = DeviceScene(out["points"][:m], out["delta"][:m], out["sigma"][:m], out["opacity"][:m],
+                             out["sh"][:m], device=dev)
+            return ns, out["src"][:m]
+        raise CSError(CS_EOVERFLOW, "densify output did not fit after growing")
 
     def l1_loss_grad(self, rgb: torch.Tensor, target: torch.Tensor, grad=None, loss=None):
         H, W = rgb.shape[:2]

@@ -226,6 +226,21 @@ int Frame::upload_views(const FrameHeader &hdr, const ViewDesc *views)
     return CS_OK;
 }
 
+int check_scene(const cs_scene *s)
+{
+    if (!s) return fail(CS_EINVAL, "scene is NULL");
+    if (s->n < 0) return fail(CS_EINVAL, "scene.n = %d < 0", s->n);
+    if (s->k < 3 || s->k > CS_MAX_K) return fail(CS_EINVAL, "scene.k = %d outside [3, %d]", s->k, CS_MAX_K);
+    if (s->sh_degree < 0 || s->sh_degree > CS_MAX_SH_DEGREE)
+        return fail(CS_EINVAL, "scene.sh_degree = %d outside [0, 3]", s->sh_degree);
+    if (s->n > 0 && (!s->points || !s->delta || !s->sigma || !s->opacity || !s->sh))
+        return fail(CS_EINVAL, "scene array pointer is NULL");
+    if (s->dtype != CS_DTYPE_F32 && s->dtype != CS_DTYPE_F16 && s->dtype != CS_DTYPE_BF16)
+        return fail(CS_EINVAL, "scene.dtype = %d is not a CS_DTYPE_*", s->dtype);
+    if ((int64_t)s->n * s->k > (1ll << 30)) return fail(CS_EINVAL, "scene too large");
+    return CS_OK;
+}
+
 } // namespace cs
 
 // ------------------------------------------------------------- context -----
@@ -266,20 +281,6 @@ struct StageTimer {
     }
 };
 
-int check_scene(const cs_scene *s)
-{
-    if (!s) return fail(CS_EINVAL, "scene is NULL");
-    if (s->n < 0) return fail(CS_EINVAL, "scene.n = %d < 0", s->n);
-    if (s->k < 3 || s->k > CS_MAX_K) return fail(CS_EINVAL, "scene.k = %d outside [3, %d]", s->k, CS_MAX_K);
-    if (s->sh_degree < 0 || s->sh_degree > CS_MAX_SH_DEGREE)
-        return fail(CS_EINVAL, "scene.sh_degree = %d outside [0, 3]", s->sh_degree);
-    if (s->n > 0 && (!s->points || !s->delta || !s->sigma || !s->opacity || !s->sh))
-        return fail(CS_EINVAL, "scene array pointer is NULL");
-    if (s->dtype != CS_DTYPE_F32 && s->dtype != CS_DTYPE_F16 && s->dtype != CS_DTYPE_BF16)
-        return fail(CS_EINVAL, "scene.dtype = %d is not a CS_DTYPE_*", s->dtype);
-    if ((int64_t)s->n * s->k > (1ll << 30)) return fail(CS_EINVAL, "scene too large");
-    return CS_OK;
-}
 
 int check_camera(const cs_camera *c)
 {

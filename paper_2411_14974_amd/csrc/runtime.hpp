@@ -11,6 +11,8 @@
 namespace cs {
 
 int fail(int code, const char *fmt, ...);
+// CS_OK, or CS_EINVAL (with the message set) for a malformed scene description
+int check_scene(const cs_scene *s);
 
 // Pinned staging buffers for view-table uploads, shared by the frames of one
 // context; a slot is reused only after its previous copy has completed.
