@@ -235,6 +235,58 @@ def bench_light(scene, cam, target, steps, warmup, ms_f32):
             "stages_ms": {k: round(t / c, 4) for k, (t, c) in tm.items() if c and k.startswith("preprocess")}}
 
 
+def bench_train(scene, cam, target, steps, warmup):
+    """A full training step of the paper's optimisation (Sec. 3.3): render,
+    (1 - 0.2) L1 + 0.2 D-SSIM loss and its gradient, backward, fused Adam on
+    the raw parameters writing the next step's activated scene."""
+    import torch
+
+    from paper_2411_14974_amd.binding import PARAM_NAMES, DeviceScene, Renderer, make_adam_params, make_params
+    dev = torch.device("cuda:0")
+    R = Renderer(0)
+    act = DeviceScene.from_scene(scene, dev)
+    raw = {"points": act.points.clone(), "delta": torch.log(act.delta), "sigma": torch.log(act.sigma),
+           "opacity": torch.logit(act.opacity), "sh": act.sh.clone()}
+    actd = {k: getattr(act, k) for k in PARAM_NAMES}
+    m = {k: torch.zeros_like(v) for k, v in raw.items()}
+    v2 = {k: torch.zeros_like(v) for k, v in raw.items()}
+    grads = {k: torch.empty_like(v) for k, v in raw.items()}
+    tgt = torch.from_numpy(target).to(dev)
+    H, W = tgt.shape[:2]
+    rgb = torch.empty((H, W, 3), device=dev)
+    dl = torch.empty_like(rgb)
+    loss = torch.zeros(1, device=dev)
+    params = make_params()
+
+    def step(t):
+        out, st = R.forward(act, cam, params, want_state=True, out=rgb)
+        R.ssim_loss_grad(out, tgt, 0.2, grad=dl, loss=loss)
+        R.backward(st, dl, grads=grads)
+        R.adam_step(grads, raw, m, v2, actd, make_adam_params(t))
+        return st
+
+    held, t = [], 1
+    for _ in range(max(warmup, 3)):
+        held.append(step(t))
+        t += 1
+        if len(held) > 2:
+            held.pop(0).release()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        held.append(step(t))
+        t += 1
+        if len(held) > 2:
+            held.pop(0).release()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    for s_ in held:
+        s_.release()
+    R.close()
+    return {"step": "render + L1/D-SSIM loss + backward + Adam (raw parameters, activations fused)",
+            "ms_per_step": ms, "mpixels_per_s": W * H / (ms / 1e3) / 1e6}
+
+
 def bench_densify(scene, steps):
     """One split / prune step (paper Sec. 3.3) over the workload's scene: 5 % of
     the convexes split, those below opacity 0.03 pruned (about 2.5 % of this
@@ -327,8 +379,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=163840)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
-    ap.add_argument("--forms", default="plain,light,densify,batched,serving",
-                    help="comma list of plain, light (16-bit scene), densify, batched, serving")
+    ap.add_argument("--forms", default="plain,light,train,densify,batched,serving",
+                    help="comma list of plain, light (16-bit scene), train, densify, batched, serving")
     ap.add_argument("--serve-rates", default="50,200,800", help="request rates (req/s) of the serving sweep")
     ap.add_argument("--serve-seconds", type=float, default=1.5)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -436,6 +488,8 @@ def main():
     forms = set(args.forms.split(","))
     if "light" in forms:
         line["light_16bit"] = bench_light(scene, cam, target, args.steps, args.warmup, ms)
+    if "train" in forms:
+        line["train_step"] = bench_train(scene, cam, target, args.steps, args.warmup)
     if "densify" in forms:
         line["densify"] = bench_densify(scene, args.steps)
     if "batched" in forms:

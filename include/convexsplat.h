@@ -335,6 +335,46 @@ int cs_densify(cs_ctx *ctx, const cs_scene *scene, const float *accum, const flo
                const cs_densify_params *params, int64_t capacity, const cs_scene_out *out, int64_t *n_out,
                void *hip_stream);
 
+/* Photometric loss of a training step (paper Sec. 3.3, Eq. loss, with
+ * lambda = 0.2 there): L = (1 - lambda) mean|rgb - target| + lambda (1 - SSIM),
+ * SSIM the mean over pixels and channels of the SSIM map with an 11x11
+ * Gaussian window (sigma 1.5), zero padding, C1 = 0.01^2, C2 = 0.03^2 (the
+ * 3DGS convention the paper follows).  Writes dl_drgb = dL/drgb ([h][w][3],
+ * DEVICE) and ADDS L to *loss (DEVICE, one float; the caller zeroes it).  The
+ * mask term of the equation belongs to a learnable-mask extension that this
+ * rasterizer does not have.  Uses 36 bytes per pixel of stream-ordered scratch. */
+int cs_ssim_loss_grad(cs_ctx *ctx, const float *rgb, const float *target, int32_t width, int32_t height, float lambda,
+                      float *dl_drgb, float *loss, void *hip_stream);
+
+/* ---------------------------------------------------------- optimiser step --
+ * Adam on the raw (optimised) parameters (paper Sec. 3.3 "Initialization and
+ * losses": opacity through a sigmoid, delta and sigma through an exponential;
+ * the position learning rate decays exponentially, which the caller applies
+ * through lr_points per step; Supp. Initialization & Hyperparameters gives the
+ * rates).  grad holds dL/d(activated value), as cs_render_backward writes it;
+ * the kernel chains it through the activation at the current raw value,
+ * updates raw, m and v in place (torch.optim.Adam's arithmetic: m moves
+ * towards g by 1 - beta1, v = beta2 v + (1 - beta2) g^2, step lr / (1 -
+ * beta1^t), denominator sqrt(v) / sqrt(1 - beta2^t) + eps) and, when
+ * `activated` is non-NULL, writes the activated values of the new raw
+ * parameters (the scene arrays of the next render).  All arrays DEVICE
+ * float32 with the scene's shapes; SH coefficient 0 of each channel takes
+ * lr_sh_dc, the others lr_sh_rest. */
+typedef struct {
+    float *points, *delta, *sigma, *opacity, *sh;
+} cs_param_set;
+
+typedef struct {
+    float lr_points, lr_delta, lr_sigma, lr_opacity, lr_sh_dc, lr_sh_rest;
+    double beta1, beta2; /* double: 1 - beta is formed before rounding to float32 */
+    float eps;
+    int32_t step; /* 1-based step count of the bias corrections */
+} cs_adam_params;
+
+int cs_adam_step(cs_ctx *ctx, int32_t n, int32_t k, int32_t sh_degree, const cs_grads *grad, const cs_param_set *raw,
+                 const cs_param_set *m, const cs_param_set *v, const cs_param_set *activated,
+                 const cs_adam_params *params, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

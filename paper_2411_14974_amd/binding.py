@@ -7,6 +7,7 @@ fails loudly when the library is missing; there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -25,6 +26,7 @@ EXPORTED = (
     "cs_timing_read", "cs_render_forward_batch", "cs_render_backward_batch", "cs_batch_check", "cs_autotune",
     "cs_serve_start", "cs_serve_resume", "cs_serve_stop", "cs_scene_register", "cs_scene_unregister",
     "cs_serve_submit", "cs_serve_wait", "cs_serve_get_stats", "cs_densify_accumulate", "cs_densify",
+    "cs_adam_step", "cs_ssim_loss_grad",
 )
 # storage formats of the scene arrays (cs_scene.dtype)
 DTYPE_F32, DTYPE_F16, DTYPE_BF16 = 0, 1, 2
@@ -93,6 +95,41 @@ def make_densify_params(opacity_min=0.03, size_max=0.3 * 4.0, split_threshold=4e
                          child_opacity_scale)
 
 
+class ParamSet(C.Structure):
+    _fields_ = [("points", C.c_void_p), ("delta", C.c_void_p), ("sigma", C.c_void_p), ("opacity", C.c_void_p),
+                ("sh", C.c_void_p)]
+
+
+class AdamParams(C.Structure):
+    _fields_ = [("lr_points", C.c_float), ("lr_delta", C.c_float), ("lr_sigma", C.c_float),
+                ("lr_opacity", C.c_float), ("lr_sh_dc", C.c_float), ("lr_sh_rest", C.c_float),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_float), ("step", C.c_int32)]
+
+
+def expon_lr(step, lr_init=5e-4, lr_final=5e-6, max_steps=30_000):
+    """Exponential decay from lr_init at step 0 to lr_final at max_steps (then
+    constant): the position learning rate of the paper's Sec. 3.3 / Supp.
+    (5e-4 to 5e-6; the step count of the decay is not stated, 30 000 here)."""
+    t = min(max(step / max_steps, 0.0), 1.0)
+    return math.exp((1.0 - t) * math.log(lr_init) + t * math.log(lr_final))
+
+
+def make_adam_params(step, lr_points=None, lr_delta=0.005, lr_sigma=0.0045, lr_opacity=0.05, lr_sh_dc=0.0025,
+                     lr_sh_rest=0.0025 / 20, beta1=0.9, beta2=0.999, eps=1e-15) -> AdamParams:
+    """Rates of the paper's Supp. (positions by expon_lr, delta 0.005, sigma
+    0.0045); opacity, SH and eps, which it does not state, follow the 3DGS
+    settings it builds on."""
+    return AdamParams(expon_lr(step) if lr_points is None else lr_points, lr_delta, lr_sigma, lr_opacity, lr_sh_dc,
+                      lr_sh_rest, beta1, beta2, eps, step)
+
+
+PARAM_NAMES = ("points", "delta", "sigma", "opacity", "sh")
+
+
+def _param_set(d):
+    return ParamSet(*(d[k].data_ptr() for k in PARAM_NAMES)) if d is not None else None
+
+
 class ServeConfig(C.Structure):
     _fields_ = [("workers", C.c_int32), ("max_batch", C.c_int32), ("max_queue", C.c_int32),
                 ("start_paused", C.c_int32), ("hbm_budget_bytes", C.c_size_t), ("params", Params)]
@@ -153,6 +190,8 @@ def lib():
         L.cs_serve_get_stats.argtypes = [vp, vp]
         L.cs_densify_accumulate.argtypes = [vp, vp, vp, vp, vp, vp]
         L.cs_densify.argtypes = [vp, vp, vp, vp, vp, i64, vp, C.POINTER(i64), vp]
+        L.cs_adam_step.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.cs_ssim_loss_grad.argtypes = [vp, vp, vp, i32, i32, C.c_float, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -454,6 +493,30 @@ class Renderer:
                              out["sh"][:m], device=dev)
             return ns, out["src"][:m]
         raise CSError(CS_EOVERFLOW, "densify output did not fit after growing")
+
+    def adam_step(self, grads, raw, m, v, activated=None, params: AdamParams = None, step: int = 1):
+        """One fused Adam step on the raw parameters (dicts of float32 device
+        tensors keyed by PARAM_NAMES); grads are dL/d(activated), as the
+        backward pass writes them.  Writes the new activated values into
+        `activated` when given."""
+        params = params or make_adam_params(step)
+        p = raw["points"]
+        n, k = p.shape[0], p.shape[1]
+        deg = int(round(raw["sh"].shape[1] ** 0.5)) - 1
+        g = GradsS(*(grads[k_].data_ptr() for k_ in PARAM_NAMES))
+        act = _param_set(activated)
+        _check(lib().cs_adam_step(self.ctx, n, k, deg, C.byref(g), C.byref(_param_set(raw)), C.byref(_param_set(m)),
+                                  C.byref(_param_set(v)), C.byref(act) if act is not None else None,
+                                  C.byref(params), _stream_handle(p.device)))
+
+    def ssim_loss_grad(self, rgb: torch.Tensor, target: torch.Tensor, lam: float = 0.2, grad=None, loss=None):
+        """(1 - lam) L1 + lam (1 - SSIM): returns (dL/drgb, loss tensor of one float)."""
+        H, W = rgb.shape[:2]
+        grad = torch.empty_like(rgb) if grad is None else grad
+        loss = torch.zeros(1, device=rgb.device) if loss is None else loss
+        _check(lib().cs_ssim_loss_grad(self.ctx, rgb.data_ptr(), target.data_ptr(), W, H, lam, grad.data_ptr(),
+                                       loss.data_ptr(), _stream_handle(rgb.device)))
+        return grad, loss
 
     def l1_loss_grad(self, rgb: torch.Tensor, target: torch.Tensor, grad=None, loss=None):
         H, W = rgb.shape[:2]
