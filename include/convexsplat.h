@@ -375,6 +375,25 @@ int cs_adam_step(cs_ctx *ctx, int32_t n, int32_t k, int32_t sh_degree, const cs_
                  const cs_param_set *m, const cs_param_set *v, const cs_param_set *activated,
                  const cs_adam_params *params, void *hip_stream);
 
+/* Initial convex set from a point cloud (paper Sec. 3.3 "Initialization and
+ * losses"; Supp. Initialization & Hyperparameters): convex i has its k points
+ * on a sphere round cloud point i, at the Fibonacci-sphere directions
+ * (heights 1 - (2j + 1)/k, azimuths j x the golden angle pi (3 - sqrt 5)),
+ * radius radius_scale x max(mean distance to the 3 nearest other cloud
+ * points, radius_min) (fewer than 3 other points: the mean over those there
+ * are).  delta, sigma, opacity take the given initial (activated) values; SH
+ * coefficient 0 reproduces rgb (nullable: grey 0.5), the others are 0.
+ * xyz, rgb: DEVICE [n][3]; out: DEVICE arrays of the scene's shapes.  The
+ * neighbour search is exact and brute force: O(n^2). */
+typedef struct {
+    float radius_scale; /* paper: 1.2 */
+    float radius_min;   /* floor of the mean distance (coincident cloud points) */
+    float delta0, sigma0, opacity0; /* paper: 0.1, 0.00095, 0.1 */
+} cs_init_params;
+
+int cs_init_from_points(cs_ctx *ctx, int32_t n, const float *xyz, const float *rgb, int32_t k, int32_t sh_degree,
+                        const cs_init_params *params, const cs_param_set *out, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,7 @@ EXPORTED = (
     "cs_timing_read", "cs_render_forward_batch", "cs_render_backward_batch", "cs_batch_check", "cs_autotune",
     "cs_serve_start", "cs_serve_resume", "cs_serve_stop", "cs_scene_register", "cs_scene_unregister",
     "cs_serve_submit", "cs_serve_wait", "cs_serve_get_stats", "cs_densify_accumulate", "cs_densify",
-    "cs_adam_step", "cs_ssim_loss_grad",
+    "cs_adam_step", "cs_ssim_loss_grad", "cs_init_from_points",
 )
 # storage formats of the scene arrays (cs_scene.dtype)
 DTYPE_F32, DTYPE_F16, DTYPE_BF16 = 0, 1, 2
@@ -126,6 +126,17 @@ def make_adam_params(step, lr_points=None, lr_delta=0.005, lr_sigma=0.0045, lr_o
 PARAM_NAMES = ("points", "delta", "sigma", "opacity", "sh")
 
 
+class InitParams(C.Structure):
+    _fields_ = [("radius_scale", C.c_float), ("radius_min", C.c_float), ("delta0", C.c_float),
+                ("sigma0", C.c_float), ("opacity0", C.c_float)]
+
+
+def make_init_params(radius_scale=1.2, radius_min=1e-7, delta0=0.1, sigma0=0.00095, opacity0=0.1) -> InitParams:
+    """The paper's initial values (Supp. Initialization & Hyperparameters);
+    radius_min, the floor for coincident cloud points, is this binding's."""
+    return InitParams(radius_scale, radius_min, delta0, sigma0, opacity0)
+
+
 def _param_set(d):
     return ParamSet(*(d[k].data_ptr() for k in PARAM_NAMES)) if d is not None else None
 
@@ -192,6 +203,7 @@ def lib():
         L.cs_densify.argtypes = [vp, vp, vp, vp, vp, i64, vp, C.POINTER(i64), vp]
         L.cs_adam_step.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.cs_ssim_loss_grad.argtypes = [vp, vp, vp, i32, i32, C.c_float, vp, vp, vp]
+        L.cs_init_from_points.argtypes = [vp, i32, vp, vp, i32, i32, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -517,6 +529,21 @@ class Renderer:
         _check(lib().cs_ssim_loss_grad(self.ctx, rgb.data_ptr(), target.data_ptr(), W, H, lam, grad.data_ptr(),
                                        loss.data_ptr(), _stream_handle(rgb.device)))
         return grad, loss
+
+    def init_from_points(self, xyz: torch.Tensor, rgb: torch.Tensor = None, k: int = 6, sh_degree: int = 3,
+                         params: InitParams = None) -> DeviceScene:
+        """Initial convex set, one convex per cloud point (activated values)."""
+        params = params or make_init_params()
+        xyz = xyz.contiguous().float()
+        n, dev = xyz.shape[0], xyz.device
+        f32 = dict(device=dev, dtype=torch.float32)
+        out = {"points": torch.empty((n, k, 3), **f32), "delta": torch.empty(n, **f32), "sigma": torch.empty(n, **f32),
+               "opacity": torch.empty(n, **f32), "sh": torch.empty((n, (sh_degree + 1) ** 2, 3), **f32)}
+        rgbc = rgb.contiguous().float() if rgb is not None else None
+        _check(lib().cs_init_from_points(self.ctx, n, xyz.data_ptr(), rgbc.data_ptr() if rgbc is not None else None,
+                                         k, sh_degree, C.byref(params), C.byref(_param_set(out)),
+                                         _stream_handle(dev)))
+        return DeviceScene(out["points"], out["delta"], out["sigma"], out["opacity"], out["sh"], device=dev)
 
     def l1_loss_grad(self, rgb: torch.Tensor, target: torch.Tensor, grad=None, loss=None):
         H, W = rgb.shape[:2]

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libconvexsplat.so")
-SOURCES = ["preprocess.hip", "sort.hip", "render.hip", "runtime.hip", "serve.hip", "densify.hip", "train.hip"]
+SOURCES = ["preprocess.hip", "sort.hip", "render.hip", "runtime.hip", "serve.hip", "densify.hip", "train.hip", "init.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
