@@ -61,7 +61,7 @@ __device__ __forceinline__ void pixel_span(double a, double b, int n, int &lo, i
 
 } // namespace
 
-constexpr int PF_BLOCK = 256;
+constexpr int PF_BLOCK = 128;
 
 // DBG: also fill the per-instance debug record (a separate instantiation, so
 // that the debug copies of the lines cost no registers in the plain one).
@@ -73,9 +73,14 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
     uint32_t *__restrict__ ids, uint4 *__restrict__ bins, uint32_t *__restrict__ hullpk,
     DebugConvex *__restrict__ dbg)
 {
-    // the block's points arrive through LDS (coalesced loads; odd row stride)
+    // The block's points arrive through LDS (coalesced loads; odd row stride);
+    // once they are in registers the same LDS holds the block's records, which
+    // leave in coalesced 16-byte stores (one contiguous run per block).
     constexpr int PS = 3 * K + 1;
-    __shared__ float s_pts[PF_BLOCK * PS];
+    constexpr int RC = rec_stride(K) / 16;
+    constexpr int BUF = (PF_BLOCK * RC > (PF_BLOCK * PS + 3) / 4) ? PF_BLOCK * RC : (PF_BLOCK * PS + 3) / 4;
+    __shared__ uint4 s_buf[BUF];
+    float *s_pts = reinterpret_cast<float *>(s_buf);
     const int base = blockIdx.x * PF_BLOCK;
     const int cnt = min(PF_BLOCK, n - base);
     {
@@ -83,12 +88,13 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
         for (int j = threadIdx.x; j < cnt * 3 * K; j += PF_BLOCK) s_pts[(j / (3 * K)) * PS + j % (3 * K)] = ld(g, j);
     }
     __syncthreads();
-    const int i = base + threadIdx.x;
-    if (i >= n) return;
-    // one (view, convex) instance per thread; all outputs are indexed by the instance
+    // one (view, convex) instance per thread; all outputs are indexed by the
+    // instance (threads past n compute on the last convex and store nothing)
+    const bool active = base + (int)threadIdx.x < n;
+    const int i = active ? base + (int)threadIdx.x : n - 1;
     const CamArgs cam = reinterpret_cast<const ViewDesc *>(frame + 1)[blockIdx.y].cam;
     const size_t inst = (size_t)blockIdx.y * n + i;
-    ids[inst] = (uint32_t)inst;
+    if (active) ids[inst] = (uint32_t)inst;
 
     float px[K], py[K], pz[K];
 #pragma unroll
@@ -97,6 +103,7 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
         py[k] = s_pts[threadIdx.x * PS + 3 * k + 1];
         pz[k] = s_pts[threadIdx.x * PS + 3 * k + 2];
     }
+    __syncthreads(); // the LDS now takes the records
     // point centroid (for the SH view direction), taken now so the points can retire early
     double cxw = 0, cyw = 0, czw = 0;
 #pragma unroll
@@ -156,7 +163,7 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
 
         const double ox = rint(sx), oy = rint(sy);
         const double s2 = dp * LOG2E;
-        uint8_t *rec = records + inst * rec_stride(K);
+        uint8_t *rec = reinterpret_cast<uint8_t *>(s_buf) + threadIdx.x * rec_stride(K);
         // the lines leave as aligned pairs of doubles (16-byte stores): line j
         // occupies doubles 3j..3j+2 after the header; an odd line's first value
         // waits in `carry` for the even line's last one
@@ -383,11 +390,21 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
     }
 
     const bool has_tiles = status == ST_VISIBLE && tx0 <= tx1 && ty0 <= ty1;
-    keys[inst] = status == ST_VISIBLE ? key : KEY_CULLED;
-    bins[inst] = has_tiles ? make_bin(tx0, ty0, tx1, ty1, tmask) : make_bin(1, 0, 0, 0, 0);
-    hullpk[inst] = (status == ST_VISIBLE || status == ST_FAINT) ? (packed | ((uint32_t)T << 28)) : 0u;
+    if (active) {
+        keys[inst] = status == ST_VISIBLE ? key : KEY_CULLED;
+        bins[inst] = has_tiles ? make_bin(tx0, ty0, tx1, ty1, tmask) : make_bin(1, 0, 0, 0, 0);
+        hullpk[inst] = (status == ST_VISIBLE || status == ST_FAINT) ? (packed | ((uint32_t)T << 28)) : 0u;
+    }
+    // the block's records (culled convexes' slots hold whatever the LDS held:
+    // nothing reads a culled convex's record)
+    __syncthreads();
+    {
+        uint4 *dst = reinterpret_cast<uint4 *>(records + ((size_t)blockIdx.y * n + base) * rec_stride(K));
+        for (int c = threadIdx.x; c < cnt * RC; c += PF_BLOCK) dst[c] = s_buf[c];
+    }
 
     if constexpr (DBG) {
+        if (!active) return;
         DebugConvex &o = dbg[inst];
         o.status = status;
         o.T = (status == ST_NEAR) ? 0 : T;
