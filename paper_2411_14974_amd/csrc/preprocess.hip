@@ -439,9 +439,9 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
 // accuracy.
 template <int K, typename SP>
 __device__ __forceinline__ void view_backward(int deg, const float *P, float dl, float sg, const SP *f,
-                                              const CamArgs &cam, uint32_t hp, const RecHeader &hdr,
-                                              const float *__restrict__ Ag, float *G, float &gdelta, float &gsigma,
-                                              float &gopac, float *__restrict__ gsh, bool first)
+                                              const CamArgs &cam, uint32_t hp, const float *__restrict__ Ag,
+                                              float *G, float &gdelta, float &gsigma, float &gopac,
+                                              float *__restrict__ gsh, bool first)
 {
     // the instance's accumulator row, in 16-byte loads
     float A[acc_stride(K)];
@@ -532,6 +532,19 @@ __device__ __forceinline__ void view_backward(int deg, const float *P, float dl,
 
     const double r0 = cam.R[0], r1 = cam.R[1], r2 = cam.R[2], r3 = cam.R[3], r4 = cam.R[4], r5 = cam.R[5];
     const double r6 = cam.R[6], r7 = cam.R[7], r8 = cam.R[8];
+    // the lines' origin: the hull's start vertex (first hull index) rounded to
+    // whole pixels, with the forward pass's own projection arithmetic (so the
+    // same integers)
+    double ox, oy;
+    {
+        const int s0 = (int)(hp & 7u);
+        const double x = P[3 * s0], y = P[3 * s0 + 1], z = P[3 * s0 + 2];
+        const double X = r0 * x + r1 * y + r2 * z + (double)cam.t[0];
+        const double Y = r3 * x + r4 * y + r5 * z + (double)cam.t[1];
+        const double Z = r6 * x + r7 * y + r8 * z + (double)cam.t[2];
+        ox = rint((double)cam.fx * X / Z + (double)cam.cx);
+        oy = rint((double)cam.fy * Y / Z + (double)cam.cy);
+    }
     // per point: projected position relative to the origin, 1/Z, X/Z, Y/Z
     float qx[K], qy[K], iz[K], xz[K], yz[K];
     double zs = 0.0;
@@ -542,8 +555,8 @@ __device__ __forceinline__ void view_backward(int deg, const float *P, float dl,
         const double Y = r3 * x + r4 * y + r5 * z + (double)cam.t[1];
         const double Z = r6 * x + r7 * y + r8 * z + (double)cam.t[2];
         const double izd = 1.0 / Z;
-        qx[k] = (float)((double)cam.fx * X * izd + (double)cam.cx - (double)hdr.ox);
-        qy[k] = (float)((double)cam.fy * Y * izd + (double)cam.cy - (double)hdr.oy);
+        qx[k] = (float)((double)cam.fx * X * izd + (double)cam.cx - ox);
+        qy[k] = (float)((double)cam.fy * Y * izd + (double)cam.cy - oy);
         iz[k] = (float)izd;
         xz[k] = (float)(X * izd);
         yz[k] = (float)(Y * izd);
@@ -647,7 +660,7 @@ template <int K, typename P>
 __global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
     int n, int nviews, int deg, const P *__restrict__ points, const P *__restrict__ delta,
     const P *__restrict__ sigma, const P *__restrict__ sh, const FrameHeader *__restrict__ frame,
-    const uint8_t *__restrict__ records, const uint32_t *__restrict__ hullpk, const float *__restrict__ acc,
+    const uint32_t *__restrict__ hullpk, const float *__restrict__ acc,
     float *__restrict__ g_points, float *__restrict__ g_delta, float *__restrict__ g_sigma,
     float *__restrict__ g_opacity, float *__restrict__ g_sh)
 {
@@ -674,8 +687,7 @@ __global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
             const size_t inst = (size_t)v * n + i;
             const uint32_t hp = hullpk[inst];
             if ((int)(hp >> 28) < 3) continue; // dropped in this view: no gradient
-            const RecHeader hdr = *reinterpret_cast<const RecHeader *>(records + inst * rec_stride(K));
-            view_backward<K>(deg, &s_pts[tid * PS], dl, sg, sh + (size_t)i * 3 * nc, views[v].cam, hp, hdr,
+            view_backward<K>(deg, &s_pts[tid * PS], dl, sg, sh + (size_t)i * 3 * nc, views[v].cam, hp,
                              acc + inst * acc_stride(K), &s_gp[tid * PS], gdelta, gsigma, gopac, gsh, first);
             first = false;
         }
@@ -731,14 +743,14 @@ void launch_preprocess_fwd(hipStream_t st, int n, int nviews, int K, int deg, in
 
 void launch_preprocess_bwd(hipStream_t st, int n, int nviews, int K, int deg, int dtype, const void *points,
                            const void *delta, const void *sigma, const void *sh, const FrameHeader *views,
-                           const uint8_t *records, const uint32_t *hullpk, const float *acc, float *g_points, float *g_delta,
+                           const uint32_t *hullpk, const float *acc, float *g_points, float *g_delta,
                            float *g_sigma, float *g_opacity, float *g_sh)
 {
     if (n <= 0) return;
     dim3 grid((n + PB_BLOCK - 1) / PB_BLOCK), block(PB_BLOCK);
     CS_DISPATCH_P(dtype, CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_bwd_kernel<KK, PP>), grid, block, 0, st, n,
                                                          nviews, deg, (const PP *)points, (const PP *)delta,
-                                                         (const PP *)sigma, (const PP *)sh, views, records, hullpk,
+                                                         (const PP *)sigma, (const PP *)sh, views, hullpk,
                                                          acc, g_points, g_delta, g_sigma, g_opacity, g_sh)));
 }
 

@@ -21,7 +21,7 @@ void launch_preprocess_fwd(hipStream_t, int, int, int, int, int, const void *, c
                            const void *, const void *, const FrameHeader *, const RenderArgs &, uint8_t *,
                            uint32_t *, uint32_t *, uint4 *, uint32_t *, DebugConvex *);
 void launch_preprocess_bwd(hipStream_t, int, int, int, int, int, const void *, const void *, const void *,
-                           const void *, const FrameHeader *, const uint8_t *, const uint32_t *, const float *,
+                           const void *, const FrameHeader *, const uint32_t *, const float *,
                            float *, float *, float *, float *, float *);
 void radix_sort(hipStream_t, uint32_t **, uint32_t **, uint32_t **, uint32_t **, uint32_t, const uint32_t *, uint32_t, int,
                 uint32_t *, int, uint32_t *);
@@ -499,7 +499,7 @@ int enqueue_backward(Frame &F, const cs_scene *sc, const cs_grads *g, const Rend
                       F.records, ra, F.pixstate, F.acc);
     tm.end(CS_STAGE_RENDER_BWD);
     tm.begin();
-    launch_preprocess_bwd(st, sc->n, F.V, F.K, F.deg, sc->dtype, sc->points, sc->delta, sc->sigma, sc->sh, F.d_frame, F.records,
+    launch_preprocess_bwd(st, sc->n, F.V, F.K, F.deg, sc->dtype, sc->points, sc->delta, sc->sigma, sc->sh, F.d_frame,
                           F.hullpk, F.acc, g->points, g->delta, g->sigma, g->opacity, g->sh);
     tm.end(CS_STAGE_PREPROCESS_BWD);
     hipError_t e = hipGetLastError();
