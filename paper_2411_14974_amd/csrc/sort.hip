@@ -173,7 +173,7 @@ void launch_gather_scan(hipStream_t st, uint32_t n, const uint32_t *sorted_ids, 
 // Garland's single-pass prefix scan as used by the "Onesweep" radix sort):
 //  1. one kernel reads the keys once and builds the global digit histograms of
 //     every pass;
-//  2. per pass, each workgroup claims the next tile of OS_TILE elements from an
+//  2. per pass, each workgroup claims the next tile of elements from an
 //     atomic counter (tiles are claimed in order by running workgroups), ranks
 //     its elements per digit (wave ballots), publishes its per-digit counts,
 //     then walks back over its predecessors' published counts until it meets an
@@ -185,8 +185,8 @@ void launch_gather_scan(hipStream_t st, uint32_t n, const uint32_t *sorted_ids, 
 
 constexpr int OS_BLOCK = 512;
 constexpr int OS_WAVES = OS_BLOCK / 64;
-constexpr int OS_ITEMS = 16;
-constexpr int OS_TILE = OS_BLOCK * OS_ITEMS;
+constexpr int OS_ITEMS_MIN = 8;                       // keys per thread of the smaller tiles
+constexpr int OS_TILE_MIN = OS_BLOCK * OS_ITEMS_MIN;  // 4096 keys
 constexpr int OS_RADIX = 256; // digits of up to 8 bits
 constexpr int OS_MAX_PASSES = 8;
 constexpr uint32_t OS_AGG = 1u << 30, OS_INC = 2u << 30, OS_VAL = OS_AGG - 1u;
@@ -247,14 +247,15 @@ __device__ __forceinline__ uint32_t os_block_excl(uint32_t x, uint32_t *s_wsum)
 }
 
 // Global histograms of every pass: hist[p * 256 + digit].  A workgroup takes
-// tiles of OS_TILE keys (grid-stride), loads a tile's 16 keys per thread at
+// tiles of OS_BLOCK x ITEMS keys (grid-stride), loads a tile's keys at
 // once and counts them into per-wave LDS histograms (fewer same-address
 // collisions), then adds its nonzero bins to the global histogram.
-template <int BITS>
+template <int BITS, int ITEMS>
 __global__ __launch_bounds__(OS_BLOCK) void os_hist_kernel(const uint32_t *__restrict__ keys,
                                                            const uint32_t *__restrict__ n_dev, uint32_t n_host,
                                                            int end_bit, int P, uint32_t *__restrict__ hist)
 {
+    constexpr int TILE = OS_BLOCK * ITEMS;
     constexpr int R = 1 << BITS; // bins per pass (BITS: the widest pass)
     constexpr int HW = 1024;     // bins per wave: P * R <= 1024 for keys of up to 32 bits
     __shared__ uint32_t h[OS_WAVES][HW];
@@ -262,17 +263,17 @@ __global__ __launch_bounds__(OS_BLOCK) void os_hist_kernel(const uint32_t *__res
     const int wave = threadIdx.x >> 6;
     for (int d = threadIdx.x; d < OS_WAVES * HW; d += OS_BLOCK) (&h[0][0])[d] = 0;
     __syncthreads();
-    const uint32_t ntiles = (n + OS_TILE - 1) / OS_TILE;
+    const uint32_t ntiles = (n + TILE - 1) / TILE;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        uint32_t k[OS_ITEMS];
+        uint32_t k[ITEMS];
 #pragma unroll
-        for (int i = 0; i < OS_ITEMS; ++i) {
-            const size_t idx = (size_t)t * OS_TILE + (size_t)i * OS_BLOCK + threadIdx.x;
+        for (int i = 0; i < ITEMS; ++i) {
+            const size_t idx = (size_t)t * TILE + (size_t)i * OS_BLOCK + threadIdx.x;
             k[i] = idx < n ? keys[idx] : 0u;
         }
 #pragma unroll
-        for (int i = 0; i < OS_ITEMS; ++i)
-            if ((size_t)t * OS_TILE + (size_t)i * OS_BLOCK + threadIdx.x < n)
+        for (int i = 0; i < ITEMS; ++i)
+            if ((size_t)t * TILE + (size_t)i * OS_BLOCK + threadIdx.x < n)
                 for (int p = 0; p < P; ++p)
                     atomicAdd(&h[wave][p * R + ((k[i] >> os_shift(end_bit, P, p)) & ((1u << os_width(end_bit, P, p)) - 1u))],
                               1u);
@@ -286,16 +287,17 @@ __global__ __launch_bounds__(OS_BLOCK) void os_hist_kernel(const uint32_t *__res
     }
 }
 
-template <int BITS>
+template <int BITS, int ITEMS>
 __global__ __launch_bounds__(OS_BLOCK) void os_scatter_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
     uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ n_dev, uint32_t n_host, int shift,
     const uint32_t *__restrict__ hist, uint32_t *__restrict__ tile_counter, uint32_t *__restrict__ status,
     uint32_t *__restrict__ err)
 {
+    constexpr int TILE = OS_BLOCK * ITEMS;
     constexpr int R = 1 << BITS;
-    __shared__ uint32_t s_keys[OS_TILE];
-    __shared__ uint32_t s_vals[OS_TILE];
+    __shared__ uint32_t s_keys[TILE];
+    __shared__ uint32_t s_vals[TILE];
     __shared__ uint32_t s_wcnt[OS_WAVES][R];
     __shared__ uint32_t s_dstart[R];
     __shared__ uint32_t s_gofs[R];
@@ -309,21 +311,21 @@ __global__ __launch_bounds__(OS_BLOCK) void os_scatter_kernel(
     for (int d = tid; d < OS_WAVES * R; d += OS_BLOCK) (&s_wcnt[0][0])[d] = 0;
     __syncthreads();
     const uint32_t t = s_tile;
-    const size_t tbase = (size_t)t * OS_TILE;
+    const size_t tbase = (size_t)t * TILE;
     if (tbase >= n) return; // past the data (capacity-sized grids): nobody waits on this tile
 
     // rank: element order within the tile is (wave, item, lane)
-    uint32_t k[OS_ITEMS], v[OS_ITEMS], off[OS_ITEMS];
-    const size_t wbase = tbase + (size_t)wave * 64 * OS_ITEMS;
+    uint32_t k[ITEMS], v[ITEMS], off[ITEMS];
+    const size_t wbase = tbase + (size_t)wave * 64 * ITEMS;
 #pragma unroll
-    for (int i = 0; i < OS_ITEMS; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         const size_t idx = wbase + i * 64 + lane;
         const bool valid = idx < n;
         k[i] = valid ? keys_in[idx] : 0u;
         v[i] = valid ? vals_in[idx] : 0u;
     }
 #pragma unroll
-    for (int i = 0; i < OS_ITEMS; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         const size_t idx = wbase + i * 64 + lane;
         const bool valid = idx < n;
         const uint32_t dg = (k[i] >> shift) & (R - 1);
@@ -387,7 +389,7 @@ __global__ __launch_bounds__(OS_BLOCK) void os_scatter_kernel(
     __syncthreads();
     // digit-sorted tile in LDS, then each digit's run to its global position
 #pragma unroll
-    for (int i = 0; i < OS_ITEMS; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         const size_t idx = wbase + i * 64 + lane;
         if (idx < n) {
             const uint32_t dg = (k[i] >> shift) & (R - 1);
@@ -397,7 +399,7 @@ __global__ __launch_bounds__(OS_BLOCK) void os_scatter_kernel(
         }
     }
     __syncthreads();
-    const uint32_t nvalid = (uint32_t)min((size_t)OS_TILE, (size_t)n - tbase);
+    const uint32_t nvalid = (uint32_t)min((size_t)TILE, (size_t)n - tbase);
     for (uint32_t j = tid; j < nvalid; j += OS_BLOCK) {
         const uint32_t kk = s_keys[j];
         const uint32_t dg = (kk >> shift) & (R - 1);
@@ -412,23 +414,23 @@ __global__ void fill_u32_kernel(uint32_t *__restrict__ p, size_t n, uint32_t v);
 size_t sort_temp_words(uint32_t n_capacity, int end_bit, int digit_bits)
 {
     digit_bits = std::min(8, std::max(4, digit_bits));
-    const size_t tiles = ((size_t)n_capacity + OS_TILE - 1) / OS_TILE;
+    const size_t tiles = ((size_t)n_capacity + OS_TILE_MIN - 1) / OS_TILE_MIN; // the smaller tiles: more of them
     return OS_STATUS + (size_t)os_passes(end_bit, digit_bits) * std::max<size_t>(tiles, 1) * OS_RADIX;
 }
 
-template <int B>
+template <int B, int I>
 static void os_launch_hist(hipStream_t st, const uint32_t *keys, uint32_t n_host, const uint32_t *n_dev, int blocks,
                            int end_bit, int P, uint32_t *hist)
 {
-    hipLaunchKernelGGL(os_hist_kernel<B>, dim3(blocks), dim3(OS_BLOCK), 0, st, keys, n_dev, n_host, end_bit, P, hist);
+    hipLaunchKernelGGL((os_hist_kernel<B, I>), dim3(blocks), dim3(OS_BLOCK), 0, st, keys, n_dev, n_host, end_bit, P, hist);
 }
 
-template <int B>
+template <int B, int I>
 static void os_launch_scatter(hipStream_t st, const uint32_t *keys, const uint32_t *vals, uint32_t *keys_out,
                               uint32_t *vals_out, uint32_t n_host, const uint32_t *n_dev, int tiles, int shift,
                               const uint32_t *hist, uint32_t *ctr, uint32_t *status, uint32_t *err)
 {
-    hipLaunchKernelGGL(os_scatter_kernel<B>, dim3(tiles), dim3(OS_BLOCK), 0, st, keys, vals, keys_out, vals_out, n_dev,
+    hipLaunchKernelGGL((os_scatter_kernel<B, I>), dim3(tiles), dim3(OS_BLOCK), 0, st, keys, vals, keys_out, vals_out, n_dev,
                        n_host, shift, hist, ctr, status, err);
 }
 
@@ -459,19 +461,34 @@ void radix_sort(hipStream_t st, uint32_t **keys, uint32_t **vals, uint32_t **key
     const uint32_t n_grid = n_dev ? n_capacity : n_host;
     if (n_grid == 0 || end_bit <= 0) return;
     const int P = os_passes(end_bit, digit_bits);
-    const int tiles = (int)((n_grid + OS_TILE - 1) / OS_TILE);
+    // up to 4M elements: tiles of OS_TILE_MIN (more workgroups in flight);
+    // beyond: twice as large (half the look-back chain)
+    const bool small = n_grid <= (1u << 22);
+    const int tile = small ? OS_TILE_MIN : 2 * OS_TILE_MIN;
+    const int tiles = (int)((n_grid + tile - 1) / tile);
     const size_t words = OS_STATUS + (size_t)P * tiles * OS_RADIX;
     const size_t fb = std::min<size_t>((words + 255) / 256, 4096);
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)fb), dim3(256), 0, st, temp, words, 0u);
     const int hb = std::max(1, std::min(tiles, 1024));
     const int widest = os_width(end_bit, P, 0);
-    OS_DISPATCH(widest, os_launch_hist<BB>(st, *keys, n_host, n_dev, hb, end_bit, P, temp));
+    if (small) {
+        OS_DISPATCH(widest, (os_launch_hist<BB, OS_ITEMS_MIN>(st, *keys, n_host, n_dev, hb, end_bit, P, temp)));
+    } else {
+        OS_DISPATCH(widest, (os_launch_hist<BB, 2 * OS_ITEMS_MIN>(st, *keys, n_host, n_dev, hb, end_bit, P, temp)));
+    }
     for (int p = 0; p < P; ++p) {
         const int shift = os_shift(end_bit, P, p);
         const int b = os_width(end_bit, P, p);
         uint32_t *status = temp + OS_STATUS + (size_t)p * tiles * OS_RADIX;
-        OS_DISPATCH(b, os_launch_scatter<BB>(st, *keys, *vals, *keys_alt, *vals_alt, n_host, n_dev, tiles, shift,
-                                             temp + (size_t)p * OS_RADIX, temp + OS_CTR + p, status, err));
+        if (small) {
+            OS_DISPATCH(b, (os_launch_scatter<BB, OS_ITEMS_MIN>(st, *keys, *vals, *keys_alt, *vals_alt, n_host, n_dev,
+                                                                tiles, shift, temp + (size_t)p * OS_RADIX,
+                                                                temp + OS_CTR + p, status, err)));
+        } else {
+            OS_DISPATCH(b, (os_launch_scatter<BB, 2 * OS_ITEMS_MIN>(st, *keys, *vals, *keys_alt, *vals_alt, n_host,
+                                                                    n_dev, tiles, shift, temp + (size_t)p * OS_RADIX,
+                                                                    temp + OS_CTR + p, status, err)));
+        }
         std::swap(*keys, *keys_alt);
         std::swap(*vals, *vals_alt);
     }
