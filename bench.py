@@ -155,12 +155,23 @@ def bench_serving(rates, duration):
                       ("plain_fifo", dict(workers=1, max_batch=1))):
         R.serve_start(hbm_budget_bytes=96 << 30, **cfg)
         sids = [R.scene_register(d) for d in ds]
-        for i in range(8):  # warm-up
-            R.serve_wait(R.serve_submit(sids[i % 4], scenes.orbit_camera(np.random.default_rng(i), 256, 256),
-                                        pools[(256, 256)][0]))
+        # warm-up: half a second of the highest rate's request mix (other poses), so
+        # that the workers' frames and the memory pool have met every scene,
+        # resolution and batch size before the measured streams
+        warm = scenes.serve_requests(max(rates), 0.5, variant=9)
+        t0, wid = time.perf_counter(), []
+        for k, (ta, s_, c) in enumerate(warm):
+            while ta > time.perf_counter() - t0:
+                time.sleep(2e-4)
+            rc, rid = R.serve_submit_raw(sids[s_], make_camera(c), pools[(c.width, c.height)][k % 48].data_ptr())
+            if rc == 0:
+                wid.append(rid)
+        for r_ in wid:
+            R.serve_wait(r_)
         rows = []
         for rate in rates:
             reqs = [(t, sids[s], make_camera(c)) for t, s, c in scenes.serve_requests(rate, duration)]
+            st0 = R.serve_stats()
             ids, pix, k = [], 0, 0
             t0 = time.perf_counter()
             for ta, sid, cam in reqs:
@@ -178,9 +189,11 @@ def bench_serving(rates, duration):
             lat = np.array([R.serve_wait(r) for r in ids])
             wall = time.perf_counter() - t0
             st = R.serve_stats()
+            nb = st["batches"] - st0["batches"]
+            nr = (st["completed"] + st["failed"]) - (st0["completed"] + st0["failed"])
             rows.append({"rate_rps": rate, "requests": len(ids), "p50_ms": float(np.percentile(lat, 50)),
                          "p99_ms": float(np.percentile(lat, 99)), "mpixels_per_s": pix / wall / 1e6,
-                         "mean_batch": st["mean_batch"]})
+                         "mean_batch": nr / nb if nb else 0.0})
         R.serve_stop()
         out["modes"][mode] = rows
     R.close()
