@@ -437,7 +437,9 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
 // pixel coordinates relative to the record's origin, the frame in which the
 // forward pass stored its lines); gradients need relative, not absolute,
 // accuracy.
-template <int K, typename SP>
+// SHL: the SH gradient row lives in LDS (several views add into it);
+// otherwise it is the thread's own row in global memory.
+template <int K, bool SHL, typename SP>
 __device__ __forceinline__ void view_backward(int deg, const float *P, float dl, float sg, const SP *f,
                                               const CamArgs &cam, uint32_t hp, const float *__restrict__ Ag,
                                               float *G, float &gdelta, float &gsigma, float &gopac,
@@ -482,10 +484,14 @@ __device__ __forceinline__ void view_backward(int deg, const float *P, float dl,
     float graw[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) graw[c] = raw[c] > 0.0f ? A[3 * K + 2 + c] : 0.0f;
-    // the SH gradient row of this convex (this thread's alone): stored by the
-    // first view that reaches it, added to by later ones
+    // the SH gradient row of this convex (this thread's alone): in LDS, added
+    // to; in global memory, stored by the first view that reaches it
     float4 *g4 = reinterpret_cast<float4 *>(gsh);
-    if (deg == 3) {
+    if (SHL) {
+        for (int c = 0; c < nc; ++c)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) gsh[3 * c + t] += graw[t] * Yb[c];
+    } else if (deg == 3) {
 #pragma unroll
         for (int q = 0; q < 12; ++q) {
             float gv[4];
@@ -642,6 +648,7 @@ __device__ __forceinline__ void view_backward(int deg, const float *P, float dl,
 }
 
 constexpr int PB_BLOCK = 128;
+constexpr int PB_SH_STRIDE = 49; // odd LDS row stride: per-thread rows conflict-free
 // Block-cooperative, coalesced copies between a contiguous global run of
 // `rows` rows of W floats and LDS rows of stride S.
 template <int W, int S, typename P> __device__ __forceinline__ void rows_to_lds(float *lds, const P *g, int rows)
@@ -656,7 +663,9 @@ template <int W, int S> __device__ __forceinline__ void rows_from_lds(float *g, 
 // gradients leave through LDS as coalesced rows (the point gradients are
 // summed over the views in LDS); each thread keeps its convex's SH gradient
 // row in global memory itself.
-template <int K, typename P>
+// MV (several views): the SH gradients are summed over the views in LDS and
+// leave as coalesced rows; one view writes each row directly.
+template <int K, typename P, bool MV>
 __global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
     int n, int nviews, int deg, const P *__restrict__ points, const P *__restrict__ delta,
     const P *__restrict__ sigma, const P *__restrict__ sh, const FrameHeader *__restrict__ frame,
@@ -667,6 +676,7 @@ __global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
     constexpr int PS = 3 * K + 1;
     __shared__ float s_pts[PB_BLOCK * PS];
     __shared__ float s_gp[PB_BLOCK * PS];
+    __shared__ float s_gsh[MV ? PB_BLOCK * PB_SH_STRIDE : 1];
     const int base = blockIdx.x * PB_BLOCK;
     const int cnt = min(PB_BLOCK, n - base);
     const int tid = threadIdx.x;
@@ -674,6 +684,8 @@ __global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
     rows_to_lds<3 * K, PS>(s_pts, points + (size_t)base * 3 * K, cnt);
 #pragma unroll
     for (int k = 0; k < 3 * K; ++k) s_gp[tid * PS + k] = 0.0f;
+    if constexpr (MV)
+        for (int j = tid; j < PB_BLOCK * PB_SH_STRIDE; j += PB_BLOCK) s_gsh[j] = 0.0f;
     __syncthreads();
 
     const int i = base + tid;
@@ -681,17 +693,17 @@ __global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
         float gdelta = 0.0f, gsigma = 0.0f, gopac = 0.0f;
         const float dl = ld(delta, i), sg = ld(sigma, i);
         const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
-        float *gsh = g_sh + (size_t)i * 3 * nc;
+        float *gsh = MV ? &s_gsh[tid * PB_SH_STRIDE] : g_sh + (size_t)i * 3 * nc;
         bool first = true;
         for (int v = 0; v < nviews; ++v) {
             const size_t inst = (size_t)v * n + i;
             const uint32_t hp = hullpk[inst];
             if ((int)(hp >> 28) < 3) continue; // dropped in this view: no gradient
-            view_backward<K>(deg, &s_pts[tid * PS], dl, sg, sh + (size_t)i * 3 * nc, views[v].cam, hp,
+            view_backward<K, MV>(deg, &s_pts[tid * PS], dl, sg, sh + (size_t)i * 3 * nc, views[v].cam, hp,
                              acc + inst * acc_stride(K), &s_gp[tid * PS], gdelta, gsigma, gopac, gsh, first);
             first = false;
         }
-        if (first) // no view reached the convex
+        if (!MV && first) // no view reached the convex
             for (int c = 0; c < 3 * nc; ++c) gsh[c] = 0.0f;
         g_delta[i] = gdelta;
         g_sigma[i] = gsigma;
@@ -699,6 +711,10 @@ __global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
     }
     __syncthreads();
     rows_from_lds<3 * K, PS>(g_points + (size_t)base * 3 * K, s_gp, cnt);
+    if constexpr (MV) {
+        float *g = g_sh + (size_t)base * 3 * nc;
+        for (int j = tid; j < cnt * 3 * nc; j += PB_BLOCK) g[j] = s_gsh[(j / (3 * nc)) * PB_SH_STRIDE + j % (3 * nc)];
+    }
 }
 
 // ------------------------------------------------------------- launchers ---
@@ -748,10 +764,18 @@ void launch_preprocess_bwd(hipStream_t st, int n, int nviews, int K, int deg, in
 {
     if (n <= 0) return;
     dim3 grid((n + PB_BLOCK - 1) / PB_BLOCK), block(PB_BLOCK);
-    CS_DISPATCH_P(dtype, CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_bwd_kernel<KK, PP>), grid, block, 0, st, n,
-                                                         nviews, deg, (const PP *)points, (const PP *)delta,
-                                                         (const PP *)sigma, (const PP *)sh, views, hullpk,
-                                                         acc, g_points, g_delta, g_sigma, g_opacity, g_sh)));
+    if (nviews > 1)
+        CS_DISPATCH_P(dtype, CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_bwd_kernel<KK, PP, true>), grid, block, 0,
+                                                             st, n, nviews, deg, (const PP *)points,
+                                                             (const PP *)delta, (const PP *)sigma, (const PP *)sh,
+                                                             views, hullpk, acc, g_points, g_delta, g_sigma,
+                                                             g_opacity, g_sh)))
+    else
+        CS_DISPATCH_P(dtype, CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_bwd_kernel<KK, PP, false>), grid, block, 0,
+                                                             st, n, nviews, deg, (const PP *)points,
+                                                             (const PP *)delta, (const PP *)sigma, (const PP *)sh,
+                                                             views, hullpk, acc, g_points, g_delta, g_sigma,
+                                                             g_opacity, g_sh)))
 }
 
 } // namespace cs
