@@ -253,7 +253,7 @@ __device__ __forceinline__ uint32_t next_item(uint32_t *counters, uint32_t total
         while (tried < NUM_QUEUES) {
             const uint32_t lo = q * per, hi = min(total, lo + per);
             if (lo < hi) {
-                const uint32_t k = atomicAdd(&counters[CNT_QUEUE + 2 * q], 1u);
+                const uint32_t k = atomicAdd(&counters[CNT_QUEUE + QUEUE_STRIDE * q], 1u);
                 if (lo + k < hi) { item = lo + k; break; }
             }
             q = (q + 1) % NUM_QUEUES;

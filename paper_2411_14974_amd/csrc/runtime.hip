@@ -172,7 +172,7 @@ int Frame::init(int n_, int K_, int deg_, int V_, size_t tiles, size_t pix, hipS
     CS_A(ord_k_alt, cap_tiles * 4);
     CS_A(ord_v_alt, cap_tiles * 4);
     CS_A(pixstate, cap_pix * 8);
-    counter_words = CNT_WORDS + scan_status_words((uint32_t)cap_inst);
+    counter_words = CNT_STATUS + scan_status_words((uint32_t)cap_inst);
     CS_A(counters, counter_words * 4);
     CS_A(evalcount, 16);
 #undef CS_A
@@ -477,7 +477,7 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
         if (M > F.cap_pairs) { // did not fit: grow, reset the tile queues and counts, run the tail again
             int r = F.ensure_pairs((size_t)std::ceil(M * margin));
             if (r) return r;
-            launch_zero_ranges(st, F.counters + CNT_QUEUE, 2 * NUM_QUEUES, reinterpret_cast<uint32_t *>(F.evalcount), 4,
+            launch_zero_ranges(st, F.counters + CNT_QUEUE, QUEUE_WORDS, reinterpret_cast<uint32_t *>(F.evalcount), 4,
                                nullptr, 0);
             tail(M, nullptr);
         }
@@ -493,7 +493,7 @@ int enqueue_backward(Frame &F, const cs_scene *sc, const cs_grads *g, const Rend
     int r = F.ensure_acc();
     if (r) return r;
     launch_zero_ranges(st, reinterpret_cast<uint32_t *>(F.acc), F.cap_inst * acc_stride(F.K), F.counters + CNT_QUEUE,
-                       2 * NUM_QUEUES, nullptr, 0);
+                       QUEUE_WORDS, nullptr, 0);
     tm.begin();
     launch_render_bwd(st, F.K, F.tile, F.d_frame, F.order, (uint32_t)F.cap_tiles, F.counters, F.ranges, F.sorted_ids,
                       F.records, ra, F.pixstate, F.acc);

@@ -163,7 +163,7 @@ void launch_gather_scan(hipStream_t st, uint32_t n, const uint32_t *sorted_ids, 
     if (n == 0) return;
     const uint32_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     hipLaunchKernelGGL(gather_scan_kernel, dim3(tiles), dim3(SCAN_BLOCK), 0, st, n, sorted_ids, bins, bins_sorted,
-                       counts_sorted, offsets, counters, reinterpret_cast<uint64_t *>(counters + CNT_WORDS));
+                       counts_sorted, offsets, counters, reinterpret_cast<uint64_t *>(counters + CNT_STATUS));
 }
 
 // ----------------------------------------------------------- radix sort ----
