@@ -244,20 +244,32 @@ __device__ __forceinline__ void pipe_store_records(const u32x4 (&pre)[NL], uint4
 // (workgroups are dealt to the 8 XCDs round-robin), so neighbouring tiles, which
 // share convex records, meet in one L2, and steals from the other queues when
 // its own runs dry.  Every workgroup exits once all queues are empty.
+// CHUNK items are claimed per atomic (the workgroup keeps the rest of its
+// run in cnext..cend).
+template <uint32_t CHUNK>
 __device__ __forceinline__ uint32_t next_item(uint32_t *counters, uint32_t total, int &q, int &tried,
-                                              uint32_t *s_item)
+                                              uint32_t &cnext, uint32_t &cend, uint32_t *s_item)
 {
     if (threadIdx.x == 0) {
-        const uint32_t per = (total + NUM_QUEUES - 1) / NUM_QUEUES;
         uint32_t item = 0xFFFFFFFFu;
-        while (tried < NUM_QUEUES) {
-            const uint32_t lo = q * per, hi = min(total, lo + per);
-            if (lo < hi) {
-                const uint32_t k = atomicAdd(&counters[CNT_QUEUE + QUEUE_STRIDE * q], 1u);
-                if (lo + k < hi) { item = lo + k; break; }
+        if (cnext < cend) {
+            item = cnext++;
+        } else {
+            const uint32_t per = (total + NUM_QUEUES - 1) / NUM_QUEUES;
+            while (tried < NUM_QUEUES) {
+                const uint32_t lo = q * per, hi = min(total, lo + per);
+                if (lo < hi) {
+                    const uint32_t k = atomicAdd(&counters[CNT_QUEUE + QUEUE_STRIDE * q], CHUNK);
+                    if (lo + k < hi) {
+                        item = lo + k;
+                        cnext = item + 1;
+                        cend = min(hi, item + CHUNK);
+                        break;
+                    }
+                }
+                q = (q + 1) % NUM_QUEUES;
+                ++tried;
             }
-            q = (q + 1) % NUM_QUEUES;
-            ++tried;
         }
         *s_item = item;
     }
@@ -279,6 +291,10 @@ __device__ __forceinline__ int find_view(const ViewDesc *__restrict__ views, int
 }
 
 } // namespace
+
+// Tiles the forward claims per queue atomic: its per-tile cost is even enough
+// that runs of 2 balance; the backward's varies more and claims one at a time.
+constexpr uint32_t FWD_CHUNK = 2;
 
 // At least 4 wavefronts per SIMD: lets the compiler use up to 128 VGPRs (the
 // record prefetch registers) instead of spilling to reach 8.
@@ -304,9 +320,10 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4)))
     const int nviews = (int)frame->nviews;
     const uint32_t total_tiles = frame->total_tiles;
     int q = blockIdx.x % NUM_QUEUES, tried = 0;
+    uint32_t cnext = 0, cend = 0;
     uint32_t nevals = 0, nfull = 0; // pairs tested / pairs past the max-line test
     for (;;) {
-        const uint32_t item = next_item(counters, total_tiles, q, tried, &s_item);
+        const uint32_t item = next_item<FWD_CHUNK>(counters, total_tiles, q, tried, cnext, cend, &s_item);
         if (item == 0xFFFFFFFFu) break;
         const int gt = order ? (int)order[item] : (int)item;
         const int v = find_view(views, nviews, gt);
@@ -424,8 +441,9 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
     const uint32_t total_tiles = frame->total_tiles;
     const int lane = threadIdx.x & 63, wbit = threadIdx.x >> 6;
     int q = blockIdx.x % NUM_QUEUES, tried = 0;
+    uint32_t cnext = 0, cend = 0;
     for (;;) {
-        const uint32_t item = next_item(counters, total_tiles, q, tried, &s_item);
+        const uint32_t item = next_item<1>(counters, total_tiles, q, tried, cnext, cend, &s_item);
         if (item == 0xFFFFFFFFu) break;
         const int gt = order ? (int)order[item] : (int)item;
         const int v = find_view(views, nviews, gt);
