@@ -505,6 +505,8 @@ void radix_sort(hipStream_t st, uint32_t **keys, uint32_t **vals, uint32_t **key
 // tiles), read from the binning records in depth order.  Instance id = view * n_convex + convex; the view's
 // tiles start at its tile_off.
 constexpr int EMIT_BLOCK = 256;
+constexpr int EMIT_ITEMS = 8;
+constexpr int EMIT_CHUNK = EMIT_BLOCK * EMIT_ITEMS; // pairs whose owners are found per round
 
 // Position of the q-th set bit of m (q < popcount(m)).
 __device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t q)
@@ -534,6 +536,9 @@ __global__ __launch_bounds__(EMIT_BLOCK) void emit_pairs_kernel(
     __shared__ uint32_t s_tx[EMIT_BLOCK];   // the view's tiles_x
     __shared__ uint64_t s_mask[EMIT_BLOCK]; // kept tiles of a rectangle of <= 64 tiles (else unused)
     __shared__ uint32_t s_small[EMIT_BLOCK];
+    __shared__ float s_rw[EMIT_BLOCK];       // 1 / rect width
+    __shared__ uint32_t s_own[EMIT_CHUNK];  // owner (block-local convex) of each pair of the chunk
+    __shared__ uint32_t s_wmax[EMIT_BLOCK / 64];
     __shared__ uint32_t s_end;
     const uint32_t r0 = blockIdx.x * EMIT_BLOCK;
     const int cnt = (int)min((uint32_t)EMIT_BLOCK, n - r0);
@@ -562,24 +567,70 @@ __global__ __launch_bounds__(EMIT_BLOCK) void emit_pairs_kernel(
         s_tx[tid] = tx;
         s_mask[tid] = mask;
         s_small[tid] = small;
+        s_rw[tid] = 1.0f / (float)max(x0w >> 16, 1u);
         if (tid == cnt - 1) s_end = off + counts_sorted[r];
     }
     __syncthreads();
     const uint32_t p0 = s_off[0], p1 = min(s_end, capacity);
-    for (uint32_t p = p0 + tid; p < p1; p += EMIT_BLOCK) {
-        // last entry with s_off <= p (entries with no pairs share the next one's offset)
-        int lo = 0, hi = cnt - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= p) lo = mid;
-            else hi = mid - 1;
+    const int lane = tid & 63, wave = tid >> 6;
+    // The pairs' owners, EMIT_CHUNK pairs at a time: each convex marks the first
+    // pair of its run (entries with no pairs share the next one's offset: the
+    // larger index, the owner, wins), the chunk's first pair gets its owner by
+    // one binary search, and a running maximum carries the marks along the runs.
+    for (uint32_t c0 = p0; c0 < p1; c0 += EMIT_CHUNK) {
+        const uint32_t cn = min((uint32_t)EMIT_CHUNK, p1 - c0);
+        for (int j = tid; j < EMIT_CHUNK; j += EMIT_BLOCK) s_own[j] = 0u;
+        __syncthreads();
+        if (tid == 0) { // last entry with s_off <= c0
+            int lo = 0, hi = cnt - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= c0) lo = mid;
+                else hi = mid - 1;
+            }
+            atomicMax(&s_own[0], (uint32_t)lo);
         }
-        uint32_t q = p - s_off[lo];
-        if (s_small[lo]) q = nth_set_bit(s_mask[lo], q); // the q-th kept tile of the rectangle
-        const uint32_t x0w = s_x0w[lo], w = x0w >> 16;
-        const uint32_t row = q / w, col = q - row * w;
-        pair_tiles[p] = s_base[lo] + row * s_tx[lo] + (x0w & 0xFFFFu) + col;
-        pair_ids[p] = s_id[lo];
+        if (tid < cnt) {
+            const uint32_t o = s_off[tid];
+            if (o >= c0 && o < c0 + cn) atomicMax(&s_own[o - c0], (uint32_t)tid);
+        }
+        __syncthreads();
+        // inclusive running maximum over the chunk: EMIT_ITEMS consecutive entries per thread
+        uint32_t v[EMIT_ITEMS], m = 0u;
+#pragma unroll
+        for (int k = 0; k < EMIT_ITEMS; ++k) {
+            m = max(m, s_own[tid * EMIT_ITEMS + k]);
+            v[k] = m;
+        }
+        uint32_t incl = m;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl = max(incl, y);
+        }
+        if (lane == 63) s_wmax[wave] = incl;
+        __syncthreads();
+        uint32_t before = __shfl_up(incl, 1, 64);
+        if (lane == 0) before = 0u;
+        for (int w = 0; w < wave; ++w) before = max(before, s_wmax[w]);
+#pragma unroll
+        for (int k = 0; k < EMIT_ITEMS; ++k) s_own[tid * EMIT_ITEMS + k] = max(before, v[k]);
+        __syncthreads();
+        for (uint32_t j = tid; j < cn; j += EMIT_BLOCK) {
+            const uint32_t p = c0 + j;
+            const int lo = (int)s_own[j];
+            uint32_t q = p - s_off[lo];
+            if (s_small[lo]) q = nth_set_bit(s_mask[lo], q); // the q-th kept tile of the rectangle
+            const uint32_t x0w = s_x0w[lo], w = x0w >> 16;
+            // q / w through the reciprocal (q < 2^24), corrected by one step
+            uint32_t row = (uint32_t)((float)q * s_rw[lo]);
+            if (row * w > q) --row;
+            else if ((row + 1) * w <= q) ++row;
+            const uint32_t col = q - row * w;
+            pair_tiles[p] = s_base[lo] + row * s_tx[lo] + (x0w & 0xFFFFu) + col;
+            pair_ids[p] = s_id[lo];
+        }
+        __syncthreads();
     }
 }
 
