@@ -84,6 +84,10 @@ static_assert(sizeof(FrameHeader) == 64, "frame header is 64 bytes");
 
 constexpr int MAX_VIEWS = 256;
 constexpr int NUM_QUEUES = 8; // one work queue per XCD
+// Per-workgroup slots of the forward's work counters (tested, full pairs): each
+// workgroup of the persistent grid stores its sums in a slot of its own and
+// readers add the slots (same-address atomics from every wavefront serialise)
+constexpr int EVAL_SLOTS = 16384;
 
 // Device counters of one frame (u32 words).
 // Per-instance binning record (16 bytes): the tile rectangle, tx0 | ty0 << 16

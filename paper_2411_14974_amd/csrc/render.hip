@@ -312,7 +312,9 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4)))
     __shared__ uint4 lds[BATCH * CH];
     __shared__ uint32_t s_ids[2][BATCH];
     __shared__ uint32_t s_item;
+    __shared__ unsigned long long s_ev[2];
     const int lane = threadIdx.x & 63, wbit = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_ev[0] = s_ev[1] = 0ull;
     constexpr int NL = pipe_regs<K, NT, BATCH>();
     u32x4 pre[NL];
     uint32_t idr = 0;
@@ -400,7 +402,7 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4)))
             pixstate[vd.pix_off + pix] = make_uint2((uint32_t)nend, __float_as_uint(Tlast));
         }
     }
-    if (evalcount) {
+    if (evalcount) { // the workgroup's sums, stored in its own slot
         unsigned long long c = nevals, f = nfull;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -408,8 +410,13 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4)))
             f += __shfl_xor(f, o, 64);
         }
         if ((threadIdx.x & 63) == 0) {
-            atomicAdd(evalcount, c);
-            atomicAdd(evalcount + 1, f);
+            atomicAdd(&s_ev[0], c);
+            atomicAdd(&s_ev[1], f);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            evalcount[2 * blockIdx.x] = s_ev[0];
+            evalcount[2 * blockIdx.x + 1] = s_ev[1];
         }
     }
 }
@@ -608,17 +615,21 @@ template <class F> int persistent_grid(F kernel, int threads)
 } // namespace
 
 // max_items bounds the grid (a persistent grid larger than the work only idles).
-void launch_render_fwd(hipStream_t st, int K, int tile, const FrameHeader *frame, const uint32_t *order,
-                       uint32_t max_items, uint32_t *counters, const uint2 *ranges, const uint32_t *ids,
-                       const uint8_t *records, const RenderArgs &ra, uint2 *pixstate, unsigned long long *evalcount)
+// Returns the grid size (the number of evalcount slots written).
+int launch_render_fwd(hipStream_t st, int K, int tile, const FrameHeader *frame, const uint32_t *order,
+                      uint32_t max_items, uint32_t *counters, const uint2 *ranges, const uint32_t *ids,
+                      const uint8_t *records, const RenderArgs &ra, uint2 *pixstate, unsigned long long *evalcount)
 {
-    if (max_items == 0) return;
+    if (max_items == 0) return 0;
+    int used = 0;
     CS_DISPATCH_K(K, CS_DISPATCH_TILE(tile, {
         auto kern = render_fwd_kernel<KK, TT, BF>;
-        const int grid = std::min<int>(persistent_grid(kern, TT * TT), (int)max_items);
+        const int grid = std::min({persistent_grid(kern, TT * TT), (int)max_items, EVAL_SLOTS});
         hipLaunchKernelGGL(kern, dim3(grid), dim3(TT * TT), 0, st, frame, order, counters, ranges, ids, records, ra,
                            pixstate, evalcount);
+        used = grid;
     }));
+    return used;
 }
 
 void launch_render_bwd(hipStream_t st, int K, int tile, const FrameHeader *frame, const uint32_t *order,

@@ -36,7 +36,7 @@ void launch_prepare_tail(hipStream_t, uint32_t *, uint32_t, uint32_t *, size_t);
 void launch_zero_ranges(hipStream_t, uint32_t *, size_t, uint32_t *, size_t, uint32_t *, size_t);
 void launch_tile_length_keys(hipStream_t, uint32_t, const uint2 *, uint32_t *, uint32_t *);
 void launch_tile_ranges(hipStream_t, const uint32_t *, uint32_t, const uint32_t *, uint32_t, uint2 *);
-void launch_render_fwd(hipStream_t, int, int, const FrameHeader *, const uint32_t *, uint32_t, uint32_t *,
+int launch_render_fwd(hipStream_t, int, int, const FrameHeader *, const uint32_t *, uint32_t, uint32_t *,
                        const uint2 *, const uint32_t *, const uint8_t *, const RenderArgs &, uint2 *,
                        unsigned long long *);
 void launch_render_bwd(hipStream_t, int, int, const FrameHeader *, const uint32_t *, uint32_t, uint32_t *,
@@ -174,7 +174,7 @@ int Frame::init(int n_, int K_, int deg_, int V_, size_t tiles, size_t pix, hipS
     CS_A(pixstate, cap_pix * 8);
     counter_words = CNT_STATUS + scan_status_words((uint32_t)cap_inst);
     CS_A(counters, counter_words * 4);
-    CS_A(evalcount, 16);
+    CS_A(evalcount, (size_t)EVAL_SLOTS * 16);
 #undef CS_A
     return CS_OK;
 }
@@ -386,7 +386,7 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
     F.tile = kn.tile;
     F.longest = kn.longest;
     F.digits = kn.digits;
-    launch_zero_ranges(st, F.counters, F.counter_words, reinterpret_cast<uint32_t *>(F.evalcount), 4, nullptr, 0);
+    launch_zero_ranges(st, F.counters, F.counter_words, nullptr, 0, nullptr, 0);
     tm.begin();
     launch_preprocess_fwd(st, n, F.V, F.K, F.deg, sc->dtype, sc->points, sc->delta, sc->sigma, sc->opacity, sc->sh, F.d_frame,
                           ra, F.records, F.keys, F.ids, F.bins, F.hullpk, nullptr);
@@ -426,7 +426,7 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
             F.order = ov;
         }
         tm.begin();
-        launch_render_fwd(st, F.K, kn.tile, F.d_frame, F.order, (uint32_t)F.cap_tiles, F.counters, F.ranges,
+        F.eval_slots = launch_render_fwd(st, F.K, kn.tile, F.d_frame, F.order, (uint32_t)F.cap_tiles, F.counters, F.ranges,
                           F.sorted_ids, F.records, ra, F.pixstate, F.evalcount);
         tm.end(CS_STAGE_RENDER_FWD);
     };
@@ -477,7 +477,7 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
         if (M > F.cap_pairs) { // did not fit: grow, reset the tile queues and counts, run the tail again
             int r = F.ensure_pairs((size_t)std::ceil(M * margin));
             if (r) return r;
-            launch_zero_ranges(st, F.counters + CNT_QUEUE, QUEUE_WORDS, reinterpret_cast<uint32_t *>(F.evalcount), 4,
+            launch_zero_ranges(st, F.counters + CNT_QUEUE, QUEUE_WORDS, nullptr, 0,
                                nullptr, 0);
             tail(M, nullptr);
         }
@@ -996,15 +996,21 @@ int cs_state_stats(cs_ctx *ctx, const cs_fwd_state *s, int64_t *n_pairs, int64_t
     if (!ctx || !s || !s->frame) return fail(CS_EINVAL, "ctx or state is NULL");
     CS_HIP(hipSetDevice(ctx->device));
     Frame *F = s->frame;
-    unsigned long long ev[2] = {0, 0};
+    std::vector<unsigned long long> ev(2 * (size_t)F->eval_slots + 2, 0ull);
     uint32_t cnt[CNT_WORDS];
-    CS_HIP(hipMemcpyAsync(ev, F->evalcount, sizeof(ev), hipMemcpyDeviceToHost, F->st));
+    if (F->eval_slots > 0)
+        CS_HIP(hipMemcpyAsync(ev.data(), F->evalcount, 16 * (size_t)F->eval_slots, hipMemcpyDeviceToHost, F->st));
     CS_HIP(hipMemcpyAsync(cnt, F->counters, sizeof(cnt), hipMemcpyDeviceToHost, F->st));
     CS_HIP(hipStreamSynchronize(F->st));
     if (cnt[CNT_SORT_ERR]) return fail(CS_EHIP, "radix sort: a look-back wait exceeded its bound");
+    unsigned long long tested = 0, full = 0;
+    for (int g = 0; g < F->eval_slots; ++g) {
+        tested += ev[2 * g];
+        full += ev[2 * g + 1];
+    }
     if (n_pairs) *n_pairs = cnt[CNT_PAIRS];
-    if (n_evaluated) *n_evaluated = (int64_t)ev[0];
-    if (n_full) *n_full = (int64_t)ev[1];
+    if (n_evaluated) *n_evaluated = (int64_t)tested;
+    if (n_full) *n_full = (int64_t)full;
     return CS_OK;
 }
 

@@ -52,7 +52,8 @@ struct Frame {
     float *acc = nullptr;
     uint32_t *counters = nullptr; // CNT_WORDS counters, then the pair-offset scan's look-back status
     size_t counter_words = 0;
-    unsigned long long *evalcount = nullptr;
+    unsigned long long *evalcount = nullptr; // EVAL_SLOTS x (tested, full) of the last forward's workgroups
+    int eval_slots = 0;                      // slots that launch wrote
     uint32_t *h_counters = nullptr; // pinned read-back of the counters
     hipEvent_t counters_ev = nullptr;
     hipEvent_t mcount_ev = nullptr; // after the pair count's read-back (reused frames)
