@@ -647,28 +647,63 @@ void launch_render_bwd(hipStream_t st, int K, int tile, const FrameHeader *frame
 
 // ------------------------------------------------------------ L1 loss ----
 
-__global__ void l1_grad_kernel(const float *__restrict__ rgb, const float *__restrict__ target, size_t n, float scale,
-                               float *__restrict__ grad, float *__restrict__ loss)
+// block_sum (nullable): each block stores its sum of |rgb - target| in its
+// own slot (same-address atomics from every block would serialise)
+__global__ __launch_bounds__(256) void l1_grad_kernel(const float *__restrict__ rgb, const float *__restrict__ target,
+                                                      size_t n, float scale, float *__restrict__ grad,
+                                                      float *__restrict__ block_sum)
 {
+    __shared__ float s_w[4];
     float part = 0.0f;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const float d = rgb[i] - target[i];
         grad[i] = d > 0.0f ? scale : (d < 0.0f ? -scale : 0.0f);
         part += fabsf(d);
     }
-    if (loss) {
+    if (block_sum) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-        if ((threadIdx.x & 63) == 0) atomicAdd(loss, part * scale);
+        if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = part;
+        __syncthreads();
+        if (threadIdx.x == 0) block_sum[blockIdx.x] = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
     }
 }
 
-void launch_l1_grad(hipStream_t st, const float *rgb, const float *target, size_t n, float *grad, float *loss)
+// *loss += scale * (sum of the nb block sums): one workgroup
+__global__ __launch_bounds__(1024) void sum_slots_kernel(const float *__restrict__ slots, int nb, float scale,
+                                                         float *__restrict__ loss)
 {
-    if (n == 0) return;
+    __shared__ float s_w[16];
+    float t = 0.0f;
+    for (int b = threadIdx.x; b < nb; b += 1024) t += slots[b];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float u = 0.0f;
+        for (int w = 0; w < 16; ++w) u += s_w[w];
+        *loss += u * scale;
+    }
+}
+
+// Returns hipSuccess, or the error of the scratch allocation (loss only).
+hipError_t launch_l1_grad(hipStream_t st, const float *rgb, const float *target, size_t n, float *grad, float *loss)
+{
+    if (n == 0) return hipSuccess;
     const size_t blocks = std::min<size_t>((n + 255) / 256, 2048);
+    float *slots = nullptr;
+    if (loss) {
+        const hipError_t e = hipMallocAsync((void **)&slots, blocks * sizeof(float), st);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(l1_grad_kernel, dim3((unsigned)blocks), dim3(256), 0, st, rgb, target, n, 1.0f / (float)n,
-                       grad, loss);
+                       grad, slots);
+    if (loss) {
+        hipLaunchKernelGGL(sum_slots_kernel, dim3(1), dim3(1024), 0, st, slots, (int)blocks, 1.0f / (float)n, loss);
+        (void)hipFreeAsync(slots, st);
+    }
+    return hipSuccess;
 }
 
 } // namespace cs

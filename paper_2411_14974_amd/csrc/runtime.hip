@@ -41,7 +41,7 @@ int launch_render_fwd(hipStream_t, int, int, const FrameHeader *, const uint32_t
                        unsigned long long *);
 void launch_render_bwd(hipStream_t, int, int, const FrameHeader *, const uint32_t *, uint32_t, uint32_t *,
                        const uint2 *, const uint32_t *, const uint8_t *, const RenderArgs &, const uint2 *, float *);
-void launch_l1_grad(hipStream_t, const float *, const float *, size_t, float *, float *);
+hipError_t launch_l1_grad(hipStream_t, const float *, const float *, size_t, float *, float *);
 } // namespace cs
 
 using namespace cs;
@@ -1093,7 +1093,8 @@ int cs_l1_loss_grad(cs_ctx *ctx, const float *rgb, const float *target, int32_t 
     if (!ctx || !rgb || !target || !dl_drgb) return fail(CS_EINVAL, "NULL argument");
     if (width <= 0 || height <= 0) return fail(CS_EINVAL, "bad image size");
     CS_HIP(hipSetDevice(ctx->device));
-    launch_l1_grad((hipStream_t)hip_stream, rgb, target, (size_t)width * height * 3, dl_drgb, loss);
+    const hipError_t e = launch_l1_grad((hipStream_t)hip_stream, rgb, target, (size_t)width * height * 3, dl_drgb, loss);
+    if (e != hipSuccess) return fail(CS_ENOMEM, "l1 loss scratch: %s", hipGetErrorString(e));
     CS_HIP(hipGetLastError());
     return CS_OK;
 }

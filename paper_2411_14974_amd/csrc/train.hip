@@ -44,7 +44,7 @@ struct SsimArgs {
 __global__ __launch_bounds__(SS_TILE * SS_TILE) void ssim_moments_kernel(const float *__restrict__ x,
                                                                          const float *__restrict__ y, SsimArgs a,
                                                                          float *__restrict__ part,
-                                                                         float *__restrict__ loss)
+                                                                         float *__restrict__ block_loss)
 {
     constexpr int NM = 15; // per channel: x, y, x^2, y^2, xy
     __shared__ float s_in[SS_IN * SS_IN * 6];
@@ -115,13 +115,35 @@ __global__ __launch_bounds__(SS_TILE * SS_TILE) void ssim_moments_kernel(const f
             contrib += (1.0f - a.lambda) * fabsf(xin[ch] - xin[3 + ch]) - a.lambda * S;
         }
     }
-    // the block's loss terms, one atomic per wavefront
+    // the block's loss terms into its own slot (same-address atomics from
+    // every block would serialise); a last pass adds the slots
+    __shared__ float s_w[SS_TILE * SS_TILE / 64];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) contrib += __shfl_xor(contrib, o, 64);
-    if ((threadIdx.x & 63) == 0) {
-        float add = contrib * a.inv_n;
-        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) add += a.lambda; // lambda (1 - mean S)
-        atomicAdd(loss, add);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = contrib;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int w = 0; w < SS_TILE * SS_TILE / 64; ++w) t += s_w[w];
+        block_loss[blockIdx.y * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// loss += lambda + inv_n * (sum of the blocks' terms): one workgroup.
+__global__ __launch_bounds__(1024) void ssim_loss_sum_kernel(const float *__restrict__ block_loss, int nb, SsimArgs a,
+                                                             float *__restrict__ loss)
+{
+    __shared__ float s_w[16];
+    float t = 0.0f;
+    for (int b = threadIdx.x; b < nb; b += 1024) t += block_loss[b];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float u = 0.0f;
+        for (int w = 0; w < 16; ++w) u += s_w[w];
+        *loss += a.lambda + u * a.inv_n;
     }
 }
 
@@ -312,11 +334,15 @@ int cs_ssim_loss_grad(cs_ctx *ctx, const float *rgb, const float *target, int32_
     double gs[2 * SS_R + 1], tot = 0.0;
     for (int t = -SS_R; t <= SS_R; ++t) tot += gs[t + SS_R] = std::exp(-(double)(t * t) / (2.0 * 1.5 * 1.5));
     for (int t = 0; t <= 2 * SS_R; ++t) a.g[t] = (float)(gs[t] / tot);
-    float *part = nullptr;
-    hipError_t e = hipMallocAsync((void **)&part, (size_t)width * height * 9 * sizeof(float), st);
-    if (e != hipSuccess) return fail(CS_ENOMEM, "ssim scratch: %s", hipGetErrorString(e));
     const dim3 grid((width + SS_TILE - 1) / SS_TILE, (height + SS_TILE - 1) / SS_TILE), block(SS_TILE * SS_TILE);
-    hipLaunchKernelGGL(ssim_moments_kernel, grid, block, 0, st, rgb, target, a, part, loss);
+    const int nb = (int)(grid.x * grid.y);
+    float *part = nullptr;
+    const size_t part_floats = (size_t)width * height * 9;
+    hipError_t e = hipMallocAsync((void **)&part, (part_floats + nb) * sizeof(float), st);
+    if (e != hipSuccess) return fail(CS_ENOMEM, "ssim scratch: %s", hipGetErrorString(e));
+    float *block_loss = part + part_floats;
+    hipLaunchKernelGGL(ssim_moments_kernel, grid, block, 0, st, rgb, target, a, part, block_loss);
+    hipLaunchKernelGGL(ssim_loss_sum_kernel, dim3(1), dim3(1024), 0, st, block_loss, nb, a, loss);
     hipLaunchKernelGGL(ssim_grad_kernel, grid, block, 0, st, rgb, target, a, part, dl_drgb);
     e = hipGetLastError();
     (void)hipFreeAsync(part, st);

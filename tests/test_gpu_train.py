@@ -121,3 +121,18 @@ def test_ssim_loss_matches_oracle(R, W, H, kind):
     say(f"[ssim {W}x{H} {kind}] loss {L:.7f} vs {Lref:.7f}; grad max err / max |g| {err:.1e}")
     assert abs(L - Lref) <= 1e-5 * abs(Lref)
     assert err <= 1e-3
+
+
+@pytest.mark.parametrize("W,H", [(61, 37), (1920, 1080)])
+def test_l1_loss_value_and_gradient(R, W, H):
+    """mean |rgb - target| (added to the loss word) and sign(rgb - target) / n."""
+    rng = np.random.default_rng(W)
+    x = rng.uniform(0, 1, (H, W, 3)).astype(np.float32)
+    y = rng.uniform(0, 1, (H, W, 3)).astype(np.float32)
+    y[:5] = x[:5]  # ties: zero gradient
+    loss = torch.full((1,), 0.5, device="cuda")
+    g = R.l1_loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), loss=loss)
+    torch.cuda.synchronize()
+    want = float(np.abs(x.astype(np.float64) - y).mean())
+    assert abs(float(loss.cpu()[0]) - 0.5 - want) <= 1e-5 * want
+    np.testing.assert_array_equal(g.cpu().numpy(), np.sign(x - y).astype(np.float32) / np.float32(x.size))
