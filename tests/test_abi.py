@@ -117,3 +117,43 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(name, "size")] == C.sizeof(S), name
         for f, _ in S._fields_:
             assert got[(name, f)] == getattr(S, f).offset, (name, f)
+
+
+def test_training_entry_points_reject_bad_arguments_without_a_gpu():
+    """Argument checks of the density-control, loss, optimiser and
+    initialisation entry points run before any device call."""
+    L = binding.lib()
+    dummy = (C.c_char * 64)()
+    E = binding.CS_EINVAL
+    sc = binding.SceneS(10, 6, 3, 1, 1, 1, 1, 1)
+    dp = binding.make_densify_params()
+    out = binding.SceneOut(1, 1, 1, 1, 1, 1)
+    n_out = C.c_int64()
+    assert L.cs_densify(None, C.byref(sc), 1, 1, C.byref(dp), 10, C.byref(out), C.byref(n_out), None) == E
+    assert L.cs_densify(dummy, C.byref(sc), None, 1, C.byref(dp), 10, C.byref(out), C.byref(n_out), None) == E
+    assert L.cs_densify(dummy, C.byref(sc), 1, 1, None, 10, C.byref(out), C.byref(n_out), None) == E
+    assert L.cs_densify(dummy, C.byref(sc), 1, 1, C.byref(dp), -1, C.byref(out), C.byref(n_out), None) == E
+    half = binding.SceneS(10, 6, 3, 1, 1, 1, 1, 1, binding.DTYPE_F16)
+    assert L.cs_densify(dummy, C.byref(half), 1, 1, C.byref(dp), 10, C.byref(out), C.byref(n_out), None) == E
+    assert b"float32" in L.cs_last_error()
+    assert L.cs_densify_accumulate(dummy, None, 1, 1, 1, None) == E
+    # loss: null pointers, bad size, lambda outside [0, 1]
+    assert L.cs_ssim_loss_grad(dummy, None, 1, 8, 8, 0.2, 1, 1, None) == E
+    assert L.cs_ssim_loss_grad(dummy, 1, 1, 0, 8, 0.2, 1, 1, None) == E
+    assert L.cs_ssim_loss_grad(dummy, 1, 1, 8, 8, 1.5, 1, 1, None) == E
+    # Adam: step 0, betas outside [0, 1), bad K
+    g = binding.GradsS(1, 1, 1, 1, 1)
+    ps = binding.ParamSet(1, 1, 1, 1, 1)
+    ap = binding.make_adam_params(0)
+    assert L.cs_adam_step(dummy, 10, 6, 3, C.byref(g), C.byref(ps), C.byref(ps), C.byref(ps), None, C.byref(ap),
+                          None) == E
+    ap = binding.make_adam_params(1, beta2=1.0)
+    assert L.cs_adam_step(dummy, 10, 6, 3, C.byref(g), C.byref(ps), C.byref(ps), C.byref(ps), None, C.byref(ap),
+                          None) == E
+    ap = binding.make_adam_params(1)
+    assert L.cs_adam_step(dummy, 10, 9, 3, C.byref(g), C.byref(ps), C.byref(ps), C.byref(ps), None, C.byref(ap),
+                          None) == E
+    # initialisation: bad K, missing output
+    ip = binding.make_init_params()
+    assert L.cs_init_from_points(dummy, 10, 1, None, 2, 3, C.byref(ip), C.byref(ps), None) == E
+    assert L.cs_init_from_points(dummy, 10, 1, None, 6, 3, C.byref(ip), None, None) == E
