@@ -151,6 +151,7 @@ int Frame::init(int n_, int K_, int deg_, int V_, size_t tiles, size_t pix, hipS
     if (hipEventCreateWithFlags(&mcount_ev, hipEventDisableTiming) != hipSuccess)
         return fail(CS_EHIP, "event creation failed");
     cap_inst = (size_t)n * V;
+    ninst = cap_inst;
     cap_tiles = std::max<size_t>(tiles, 1);
     cap_pix = std::max<size_t>(pix, 1);
     const uint32_t ui = (uint32_t)cap_inst;
@@ -382,7 +383,7 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
 {
     hipStream_t st = F.st;
     const int n = sc->n;
-    const uint32_t ninst = (uint32_t)F.cap_inst;
+    const uint32_t ninst = (uint32_t)F.ninst;
     F.tile = kn.tile;
     F.longest = kn.longest;
     F.digits = kn.digits;
@@ -492,7 +493,7 @@ int enqueue_backward(Frame &F, const cs_scene *sc, const cs_grads *g, const Rend
     hipStream_t st = F.st;
     int r = F.ensure_acc();
     if (r) return r;
-    launch_zero_ranges(st, reinterpret_cast<uint32_t *>(F.acc), F.cap_inst * acc_stride(F.K), F.counters + CNT_QUEUE,
+    launch_zero_ranges(st, reinterpret_cast<uint32_t *>(F.acc), F.ninst * acc_stride(F.K), F.counters + CNT_QUEUE,
                        QUEUE_WORDS, nullptr, 0);
     tm.begin();
     launch_render_bwd(st, F.K, F.tile, F.d_frame, F.order, (uint32_t)F.cap_tiles, F.counters, F.ranges, F.sorted_ids,
@@ -552,20 +553,32 @@ uint64_t scene_key(const cs_scene *sc, int V, const Knobs &kn, const RenderArgs 
     return h;
 }
 
-// An eager frame for (n, K, deg, V) with at least the given tile and pixel
-// capacity: a cached one when available (ordered after its last use), else new.
+// An eager frame for (n, K, deg, V) with at least the given instance, tile and
+// pixel capacity: a cached one when available (ordered after its last use),
+// else new.  A cached frame serves any scene size and view count that fit its
+// buffers (up to 4x larger, so that a small request does not hold a large
+// frame); the one that fits most tightly is taken.
 int acquire_frame(cs_ctx *ctx, int n, int K, int deg, int V, size_t tiles, size_t pix, hipStream_t st, Frame **out)
 {
+    const size_t inst = (size_t)n * V;
+    int best = -1;
     for (size_t i = 0; i < ctx->free_frames.size(); ++i) {
-        Frame *F = ctx->free_frames[i];
-        if (F->n == n && F->K == K && F->deg == deg && F->V == V && F->cap_tiles >= tiles && F->cap_pix >= pix &&
-            F->cap_tiles <= 4 * std::max<size_t>(tiles, 1)) {
-            ctx->free_frames.erase(ctx->free_frames.begin() + i);
-            if (F->ready) (void)hipStreamWaitEvent(st, F->ready, 0);
-            F->st = st;
-            *out = F;
-            return CS_OK;
-        }
+        const Frame *F = ctx->free_frames[i];
+        if (F->K == K && F->deg == deg && F->cap_inst >= inst && F->cap_inst <= 4 * std::max<size_t>(inst, 1) &&
+            F->cap_tiles >= tiles && F->cap_tiles <= 4 * std::max<size_t>(tiles, 1) && F->cap_pix >= pix &&
+            (best < 0 || F->cap_inst < ctx->free_frames[best]->cap_inst))
+            best = (int)i;
+    }
+    if (best >= 0) {
+        Frame *F = ctx->free_frames[best];
+        ctx->free_frames.erase(ctx->free_frames.begin() + best);
+        if (F->ready) (void)hipStreamWaitEvent(st, F->ready, 0);
+        F->st = st;
+        F->n = n;
+        F->V = V;
+        F->ninst = inst;
+        *out = F;
+        return CS_OK;
     }
     Frame *F = new Frame;
     int r = F->init(n, K, deg, V, tiles, pix, st, &ctx->ring);

@@ -34,6 +34,7 @@ struct Frame {
     int n = 0, K = 0, deg = 0, V = 0;
     int tile = 16, longest = 0, digits = 8;
     size_t cap_inst = 0, cap_pairs = 0, cap_tiles = 0, cap_pix = 0;
+    size_t ninst = 0; // instances of the current use (n V <= cap_inst)
     uint32_t npairs = 0;
     hipStream_t st = nullptr;
     std::vector<void *> allocs;
