@@ -137,9 +137,10 @@ def bench_batched(steps, warmup):
     }
 
 
-def bench_serving(rates, duration):
+def bench_serving(rates, duration, max_batch=4, workers=2):
     """Poisson request streams against 4 resident scenes (0.2/0.5/1/2 M convexes), forward only:
-    continuous batching (4 worker streams, batches up to 16 views) vs plain FIFO one request at a time."""
+    continuous batching (worker streams taking batches of one scene's queued requests) vs plain FIFO one
+    request at a time."""
     import torch
 
     from paper_2411_14974_amd import scenes
@@ -151,7 +152,7 @@ def bench_serving(rates, duration):
     out = {"workload": "4 resident mixture scenes of 0.2/0.5/1/2 M convexes (K=6, SH3); requests uniform over "
                        "scenes and 256x256 / 960x540 / 1920x1080, random orbit poses, Poisson arrivals, forward only",
            "duration_s_per_rate": duration, "modes": {}}
-    for mode, cfg in (("continuous_batching", dict(workers=4, max_batch=16)),
+    for mode, cfg in (("continuous_batching", dict(workers=workers, max_batch=max_batch)),
                       ("plain_fifo", dict(workers=1, max_batch=1))):
         R.serve_start(hbm_budget_bytes=96 << 30, **cfg)
         sids = [R.scene_register(d) for d in ds]
@@ -394,8 +395,10 @@ def main():
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
     ap.add_argument("--forms", default="plain,light,train,densify,batched,serving",
                     help="comma list of plain, light (16-bit scene), train, densify, batched, serving")
-    ap.add_argument("--serve-rates", default="50,200,800", help="request rates (req/s) of the serving sweep")
+    ap.add_argument("--serve-rates", default="50,200,800,2000", help="request rates (req/s) of the serving sweep")
     ap.add_argument("--serve-seconds", type=float, default=1.5)
+    ap.add_argument("--serve-max-batch", type=int, default=4, help="requests per batch of continuous batching")
+    ap.add_argument("--serve-workers", type=int, default=2, help="worker streams of continuous batching")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -508,7 +511,8 @@ def main():
     if "batched" in forms:
         line["batched"] = bench_batched(max(3, args.steps // 4), 2)
     if "serving" in forms:
-        line["serving"] = bench_serving([float(r) for r in args.serve_rates.split(",")], args.serve_seconds)
+        line["serving"] = bench_serving([float(r) for r in args.serve_rates.split(",")], args.serve_seconds,
+                                        args.serve_max_batch, args.serve_workers)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, cam, target, args.cpu_sample)
     print(json.dumps(line), flush=True)
