@@ -151,7 +151,8 @@ def bench_serving(rates, duration, max_batch=4, workers=2):
     pools = {wh: [torch.empty((wh[1], wh[0], 3), device=dev) for _ in range(48)] for wh in scenes.RESOLUTIONS_C5}
     out = {"workload": "4 resident mixture scenes of 0.2/0.5/1/2 M convexes (K=6, SH3); requests uniform over "
                        "scenes and 256x256 / 960x540 / 1920x1080, random orbit poses, Poisson arrivals, forward only",
-           "duration_s_per_rate": duration, "modes": {}}
+           "duration_s_per_rate": duration, "continuous_batching": {"workers": workers, "max_batch": max_batch},
+           "modes": {}}
     for mode, cfg in (("continuous_batching", dict(workers=workers, max_batch=max_batch)),
                       ("plain_fifo", dict(workers=1, max_batch=1))):
         R.serve_start(hbm_budget_bytes=96 << 30, **cfg)
