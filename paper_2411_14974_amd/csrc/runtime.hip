@@ -145,15 +145,26 @@ int Frame::init_async_readback()
 }
 
 // Instance-, tile- and pixel-level buffers (pairs come later).
+// Capacities are rounded up to one of four steps per octave (at most 25 %
+// spare), so that cached frames serve whole size classes of later requests.
+static size_t capacity_class(size_t x)
+{
+    if (x <= 1024) return 1024;
+    int lg = 0;
+    while ((x >> (lg + 1)) != 0) ++lg;
+    const size_t q = (size_t)1 << (lg - 2);
+    return (x + q - 1) / q * q;
+}
+
 int Frame::init(int n_, int K_, int deg_, int V_, size_t tiles, size_t pix, hipStream_t s, HostRing *r)
 {
     n = n_; K = K_; deg = deg_; V = V_; st = s; ring = r;
     if (hipEventCreateWithFlags(&mcount_ev, hipEventDisableTiming) != hipSuccess)
         return fail(CS_EHIP, "event creation failed");
-    cap_inst = (size_t)n * V;
-    ninst = cap_inst;
-    cap_tiles = std::max<size_t>(tiles, 1);
-    cap_pix = std::max<size_t>(pix, 1);
+    ninst = (size_t)n * V;
+    cap_inst = capacity_class(ninst);
+    cap_tiles = capacity_class(std::max<size_t>(tiles, 1));
+    cap_pix = capacity_class(std::max<size_t>(pix, 1));
     const uint32_t ui = (uint32_t)cap_inst;
 #define CS_A(ptr, bytes) do { int r_ = alloc((void **)&(ptr), (bytes)); if (r_) return r_; } while (0)
     CS_A(d_frame, VIEW_TABLE_BYTES);
@@ -561,11 +572,14 @@ uint64_t scene_key(const cs_scene *sc, int V, const Knobs &kn, const RenderArgs 
 int acquire_frame(cs_ctx *ctx, int n, int K, int deg, int V, size_t tiles, size_t pix, hipStream_t st, Frame **out)
 {
     const size_t inst = (size_t)n * V;
+    // the classes a new frame would take: a cached one qualifies from there up to 4x
+    const size_t ci = capacity_class(inst), ct = capacity_class(std::max<size_t>(tiles, 1));
+    const size_t cp = capacity_class(std::max<size_t>(pix, 1));
     int best = -1;
     for (size_t i = 0; i < ctx->free_frames.size(); ++i) {
         const Frame *F = ctx->free_frames[i];
-        if (F->K == K && F->deg == deg && F->cap_inst >= inst && F->cap_inst <= 4 * std::max<size_t>(inst, 1) &&
-            F->cap_tiles >= tiles && F->cap_tiles <= 4 * std::max<size_t>(tiles, 1) && F->cap_pix >= pix &&
+        if (F->K == K && F->deg == deg && F->cap_inst >= ci && F->cap_inst <= 4 * ci && F->cap_tiles >= ct &&
+            F->cap_tiles <= 4 * ct && F->cap_pix >= cp &&
             (best < 0 || F->cap_inst < ctx->free_frames[best]->cap_inst))
             best = (int)i;
     }
