@@ -393,7 +393,11 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
     if (active) {
         keys[inst] = status == ST_VISIBLE ? key : KEY_CULLED;
         bins[inst] = has_tiles ? make_bin(tx0, ty0, tx1, ty1, tmask) : make_bin(1, 0, 0, 0, 0);
-        hullpk[inst] = (status == ST_VISIBLE || status == ST_FAINT) ? (packed | ((uint32_t)T << 28)) : 0u;
+        // hull indices (3 bits each, bits 0-23), the clamped colour channels
+        // (bits 24-26: the backward pass's colour gradient is zero there), T
+        hullpk[inst] = (status == ST_VISIBLE || status == ST_FAINT)
+                           ? (packed | ((uint32_t)clampmask << 24) | ((uint32_t)T << 28))
+                           : 0u;
     }
     // the block's records (culled convexes' slots hold whatever the LDS held:
     // nothing reads a culled convex's record)
@@ -436,14 +440,41 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
 // recomputed from the points (camera transform in FP64, the rest in FP32 with
 // pixel coordinates relative to the record's origin, the frame in which the
 // forward pass stored its lines); gradients need relative, not absolute,
-// accuracy.
-// SHL: the SH gradient row lives in LDS (several views add into it);
-// otherwise it is the thread's own row in global memory.
-template <int K, bool SHL, typename SP>
-__device__ __forceinline__ void view_backward(int deg, const float *P, float dl, float sg, const SP *f,
-                                              const CamArgs &cam, uint32_t hp, const float *__restrict__ Ag,
-                                              float *G, float &gdelta, float &gsigma, float &gopac,
-                                              float *__restrict__ gsh, bool first)
+// accuracy.  The colour clamp max(0, raw) is the forward pass's own decision,
+// carried in the packed hull word.
+
+// Unit view direction (camera centre -> point centroid) and its SH basis
+// values, with the forward pass's arithmetic.
+template <int K>
+__device__ __forceinline__ void view_dir(int deg, const float *P, const CamArgs &cam, float &dx, float &dy, float &dz,
+                                         double &inv, float *Yb)
+{
+    double cxw = 0, cyw = 0, czw = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) { cxw += P[3 * k]; cyw += P[3 * k + 1]; czw += P[3 * k + 2]; }
+    const double wx = cxw / K - cam.campos[0], wy = cyw / K - cam.campos[1], wz = czw / K - cam.campos[2];
+    inv = 1.0 / sqrt(wx * wx + wy * wy + wz * wz);
+    dx = (float)(wx * inv);
+    dy = (float)(wy * inv);
+    dz = (float)(wz * inv);
+    sh_eval(deg, dx, dy, dz, Yb);
+}
+
+// dL/draw per channel: the colour accumulator where the forward pass did not clamp.
+template <int K> __device__ __forceinline__ float colour_grad(uint32_t hp, const float *__restrict__ Ag, int c)
+{
+    return ((hp >> (24 + c)) & 1u) ? 0.0f : Ag[3 * K + 2 + c];
+}
+
+// Everything after the SH coefficients: wsum_c = sum_t dL/draw_t f_ct gives
+// the direction's gradient; then the hull lines, projection and depth.
+// ADD: G accumulates (several views); otherwise G is assigned, after the
+// last read of P (G may be P's own row).
+template <int K, bool ADD>
+__device__ __forceinline__ void geometry_backward(int deg, const float *P, float dl, float sg, const CamArgs &cam,
+                                                  uint32_t hp, const float *__restrict__ Ag, const float *wsum,
+                                                  float dx, float dy, float dz, double inv, float *G, float &gdelta,
+                                                  float &gsigma, float &gopac)
 {
     // the instance's accumulator row, in 16-byte loads
     float A[acc_stride(K)];
@@ -453,82 +484,6 @@ __device__ __forceinline__ void view_backward(int deg, const float *P, float dl,
         A[4 * q] = w.x; A[4 * q + 1] = w.y; A[4 * q + 2] = w.z; A[4 * q + 3] = w.w;
     }
     const int T = (int)(hp >> 28);
-    const int nc = (deg + 1) * (deg + 1);
-
-    // colour -> SH coefficients and the view direction (same arithmetic as the
-    // forward pass); first, while few geometry values are live
-    double cxw = 0, cyw = 0, czw = 0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) { cxw += P[3 * k]; cyw += P[3 * k + 1]; czw += P[3 * k + 2]; }
-    const double wx = cxw / K - cam.campos[0], wy = cyw / K - cam.campos[1], wz = czw / K - cam.campos[2];
-    const double inv = 1.0 / sqrt(wx * wx + wy * wy + wz * wz);
-    const float dx = (float)(wx * inv), dy = (float)(wy * inv), dz = (float)(wz * inv);
-    float Yb[16];
-    sh_eval(deg, dx, dy, dz, Yb);
-    float raw[3] = {0.5f, 0.5f, 0.5f};
-    if (deg == 3) { // 48-value rows: 4 values per load
-#pragma unroll
-        for (int q = 0; q < 12; ++q) {
-            const float4 w = ld4(f, q);
-            const float wv[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-            for (int t = 0; t < 4; ++t) raw[(4 * q + t) % 3] = fmaf(Yb[(4 * q + t) / 3], wv[t], raw[(4 * q + t) % 3]);
-        }
-    } else {
-        for (int c = 0; c < nc; ++c) {
-            raw[0] = fmaf(Yb[c], ld(f, 3 * c + 0), raw[0]);
-            raw[1] = fmaf(Yb[c], ld(f, 3 * c + 1), raw[1]);
-            raw[2] = fmaf(Yb[c], ld(f, 3 * c + 2), raw[2]);
-        }
-    }
-    float graw[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) graw[c] = raw[c] > 0.0f ? A[3 * K + 2 + c] : 0.0f;
-    // the SH gradient row of this convex (this thread's alone): in LDS, added
-    // to; in global memory, stored by the first view that reaches it
-    float4 *g4 = reinterpret_cast<float4 *>(gsh);
-    if (SHL) {
-        for (int c = 0; c < nc; ++c)
-#pragma unroll
-            for (int t = 0; t < 3; ++t) gsh[3 * c + t] += graw[t] * Yb[c];
-    } else if (deg == 3) {
-#pragma unroll
-        for (int q = 0; q < 12; ++q) {
-            float gv[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) gv[t] = graw[(4 * q + t) % 3] * Yb[(4 * q + t) / 3];
-            float4 o = make_float4(gv[0], gv[1], gv[2], gv[3]);
-            if (!first) {
-                const float4 pv = g4[q];
-                o = make_float4(pv.x + o.x, pv.y + o.y, pv.z + o.z, pv.w + o.w);
-            }
-            g4[q] = o;
-        }
-    } else {
-        for (int c = 0; c < nc; ++c)
-#pragma unroll
-            for (int t = 0; t < 3; ++t) gsh[3 * c + t] = (first ? 0.0f : gsh[3 * c + t]) + graw[t] * Yb[c];
-    }
-    float wsum[16];
-    if (deg == 3) {
-        // read the coefficients again (from cache) rather than hold 48 registers across the stores
-        __asm__ volatile("" ::: "memory");
-#pragma unroll
-        for (int c = 0; c < 16; ++c) wsum[c] = 0.0f;
-#pragma unroll
-        for (int q = 0; q < 12; ++q) { // wsum_c = sum_k graw_k f_ck, same order as below
-            const float4 w = ld4(f, q);
-            const float wv[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int e = 4 * q + t;
-                wsum[e / 3] = (e % 3 == 0) ? graw[0] * wv[t] : wsum[e / 3] + graw[e % 3] * wv[t];
-            }
-        }
-    } else {
-        for (int c = 0; c < nc; ++c)
-            wsum[c] = graw[0] * ld(f, 3 * c + 0) + graw[1] * ld(f, 3 * c + 1) + graw[2] * ld(f, 3 * c + 2);
-    }
     float gdx = 0.f, gdy = 0.f, gdz = 0.f;
     sh_grad_dot(deg, dx, dy, dz, wsum, gdx, gdy, gdz);
     // unit direction -> centre:  (I - dir dir^T) / |centre - campos|, then / K per point
@@ -641,10 +596,37 @@ __device__ __forceinline__ void view_backward(int deg, const float *P, float dl,
     for (int k = 0; k < K; ++k) {
         const float gX = gqx[k] * fx * iz[k], gY = gqy[k] * fy * iz[k];
         const float gZ = -(gX * xz[k] + gY * yz[k]) + gd / K;
-        G[3 * k + 0] += R0 * gX + R3 * gY + R6 * gZ + gcx;
-        G[3 * k + 1] += R1 * gX + R4 * gY + R7 * gZ + gcy;
-        G[3 * k + 2] += R2 * gX + R5 * gY + R8 * gZ + gcz;
+        const float o0 = R0 * gX + R3 * gY + R6 * gZ + gcx;
+        const float o1 = R1 * gX + R4 * gY + R7 * gZ + gcy;
+        const float o2 = R2 * gX + R5 * gY + R8 * gZ + gcz;
+        G[3 * k + 0] = ADD ? G[3 * k + 0] + o0 : o0;
+        G[3 * k + 1] = ADD ? G[3 * k + 1] + o1 : o1;
+        G[3 * k + 2] = ADD ? G[3 * k + 2] + o2 : o2;
     }
+}
+
+
+// One view of a convex whose SH gradient row (in LDS) sums several views:
+// the thread reads its own coefficient row.
+template <int K, typename SP>
+__device__ __forceinline__ void view_backward_rows(int deg, const float *P, float dl, float sg, const SP *f,
+                                                   const CamArgs &cam, uint32_t hp, const float *__restrict__ Ag,
+                                                   float *G, float &gdelta, float &gsigma, float &gopac, float *gsh)
+{
+    const int nc = (deg + 1) * (deg + 1);
+    float dx, dy, dz, Yb[16];
+    double inv;
+    view_dir<K>(deg, P, cam, dx, dy, dz, inv, Yb);
+    const float gr[3] = {colour_grad<K>(hp, Ag, 0), colour_grad<K>(hp, Ag, 1), colour_grad<K>(hp, Ag, 2)};
+    float wsum[16];
+    for (int c = 0; c < nc; ++c) {
+        const float f0 = ld(f, 3 * c + 0), f1 = ld(f, 3 * c + 1), f2 = ld(f, 3 * c + 2);
+        wsum[c] = gr[0] * f0 + gr[1] * f1 + gr[2] * f2;
+        gsh[3 * c + 0] += gr[0] * Yb[c];
+        gsh[3 * c + 1] += gr[1] * Yb[c];
+        gsh[3 * c + 2] += gr[2] * Yb[c];
+    }
+    geometry_backward<K, true>(deg, P, dl, sg, cam, hp, Ag, wsum, dx, dy, dz, inv, G, gdelta, gsigma, gopac);
 }
 
 constexpr int PB_BLOCK = 128;
@@ -661,12 +643,17 @@ template <int W, int S> __device__ __forceinline__ void rows_from_lds(float *g, 
 }
 // One thread per convex, 128 convexes per workgroup.  Points arrive and their
 // gradients leave through LDS as coalesced rows (the point gradients are
-// summed over the views in LDS); each thread keeps its convex's SH gradient
-// row in global memory itself.
-// MV (several views): the SH gradients are summed over the views in LDS and
-// leave as coalesced rows; one view writes each row directly.
+// summed over the views in LDS).
+// One view (MV false): the SH work runs block-cooperatively on (convex,
+// coefficient) items, so the coefficient rows are read and their gradient
+// rows written as contiguous runs: each thread puts its direction's basis
+// values and its colour gradient in LDS, the items read the three channels
+// of one coefficient, store their gradients and leave wsum_c in place of the
+// basis value, and each thread finishes its convex's geometry.
+// Several views (MV true): each thread adds its views into its LDS gradient
+// row, which leaves as coalesced rows at the end.
 template <int K, typename P, bool MV>
-__global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
+__global__ __launch_bounds__(PB_BLOCK) __attribute__((amdgpu_waves_per_eu(MV || K > 6 ? 1 : 4))) void preprocess_bwd_kernel(
     int n, int nviews, int deg, const P *__restrict__ points, const P *__restrict__ delta,
     const P *__restrict__ sigma, const P *__restrict__ sh, const FrameHeader *__restrict__ frame,
     const uint32_t *__restrict__ hullpk, const float *__restrict__ acc,
@@ -674,47 +661,98 @@ __global__ __launch_bounds__(PB_BLOCK) void preprocess_bwd_kernel(
     float *__restrict__ g_opacity, float *__restrict__ g_sh)
 {
     constexpr int PS = 3 * K + 1;
+    constexpr int YS = 17; // odd LDS row stride of the basis values / wsum
     __shared__ float s_pts[PB_BLOCK * PS];
-    __shared__ float s_gp[PB_BLOCK * PS];
-    __shared__ float s_gsh[MV ? PB_BLOCK * PB_SH_STRIDE : 1];
+    // point gradients: summed over the views apart (MV); with one view each
+    // thread overwrites its own point row once it has read it
+    __shared__ float s_gpv[MV ? PB_BLOCK * PS : 1];
+    float *s_gp = MV ? s_gpv : s_pts;
+    __shared__ float s_gsh[MV ? PB_BLOCK * PB_SH_STRIDE : PB_BLOCK * YS];
+    __shared__ float s_gr[MV ? 1 : PB_BLOCK * 3];
     const int base = blockIdx.x * PB_BLOCK;
     const int cnt = min(PB_BLOCK, n - base);
     const int tid = threadIdx.x;
     const int nc = (deg + 1) * (deg + 1);
     rows_to_lds<3 * K, PS>(s_pts, points + (size_t)base * 3 * K, cnt);
+    if constexpr (MV) {
 #pragma unroll
-    for (int k = 0; k < 3 * K; ++k) s_gp[tid * PS + k] = 0.0f;
-    if constexpr (MV)
+        for (int k = 0; k < 3 * K; ++k) s_gp[tid * PS + k] = 0.0f;
         for (int j = tid; j < PB_BLOCK * PB_SH_STRIDE; j += PB_BLOCK) s_gsh[j] = 0.0f;
+    }
     __syncthreads();
 
     const int i = base + tid;
-    if (tid < cnt) {
-        float gdelta = 0.0f, gsigma = 0.0f, gopac = 0.0f;
-        const float dl = ld(delta, i), sg = ld(sigma, i);
-        const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
-        float *gsh = MV ? &s_gsh[tid * PB_SH_STRIDE] : g_sh + (size_t)i * 3 * nc;
-        bool first = true;
-        for (int v = 0; v < nviews; ++v) {
-            const size_t inst = (size_t)v * n + i;
-            const uint32_t hp = hullpk[inst];
-            if ((int)(hp >> 28) < 3) continue; // dropped in this view: no gradient
-            view_backward<K, MV>(deg, &s_pts[tid * PS], dl, sg, sh + (size_t)i * 3 * nc, views[v].cam, hp,
-                             acc + inst * acc_stride(K), &s_gp[tid * PS], gdelta, gsigma, gopac, gsh, first);
-            first = false;
+    const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
+    if constexpr (MV) {
+        if (tid < cnt) {
+            float gdelta = 0.0f, gsigma = 0.0f, gopac = 0.0f;
+            const float dl = ld(delta, i), sg = ld(sigma, i);
+            for (int v = 0; v < nviews; ++v) {
+                const size_t inst = (size_t)v * n + i;
+                const uint32_t hp = hullpk[inst];
+                if ((int)(hp >> 28) < 3) continue; // dropped in this view: no gradient
+                view_backward_rows<K>(deg, &s_pts[tid * PS], dl, sg, sh + (size_t)i * 3 * nc, views[v].cam, hp,
+                                      acc + inst * acc_stride(K), &s_gp[tid * PS], gdelta, gsigma, gopac,
+                                      &s_gsh[tid * PB_SH_STRIDE]);
+            }
+            g_delta[i] = gdelta;
+            g_sigma[i] = gsigma;
+            g_opacity[i] = gopac;
         }
-        if (!MV && first) // no view reached the convex
-            for (int c = 0; c < 3 * nc; ++c) gsh[c] = 0.0f;
-        g_delta[i] = gdelta;
-        g_sigma[i] = gsigma;
-        g_opacity[i] = gopac;
+        __syncthreads();
+        float *g = g_sh + (size_t)base * 3 * nc;
+        for (int j = tid; j < cnt * 3 * nc; j += PB_BLOCK) g[j] = s_gsh[(j / (3 * nc)) * PB_SH_STRIDE + j % (3 * nc)];
+    } else {
+        const CamArgs &cam = views[0].cam;
+        const uint32_t hp = tid < cnt ? hullpk[i] : 0u;
+        const bool live = (int)(hp >> 28) >= 3; // dropped (or past n): no gradient
+        const float *Ag = acc + (size_t)i * acc_stride(K);
+        float dx = 0.f, dy = 0.f, dz = 0.f, Yb[16];
+        double inv = 0.0;
+        if (live) {
+            view_dir<K>(deg, &s_pts[tid * PS], cam, dx, dy, dz, inv, Yb);
+            for (int c = 0; c < nc; ++c) s_gsh[tid * YS + c] = Yb[c];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s_gr[tid * 3 + c] = colour_grad<K>(hp, Ag, c);
+        } else {
+            for (int c = 0; c < nc; ++c) s_gsh[tid * YS + c] = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s_gr[tid * 3 + c] = 0.0f;
+        }
+        __syncthreads();
+        {
+            const P *f = sh + (size_t)base * 3 * nc;
+            float *g = g_sh + (size_t)base * 3 * nc;
+            for (int j = tid; j < cnt * nc; j += PB_BLOCK) {
+                const int row = j / nc, c = j - row * nc;
+                const float gr0 = s_gr[row * 3], gr1 = s_gr[row * 3 + 1], gr2 = s_gr[row * 3 + 2];
+                const float y = s_gsh[row * YS + c];
+                const float f0 = ld(f, 3 * j), f1 = ld(f, 3 * j + 1), f2 = ld(f, 3 * j + 2);
+                g[3 * j] = gr0 * y;
+                g[3 * j + 1] = gr1 * y;
+                g[3 * j + 2] = gr2 * y;
+                s_gsh[row * YS + c] = gr0 * f0 + gr1 * f1 + gr2 * f2;
+            }
+        }
+        __syncthreads();
+        if (tid < cnt) {
+            float gdelta = 0.0f, gsigma = 0.0f, gopac = 0.0f;
+            if (live) {
+                float wsum[16];
+                for (int c = 0; c < nc; ++c) wsum[c] = s_gsh[tid * YS + c];
+                geometry_backward<K, false>(deg, &s_pts[tid * PS], ld(delta, i), ld(sigma, i), cam, hp, Ag, wsum,
+                                            dx, dy, dz, inv, &s_pts[tid * PS], gdelta, gsigma, gopac);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 3 * K; ++k) s_pts[tid * PS + k] = 0.0f;
+            }
+            g_delta[i] = gdelta;
+            g_sigma[i] = gsigma;
+            g_opacity[i] = gopac;
+        }
     }
     __syncthreads();
     rows_from_lds<3 * K, PS>(g_points + (size_t)base * 3 * K, s_gp, cnt);
-    if constexpr (MV) {
-        float *g = g_sh + (size_t)base * 3 * nc;
-        for (int j = tid; j < cnt * 3 * nc; j += PB_BLOCK) g[j] = s_gsh[(j / (3 * nc)) * PB_SH_STRIDE + j % (3 * nc)];
-    }
 }
 
 // ------------------------------------------------------------- launchers ---
