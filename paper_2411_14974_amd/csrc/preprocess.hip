@@ -59,6 +59,32 @@ __device__ __forceinline__ void pixel_span(double a, double b, int n, int &lo, i
     hi = (int)h;
 }
 
+// Block-cooperative copy of `rows` contiguous global rows of W values into
+// LDS rows of stride S.  U loads per thread are issued before the first LDS
+// store: a plain loop would wait for each load in turn.
+template <int NT, int U, typename P>
+__device__ __forceinline__ void stage_rows(float *lds, const P *g, int rows, int W, int S)
+{
+    const int total = rows * W;
+    const int drow = NT / W, dcol = NT - drow * W;
+    int row = (int)threadIdx.x / W, col = (int)threadIdx.x - row * W;
+    for (int j0 = threadIdx.x; j0 < total; j0 += U * NT) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + u * NT;
+            v[u] = j < total ? ld(g, j) : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (j0 + u * NT < total) lds[row * S + col] = v[u];
+            row += drow;
+            col += dcol;
+            if (col >= W) { col -= W; ++row; }
+        }
+    }
+}
+
 } // namespace
 
 constexpr int PF_BLOCK = 128;
@@ -83,10 +109,7 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
     float *s_pts = reinterpret_cast<float *>(s_buf);
     const int base = blockIdx.x * PF_BLOCK;
     const int cnt = min(PF_BLOCK, n - base);
-    {
-        const P *g = points + (size_t)base * 3 * K;
-        for (int j = threadIdx.x; j < cnt * 3 * K; j += PF_BLOCK) s_pts[(j / (3 * K)) * PS + j % (3 * K)] = ld(g, j);
-    }
+    stage_rows<PF_BLOCK, 3 * K>(s_pts, points + (size_t)base * 3 * K, cnt, 3 * K, PS);
     __syncthreads();
     // one (view, convex) instance per thread; all outputs are indexed by the
     // instance (threads past n compute on the last convex and store nothing)
@@ -631,12 +654,8 @@ __device__ __forceinline__ void view_backward_rows(int deg, const float *P, floa
 
 constexpr int PB_BLOCK = 128;
 constexpr int PB_SH_STRIDE = 49; // odd LDS row stride: per-thread rows conflict-free
-// Block-cooperative, coalesced copies between a contiguous global run of
-// `rows` rows of W floats and LDS rows of stride S.
-template <int W, int S, typename P> __device__ __forceinline__ void rows_to_lds(float *lds, const P *g, int rows)
-{
-    for (int j = threadIdx.x; j < rows * W; j += PB_BLOCK) lds[(j / W) * S + j % W] = ld(g, j);
-}
+// Block-cooperative, coalesced copy of LDS rows of stride S into a
+// contiguous global run of `rows` rows of W floats.
 template <int W, int S> __device__ __forceinline__ void rows_from_lds(float *g, const float *lds, int rows)
 {
     for (int j = threadIdx.x; j < rows * W; j += PB_BLOCK) g[j] = lds[(j / W) * S + j % W];
@@ -673,7 +692,7 @@ __global__ __launch_bounds__(PB_BLOCK) __attribute__((amdgpu_waves_per_eu(MV || 
     const int cnt = min(PB_BLOCK, n - base);
     const int tid = threadIdx.x;
     const int nc = (deg + 1) * (deg + 1);
-    rows_to_lds<3 * K, PS>(s_pts, points + (size_t)base * 3 * K, cnt);
+    stage_rows<PB_BLOCK, 3 * K>(s_pts, points + (size_t)base * 3 * K, cnt, 3 * K, PS);
     if constexpr (MV) {
 #pragma unroll
         for (int k = 0; k < 3 * K; ++k) s_gp[tid * PS + k] = 0.0f;
@@ -721,17 +740,36 @@ __global__ __launch_bounds__(PB_BLOCK) __attribute__((amdgpu_waves_per_eu(MV || 
         }
         __syncthreads();
         {
+            // U items per thread in flight (their loads issued together)
+            constexpr int U = 8;
             const P *f = sh + (size_t)base * 3 * nc;
             float *g = g_sh + (size_t)base * 3 * nc;
-            for (int j = tid; j < cnt * nc; j += PB_BLOCK) {
-                const int row = j / nc, c = j - row * nc;
-                const float gr0 = s_gr[row * 3], gr1 = s_gr[row * 3 + 1], gr2 = s_gr[row * 3 + 2];
-                const float y = s_gsh[row * YS + c];
-                const float f0 = ld(f, 3 * j), f1 = ld(f, 3 * j + 1), f2 = ld(f, 3 * j + 2);
-                g[3 * j] = gr0 * y;
-                g[3 * j + 1] = gr1 * y;
-                g[3 * j + 2] = gr2 * y;
-                s_gsh[row * YS + c] = gr0 * f0 + gr1 * f1 + gr2 * f2;
+            const int total = cnt * nc;
+            const int drow = PB_BLOCK / nc, dc = PB_BLOCK - drow * nc;
+            int row = tid / nc, c = tid - row * nc;
+            for (int j0 = tid; j0 < total; j0 += U * PB_BLOCK) {
+                float fv[U][3];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = j0 + u * PB_BLOCK;
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) fv[u][t] = j < total ? ld(f, 3 * j + t) : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = j0 + u * PB_BLOCK;
+                    if (j < total) {
+                        const float gr0 = s_gr[row * 3], gr1 = s_gr[row * 3 + 1], gr2 = s_gr[row * 3 + 2];
+                        const float y = s_gsh[row * YS + c];
+                        g[3 * j] = gr0 * y;
+                        g[3 * j + 1] = gr1 * y;
+                        g[3 * j + 2] = gr2 * y;
+                        s_gsh[row * YS + c] = gr0 * fv[u][0] + gr1 * fv[u][1] + gr2 * fv[u][2];
+                    }
+                    row += drow;
+                    c += dc;
+                    if (c >= nc) { c -= nc; ++row; }
+                }
             }
         }
         __syncthreads();
