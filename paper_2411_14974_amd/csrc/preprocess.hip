@@ -489,23 +489,26 @@ template <int K> __device__ __forceinline__ float colour_grad(uint32_t hp, const
     return ((hp >> (24 + c)) & 1u) ? 0.0f : Ag[3 * K + 2 + c];
 }
 
+// An instance's accumulator row, in 16-byte loads.
+template <int K> __device__ __forceinline__ void load_acc_row(const float *__restrict__ Ag, float *A)
+{
+#pragma unroll
+    for (int q = 0; q < acc_stride(K) / 4; ++q) {
+        const float4 w = reinterpret_cast<const float4 *>(Ag)[q];
+        A[4 * q] = w.x; A[4 * q + 1] = w.y; A[4 * q + 2] = w.z; A[4 * q + 3] = w.w;
+    }
+}
+
 // Everything after the SH coefficients: wsum_c = sum_t dL/draw_t f_ct gives
 // the direction's gradient; then the hull lines, projection and depth.
 // ADD: G accumulates (several views); otherwise G is assigned, after the
 // last read of P (G may be P's own row).
 template <int K, bool ADD>
 __device__ __forceinline__ void geometry_backward(int deg, const float *P, float dl, float sg, const CamArgs &cam,
-                                                  uint32_t hp, const float *__restrict__ Ag, const float *wsum,
+                                                  uint32_t hp, const float *A, const float *wsum,
                                                   float dx, float dy, float dz, double inv, float *G, float &gdelta,
                                                   float &gsigma, float &gopac)
 {
-    // the instance's accumulator row, in 16-byte loads
-    float A[acc_stride(K)];
-#pragma unroll
-    for (int q = 0; q < acc_stride(K) / 4; ++q) {
-        const float4 w = reinterpret_cast<const float4 *>(Ag)[q];
-        A[4 * q] = w.x; A[4 * q + 1] = w.y; A[4 * q + 2] = w.z; A[4 * q + 3] = w.w;
-    }
     const int T = (int)(hp >> 28);
     float gdx = 0.f, gdy = 0.f, gdz = 0.f;
     sh_grad_dot(deg, dx, dy, dz, wsum, gdx, gdy, gdz);
@@ -629,27 +632,65 @@ __device__ __forceinline__ void geometry_backward(int deg, const float *P, float
 }
 
 
-// One view of a convex whose SH gradient row (in LDS) sums several views:
-// the thread reads its own coefficient row.
-template <int K, typename SP>
+// One view of a convex whose SH gradient row (in LDS) sums several views.
+// D3 (degree 3): the convex's 48 coefficients arrive in registers (read once
+// for all views); otherwise the thread reads its own coefficient row.
+// A: the instance's accumulator row (in registers).
+template <int K, bool D3, typename SP>
 __device__ __forceinline__ void view_backward_rows(int deg, const float *P, float dl, float sg, const SP *f,
-                                                   const CamArgs &cam, uint32_t hp, const float *__restrict__ Ag,
+                                                   const float *fr, const CamArgs &cam, uint32_t hp, const float *A,
                                                    float *G, float &gdelta, float &gsigma, float &gopac, float *gsh)
 {
-    const int nc = (deg + 1) * (deg + 1);
     float dx, dy, dz, Yb[16];
     double inv;
     view_dir<K>(deg, P, cam, dx, dy, dz, inv, Yb);
-    const float gr[3] = {colour_grad<K>(hp, Ag, 0), colour_grad<K>(hp, Ag, 1), colour_grad<K>(hp, Ag, 2)};
+    float gr[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gr[c] = ((hp >> (24 + c)) & 1u) ? 0.0f : A[3 * K + 2 + c];
     float wsum[16];
-    for (int c = 0; c < nc; ++c) {
-        const float f0 = ld(f, 3 * c + 0), f1 = ld(f, 3 * c + 1), f2 = ld(f, 3 * c + 2);
-        wsum[c] = gr[0] * f0 + gr[1] * f1 + gr[2] * f2;
-        gsh[3 * c + 0] += gr[0] * Yb[c];
-        gsh[3 * c + 1] += gr[1] * Yb[c];
-        gsh[3 * c + 2] += gr[2] * Yb[c];
+    if constexpr (D3) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            wsum[c] = gr[0] * fr[3 * c] + gr[1] * fr[3 * c + 1] + gr[2] * fr[3 * c + 2];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) gsh[3 * c + t] += gr[t] * Yb[c];
+        }
+    } else {
+        const int nc = (deg + 1) * (deg + 1);
+        for (int c = 0; c < nc; ++c) {
+            const float f0 = ld(f, 3 * c + 0), f1 = ld(f, 3 * c + 1), f2 = ld(f, 3 * c + 2);
+            wsum[c] = gr[0] * f0 + gr[1] * f1 + gr[2] * f2;
+            gsh[3 * c + 0] += gr[0] * Yb[c];
+            gsh[3 * c + 1] += gr[1] * Yb[c];
+            gsh[3 * c + 2] += gr[2] * Yb[c];
+        }
     }
-    geometry_backward<K, true>(deg, P, dl, sg, cam, hp, Ag, wsum, dx, dy, dz, inv, G, gdelta, gsigma, gopac);
+    geometry_backward<K, true>(deg, P, dl, sg, cam, hp, A, wsum, dx, dy, dz, inv, G, gdelta, gsigma, gopac);
+}
+
+// The views of one convex (several views): the next view's packed hull word
+// and accumulator row are loaded while the current view is worked on.
+template <int K, bool D3, typename SP>
+__device__ __forceinline__ void views_backward(int n, int i, int nviews, int deg, const float *P, float dl, float sg,
+                                               const SP *f, const float *fr, const ViewDesc *views,
+                                               const uint32_t *__restrict__ hullpk, const float *__restrict__ acc,
+                                               float *G, float &gdelta, float &gsigma, float &gopac, float *gsh)
+{
+    uint32_t hp = hullpk[i];
+    float A[acc_stride(K)];
+    load_acc_row<K>(acc + (size_t)i * acc_stride(K), A);
+    for (int v = 0; v < nviews; ++v) {
+        const int vn = min(v + 1, nviews - 1); // the last view reloads itself (unused)
+        const size_t instn = (size_t)vn * n + i;
+        const uint32_t hpn = hullpk[instn];
+        float An[acc_stride(K)];
+        load_acc_row<K>(acc + instn * acc_stride(K), An);
+        if ((int)(hp >> 28) >= 3) // else dropped in this view: no gradient
+            view_backward_rows<K, D3>(deg, P, dl, sg, f, fr, views[v].cam, hp, A, G, gdelta, gsigma, gopac, gsh);
+        hp = hpn;
+#pragma unroll
+        for (int q = 0; q < acc_stride(K); ++q) A[q] = An[q];
+    }
 }
 
 constexpr int PB_BLOCK = 128;
@@ -706,13 +747,19 @@ __global__ __launch_bounds__(PB_BLOCK) __attribute__((amdgpu_waves_per_eu(MV || 
         if (tid < cnt) {
             float gdelta = 0.0f, gsigma = 0.0f, gopac = 0.0f;
             const float dl = ld(delta, i), sg = ld(sigma, i);
-            for (int v = 0; v < nviews; ++v) {
-                const size_t inst = (size_t)v * n + i;
-                const uint32_t hp = hullpk[inst];
-                if ((int)(hp >> 28) < 3) continue; // dropped in this view: no gradient
-                view_backward_rows<K>(deg, &s_pts[tid * PS], dl, sg, sh + (size_t)i * 3 * nc, views[v].cam, hp,
-                                      acc + inst * acc_stride(K), &s_gp[tid * PS], gdelta, gsigma, gopac,
-                                      &s_gsh[tid * PB_SH_STRIDE]);
+            const P *f = sh + (size_t)i * 3 * nc;
+            if (deg == 3) {
+                float fr[48];
+#pragma unroll
+                for (int q = 0; q < 12; ++q) {
+                    const float4 w = ld4(f, q);
+                    fr[4 * q] = w.x; fr[4 * q + 1] = w.y; fr[4 * q + 2] = w.z; fr[4 * q + 3] = w.w;
+                }
+                views_backward<K, true>(n, i, nviews, deg, &s_pts[tid * PS], dl, sg, f, fr, views, hullpk, acc,
+                                        &s_gp[tid * PS], gdelta, gsigma, gopac, &s_gsh[tid * PB_SH_STRIDE]);
+            } else {
+                views_backward<K, false>(n, i, nviews, deg, &s_pts[tid * PS], dl, sg, f, nullptr, views, hullpk,
+                                         acc, &s_gp[tid * PS], gdelta, gsigma, gopac, &s_gsh[tid * PB_SH_STRIDE]);
             }
             g_delta[i] = gdelta;
             g_sigma[i] = gsigma;
@@ -776,9 +823,10 @@ __global__ __launch_bounds__(PB_BLOCK) __attribute__((amdgpu_waves_per_eu(MV || 
         if (tid < cnt) {
             float gdelta = 0.0f, gsigma = 0.0f, gopac = 0.0f;
             if (live) {
-                float wsum[16];
+                float wsum[16], A[acc_stride(K)];
                 for (int c = 0; c < nc; ++c) wsum[c] = s_gsh[tid * YS + c];
-                geometry_backward<K, false>(deg, &s_pts[tid * PS], ld(delta, i), ld(sigma, i), cam, hp, Ag, wsum,
+                load_acc_row<K>(Ag, A);
+                geometry_backward<K, false>(deg, &s_pts[tid * PS], ld(delta, i), ld(sigma, i), cam, hp, A, wsum,
                                             dx, dy, dz, inv, &s_pts[tid * PS], gdelta, gsigma, gopac);
             } else {
 #pragma unroll
