@@ -483,12 +483,6 @@ __device__ __forceinline__ void view_dir(int deg, const float *P, const CamArgs 
     sh_eval(deg, dx, dy, dz, Yb);
 }
 
-// dL/draw per channel: the colour accumulator where the forward pass did not clamp.
-template <int K> __device__ __forceinline__ float colour_grad(uint32_t hp, const float *__restrict__ Ag, int c)
-{
-    return ((hp >> (24 + c)) & 1u) ? 0.0f : Ag[3 * K + 2 + c];
-}
-
 // An instance's accumulator row, in 16-byte loads.
 template <int K> __device__ __forceinline__ void load_acc_row(const float *__restrict__ Ag, float *A)
 {
@@ -775,11 +769,15 @@ __global__ __launch_bounds__(PB_BLOCK) __attribute__((amdgpu_waves_per_eu(MV || 
         const float *Ag = acc + (size_t)i * acc_stride(K);
         float dx = 0.f, dy = 0.f, dz = 0.f, Yb[16];
         double inv = 0.0;
+        // the accumulator row, read once and held until the geometry step (a
+        // second read after the SH phase would find it evicted)
+        float A[acc_stride(K)];
         if (live) {
+            load_acc_row<K>(Ag, A);
             view_dir<K>(deg, &s_pts[tid * PS], cam, dx, dy, dz, inv, Yb);
             for (int c = 0; c < nc; ++c) s_gsh[tid * YS + c] = Yb[c];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) s_gr[tid * 3 + c] = colour_grad<K>(hp, Ag, c);
+            for (int c = 0; c < 3; ++c) s_gr[tid * 3 + c] = ((hp >> (24 + c)) & 1u) ? 0.0f : A[3 * K + 2 + c];
         } else {
             for (int c = 0; c < nc; ++c) s_gsh[tid * YS + c] = 0.0f;
 #pragma unroll
@@ -788,7 +786,7 @@ __global__ __launch_bounds__(PB_BLOCK) __attribute__((amdgpu_waves_per_eu(MV || 
         __syncthreads();
         {
             // U items per thread in flight (their loads issued together)
-            constexpr int U = 8;
+            constexpr int U = 4;
             const P *f = sh + (size_t)base * 3 * nc;
             float *g = g_sh + (size_t)base * 3 * nc;
             const int total = cnt * nc;
@@ -823,9 +821,8 @@ __global__ __launch_bounds__(PB_BLOCK) __attribute__((amdgpu_waves_per_eu(MV || 
         if (tid < cnt) {
             float gdelta = 0.0f, gsigma = 0.0f, gopac = 0.0f;
             if (live) {
-                float wsum[16], A[acc_stride(K)];
+                float wsum[16];
                 for (int c = 0; c < nc; ++c) wsum[c] = s_gsh[tid * YS + c];
-                load_acc_row<K>(Ag, A);
                 geometry_backward<K, false>(deg, &s_pts[tid * PS], ld(delta, i), ld(sigma, i), cam, hp, A, wsum,
                                             dx, dy, dz, inv, &s_pts[tid * PS], gdelta, gsigma, gopac);
             } else {
