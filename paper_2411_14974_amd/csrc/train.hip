@@ -50,14 +50,31 @@ __global__ __launch_bounds__(SS_TILE * SS_TILE) void ssim_moments_kernel(const f
     __shared__ float s_in[SS_IN * SS_IN * 6];
     __shared__ float s_h[SS_IN * SS_TILE * NM];
     const int tx0 = blockIdx.x * SS_TILE - SS_R, ty0 = blockIdx.y * SS_TILE - SS_R;
-    for (int j = threadIdx.x; j < SS_IN * SS_IN; j += SS_TILE * SS_TILE) {
-        const int r = j / SS_IN, c = j - r * SS_IN, u = tx0 + c, v = ty0 + r;
-        const bool in = u >= 0 && u < a.W && v >= 0 && v < a.H;
-        const size_t p = 3 * ((size_t)v * a.W + u);
+    {
+        // the halo tile: every load of a thread issued before its LDS stores
+        constexpr int NIN = SS_IN * SS_IN, PER = (NIN + SS_TILE * SS_TILE - 1) / (SS_TILE * SS_TILE);
+        float xv[PER][3], yv[PER][3];
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            s_in[j * 6 + ch] = in ? x[p + ch] : 0.0f;
-            s_in[j * 6 + 3 + ch] = in ? y[p + ch] : 0.0f;
+        for (int k = 0; k < PER; ++k) {
+            const int j = threadIdx.x + k * SS_TILE * SS_TILE;
+            const int r = j / SS_IN, c = j - r * SS_IN, u = tx0 + c, v = ty0 + r;
+            const bool in = j < NIN && u >= 0 && u < a.W && v >= 0 && v < a.H;
+            const size_t p = in ? 3 * ((size_t)v * a.W + u) : 0;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                xv[k][ch] = in ? x[p + ch] : 0.0f;
+                yv[k][ch] = in ? y[p + ch] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int j = threadIdx.x + k * SS_TILE * SS_TILE;
+            if (j < NIN)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    s_in[j * 6 + ch] = xv[k][ch];
+                    s_in[j * 6 + 3 + ch] = yv[k][ch];
+                }
         }
     }
     __syncthreads();
@@ -157,11 +174,23 @@ __global__ __launch_bounds__(SS_TILE * SS_TILE) void ssim_grad_kernel(const floa
     __shared__ float s_in[SS_IN * SS_IN * NP];
     __shared__ float s_h[SS_IN * SS_TILE * NP];
     const int tx0 = blockIdx.x * SS_TILE - SS_R, ty0 = blockIdx.y * SS_TILE - SS_R;
-    for (int j = threadIdx.x; j < SS_IN * SS_IN * NP; j += SS_TILE * SS_TILE) {
-        const int pix = j / NP, q = j - pix * NP;
-        const int r = pix / SS_IN, c = pix - r * SS_IN, u = tx0 + c, v = ty0 + r;
-        const bool in = u >= 0 && u < a.W && v >= 0 && v < a.H;
-        s_in[j] = in ? part[NP * ((size_t)v * a.W + u) + q] : 0.0f;
+    {
+        // the halo tile of the partials: every load of a thread issued before its LDS stores
+        constexpr int NE = SS_IN * SS_IN * NP, PER = (NE + SS_TILE * SS_TILE - 1) / (SS_TILE * SS_TILE);
+        float pv[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int j = threadIdx.x + k * SS_TILE * SS_TILE;
+            const int pix = j / NP, q = j - pix * NP;
+            const int r = pix / SS_IN, c = pix - r * SS_IN, u = tx0 + c, v = ty0 + r;
+            const bool in = j < NE && u >= 0 && u < a.W && v >= 0 && v < a.H;
+            pv[k] = in ? part[NP * ((size_t)v * a.W + u) + q] : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int j = threadIdx.x + k * SS_TILE * SS_TILE;
+            if (j < NE) s_in[j] = pv[k];
+        }
     }
     __syncthreads();
     for (int j = threadIdx.x; j < SS_IN * SS_TILE; j += SS_TILE * SS_TILE) {
@@ -238,7 +267,10 @@ __global__ __launch_bounds__(256) void adam_kernel(size_t n, const float *__rest
         const float mm = m0 + a.omb1 * (g - m0);
         const float vv = a.beta2 * v[e] + a.omb2 * (g * g);
         const float denom = sqrtf(vv) / a.bc2_sqrt + a.eps;
-        const float ss = (row > 0 && (int)(e % (size_t)row) >= first) ? a.step_size2 : a.step_size;
+        // position in the row (32-bit arithmetic when the index fits: a 64-bit
+        // remainder is a long software sequence)
+        const uint32_t col = row <= 0 ? 0u : (n >> 32) == 0 ? (uint32_t)e % (uint32_t)row : (uint32_t)(e % (size_t)row);
+        const float ss = (row > 0 && (int)col >= first) ? a.step_size2 : a.step_size;
         const float rn = r - ss * (mm / denom);
         raw[e] = rn;
         m[e] = mm;
