@@ -125,6 +125,26 @@ __global__ __launch_bounds__(DN_SCAN_THREADS) void densify_scan_kernel(int nb, u
     }
 }
 
+// for j in [threadIdx.x, total) in steps of DN_BLOCK: store(j, load(j)), with
+// U loads of a thread issued before their stores (a plain copy loop waits for
+// each load in turn: the stores might alias the next loads).
+template <int U, typename L, typename S> __device__ __forceinline__ void batched_for(int total, L load, S store)
+{
+    for (int j0 = threadIdx.x; j0 < total; j0 += U * DN_BLOCK) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + u * DN_BLOCK;
+            v[u] = j < total ? load(j) : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + u * DN_BLOCK;
+            if (j < total) store(j, v[u]);
+        }
+    }
+}
+
 // The block's kept convexes go to one contiguous run of output rows and its
 // children to another, so the rows are copied cooperatively (consecutive
 // threads, consecutive floats) from LDS lists of the block's kept and split
@@ -171,14 +191,20 @@ __global__ __launch_bounds__(DN_BLOCK) void densify_scatter_kernel(
     __syncthreads();
     const size_t kbase = blk[2 * blockIdx.x], sbase = (size_t)tot[0] + (size_t)K * blk[2 * blockIdx.x + 1];
     // kept rows
-    for (int j = threadIdx.x; j < (int)nk * PK; j += DN_BLOCK) {
+    batched_for<8>((int)nk * PK, [&](int j) {
         const int r = j / PK, e = j - r * PK;
-        out.points[(kbase + r) * PK + e] = points[(size_t)s_keep[r] * PK + e];
-    }
-    for (int j = threadIdx.x; j < (int)nk * nsh; j += DN_BLOCK) {
+        return points[(size_t)s_keep[r] * PK + e];
+    }, [&](int j, float x) {
+        const int r = j / PK, e = j - r * PK;
+        out.points[(kbase + r) * PK + e] = x;
+    });
+    batched_for<8>((int)nk * nsh, [&](int j) {
         const int r = j / nsh, e = j - r * nsh;
-        out.sh[(kbase + r) * nsh + e] = sh[(size_t)s_keep[r] * nsh + e];
-    }
+        return sh[(size_t)s_keep[r] * nsh + e];
+    }, [&](int j, float x) {
+        const int r = j / nsh, e = j - r * nsh;
+        out.sh[(kbase + r) * nsh + e] = x;
+    });
     for (int r = threadIdx.x; r < (int)nk; r += DN_BLOCK) {
         const uint32_t src = s_keep[r];
         out.delta[kbase + r] = delta[src];
@@ -189,16 +215,16 @@ __global__ __launch_bounds__(DN_BLOCK) void densify_scatter_kernel(
     // children: row q = t K + k is child k of the block's t-th split convex,
     // the convex scaled by child_scale about its point k
     const float s = dp.child_scale;
-    for (int j = threadIdx.x; j < (int)ns * K * PK; j += DN_BLOCK) {
+    batched_for<8>((int)ns * K * PK, [&](int j) {
         const int q = j / PK, e = j - q * PK;
         const int t = q / K, k = q - t * K, d = e % 3;
         const float *p = points + (size_t)s_split[t] * PK;
-        out.points[(sbase + q) * PK + e] = p[3 * k + d] + s * (p[e] - s_c[3 * t + d]);
-    }
-    for (int j = threadIdx.x; j < (int)ns * K * nsh; j += DN_BLOCK) {
+        return p[3 * k + d] + s * (p[e] - s_c[3 * t + d]);
+    }, [&](int j, float x) { out.points[sbase * PK + j] = x; });
+    batched_for<8>((int)ns * K * nsh, [&](int j) {
         const int q = j / nsh, e = j - q * nsh;
-        out.sh[(sbase + q) * nsh + e] = sh[(size_t)s_split[q / K] * nsh + e];
-    }
+        return sh[(size_t)s_split[q / K] * nsh + e];
+    }, [&](int j, float x) { out.sh[sbase * nsh + j] = x; });
     for (int q = threadIdx.x; q < (int)ns * K; q += DN_BLOCK) {
         const uint32_t src = s_split[q / K];
         out.delta[sbase + q] = delta[src];
