@@ -133,10 +133,7 @@ template <int U, typename L, typename S> __device__ __forceinline__ void batched
     for (int j0 = threadIdx.x; j0 < total; j0 += U * DN_BLOCK) {
         float v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = j0 + u * DN_BLOCK;
-            v[u] = j < total ? load(j) : 0.0f;
-        }
+        for (int u = 0; u < U; ++u) v[u] = load(min(j0 + u * DN_BLOCK, total - 1)); // unconditional loads
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int j = j0 + u * DN_BLOCK;

@@ -70,11 +70,10 @@ __device__ __forceinline__ void stage_rows(float *lds, const P *g, int rows, int
     int row = (int)threadIdx.x / W, col = (int)threadIdx.x - row * W;
     for (int j0 = threadIdx.x; j0 < total; j0 += U * NT) {
         float v[U];
+        // unconditional loads (a clamped index): a guarded load compiles to a
+        // branch and a wait of its own
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = j0 + u * NT;
-            v[u] = j < total ? ld(g, j) : 0.0f;
-        }
+        for (int u = 0; u < U; ++u) v[u] = ld(g, min(j0 + u * NT, total - 1));
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (j0 + u * NT < total) lds[row * S + col] = v[u];
@@ -796,9 +795,13 @@ __global__ __launch_bounds__(PB_BLOCK) __attribute__((amdgpu_waves_per_eu(MV || 
                 float fv[U][3];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int j = j0 + u * PB_BLOCK;
+                    // 16-bit loads unconditional (a clamped index): guarded, they
+                    // compile to a branch and a wait each; float32 loads are
+                    // predicated and issue back to back either way
+                    const int j = j0 + u * PB_BLOCK, jc = min(j, total - 1);
 #pragma unroll
-                    for (int t = 0; t < 3; ++t) fv[u][t] = j < total ? ld(f, 3 * j + t) : 0.0f;
+                    for (int t = 0; t < 3; ++t)
+                        fv[u][t] = sizeof(P) == 4 ? (j < total ? ld(f, 3 * j + t) : 0.0f) : ld(f, 3 * jc + t);
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {

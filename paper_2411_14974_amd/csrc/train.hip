@@ -59,11 +59,12 @@ __global__ __launch_bounds__(SS_TILE * SS_TILE) void ssim_moments_kernel(const f
             const int j = threadIdx.x + k * SS_TILE * SS_TILE;
             const int r = j / SS_IN, c = j - r * SS_IN, u = tx0 + c, v = ty0 + r;
             const bool in = j < NIN && u >= 0 && u < a.W && v >= 0 && v < a.H;
-            const size_t p = in ? 3 * ((size_t)v * a.W + u) : 0;
+            const size_t p = in ? 3 * ((size_t)v * a.W + u) : 0; // unconditional loads, zeroed after
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
-                xv[k][ch] = in ? x[p + ch] : 0.0f;
-                yv[k][ch] = in ? y[p + ch] : 0.0f;
+                const float xl = x[p + ch], yl = y[p + ch];
+                xv[k][ch] = in ? xl : 0.0f;
+                yv[k][ch] = in ? yl : 0.0f;
             }
         }
 #pragma unroll
@@ -184,7 +185,8 @@ __global__ __launch_bounds__(SS_TILE * SS_TILE) void ssim_grad_kernel(const floa
             const int pix = j / NP, q = j - pix * NP;
             const int r = pix / SS_IN, c = pix - r * SS_IN, u = tx0 + c, v = ty0 + r;
             const bool in = j < NE && u >= 0 && u < a.W && v >= 0 && v < a.H;
-            pv[k] = in ? part[NP * ((size_t)v * a.W + u) + q] : 0.0f;
+            const float l = part[in ? NP * ((size_t)v * a.W + u) + q : 0]; // unconditional load, zeroed after
+            pv[k] = in ? l : 0.0f;
         }
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
