@@ -264,6 +264,33 @@ def test_backward_k_and_degree(R, k, deg):
     backward_parity(R, scene, cam, f"K={k},D={deg}", seed=k)
 
 
+def test_backward_clamped_colours(R):
+    """Colours clamped at 0 (Sec. 3.2: the SH colour is kept non-negative) in
+    many convexes and channels: the backward pass takes the clamp decision of
+    the forward pass, so a clamped channel passes no gradient to its SH
+    coefficients, and every other gradient still matches the oracle."""
+    import oracle
+    rng = np.random.default_rng(4242)
+    scene = scenes.convexes_around(rng, scenes.uniform_centres(rng, 3000), 6, 3)
+    red, green = rng.random(scene.n) < 0.5, rng.random(scene.n) < 0.25
+    scene.sh[red, 0, 0] = -3.0                  # raw red ~ 0.5 - 0.85: clamped
+    scene.sh[green, 0, 1] = -1.8                # raw green near 0: clamped or not
+    cam = scenes.orbit_camera(rng, 160, 100)
+    cm = np.array([c.clampmask for c in oracle.preprocess(scene, cam)])
+    say(f"[clamp] red clamped in {int(((cm & 1) != 0).sum())}, green in {int(((cm & 2) != 0).sum())} of {scene.n}")
+    assert ((cm & 1) != 0).sum() > scene.n // 4 and ((cm & 2) != 0).sum() > 0
+    ds, rgb, st = render_gpu(R, scene, cam, want_state=True)
+    dl = rng.normal(size=(cam.height, cam.width, 3)).astype(np.float32)
+    g = R.backward(st, torch.from_numpy(dl).cuda())
+    torch.cuda.synchronize()
+    gsh = g["sh"].cpu().numpy()
+    for bit, ch in ((1, 0), (2, 1)):
+        assert np.all(gsh[(cm & bit) != 0][:, :, ch] == 0.0)
+    ref = oracle.backward(scene, cam, dl.reshape(-1, 3), mode=oracle.MODE_MATCHED)
+    grad_check(g, ref, "clamped colours")
+    st.release()
+
+
 # ------------------------------------------------ full size, sampled -------
 
 def sampled_parity(R, scene, cam, label, npix=400, seed=0):
