@@ -265,15 +265,29 @@ __global__ __launch_bounds__(OS_BLOCK) void os_hist_kernel(const uint32_t *__res
     __syncthreads();
     const uint32_t ntiles = (n + TILE - 1) / TILE;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        // each thread counts a contiguous run of ITEMS keys (16-byte loads), so
+        // the lanes of a wave hold keys ITEMS apart: runs of equal digits (pairs
+        // of one convex in neighbouring tiles) fall to one thread instead of
+        // colliding on one LDS counter across the wave
+        const size_t base = (size_t)t * TILE + (size_t)threadIdx.x * ITEMS;
         uint32_t k[ITEMS];
+        int cnt;
+        if (base + ITEMS <= n) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(keys + base);
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const size_t idx = (size_t)t * TILE + (size_t)i * OS_BLOCK + threadIdx.x;
-            k[i] = idx < n ? keys[idx] : 0u;
+            for (int q = 0; q < ITEMS / 4; ++q) {
+                const uint4 w = src[q];
+                k[4 * q] = w.x; k[4 * q + 1] = w.y; k[4 * q + 2] = w.z; k[4 * q + 3] = w.w;
+            }
+            cnt = ITEMS;
+        } else {
+            cnt = base < n ? (int)(n - base) : 0;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) k[i] = i < cnt ? keys[base + i] : 0u;
         }
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i)
-            if ((size_t)t * TILE + (size_t)i * OS_BLOCK + threadIdx.x < n)
+            if (i < cnt)
                 for (int p = 0; p < P; ++p)
                     atomicAdd(&h[wave][p * R + ((k[i] >> os_shift(end_bit, P, p)) & ((1u << os_width(end_bit, P, p)) - 1u))],
                               1u);
