@@ -466,7 +466,8 @@ static void os_launch_scatter(hipStream_t st, const uint32_t *keys, const uint32
 // n_dev may be NULL (n_host used); with n_dev the element count is read on the
 // device (graph capture needs no host read-back) and n_capacity bounds it.
 // temp: sort_temp_words(n_capacity, end_bit, digit_bits) words.  *err (device)
-// gets bit 0 set if a look-back wait ran out of its bound.
+// gets bit 0 set if a look-back wait ran out of its bound.  The key arrays must
+// be 16-byte aligned (the histogram pass reads them in 16-byte loads).
 void radix_sort(hipStream_t st, uint32_t **keys, uint32_t **vals, uint32_t **keys_alt, uint32_t **vals_alt,
                 uint32_t n_host, const uint32_t *n_dev, uint32_t n_capacity, int end_bit, uint32_t *temp,
                 int digit_bits, uint32_t *err)
