@@ -115,6 +115,37 @@ def test_batch_backward_sums_views_and_matches_oracle(R):
     st.release()
 
 
+@pytest.mark.parametrize("k,deg,dtype", [(4, 1, "f32"), (8, 2, "f32"), (3, 0, "f32"), (6, 3, "f16"), (5, 2, "bf16")])
+def test_batch_backward_other_k_degree_storage(R, k, deg, dtype):
+    """The several-view backward keeps degree-3 SH coefficients in registers
+    (float32 or 16-bit storage) and reads lower degrees row by row: every form
+    sums to the per-view gradients."""
+    from paper_2411_14974_amd.binding import DeviceScene, make_params
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
+    rng = np.random.default_rng(4300 + 10 * k + deg)
+    scene = scenes.convexes_around(rng, scenes.uniform_centres(rng, 3001), k, deg)
+    cams = [scenes.orbit_camera(rng, *wh) for wh in ((96, 64), (81, 57), (120, 72), (64, 48))]
+    ds = DeviceScene.from_scene(scene, "cuda:0", dtype=tdt)
+    dls = [torch.from_numpy(rng.normal(size=(c.height, c.width, 3)).astype(np.float32)).cuda() for c in cams]
+    _, st = R.forward_batch(ds, cams, make_params(), want_state=True)
+    g = R.backward_batch(st, dls)
+    torch.cuda.synchronize()
+    total = {name: torch.zeros_like(g[name]) for name in NAMES}
+    for c, d in zip(cams, dls):
+        _, s1 = R.forward(ds, c, make_params(), want_state=True)
+        g1 = R.backward(s1, d)
+        torch.cuda.synchronize()
+        for name in NAMES:
+            total[name] += g1[name]
+        s1.release()
+    for name in NAMES:
+        a, b = g[name].cpu().numpy().astype(np.float64), total[name].cpu().numpy().astype(np.float64)
+        gap = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+        assert gap <= 1e-5, (k, deg, dtype, name, gap)
+    say(f"[batch-bwd K={k} D={deg} {dtype}] equals the sum of per-view gradients")
+    st.release()
+
+
 @pytest.mark.parametrize("tile,longest", [(8, 0), (32, 0), (16, 1), (8, 1), (32, 1)])
 def test_tile_configs_identical_and_match_oracle(R, tile, longest):
     import oracle
