@@ -484,7 +484,7 @@ void radix_sort(hipStream_t st, uint32_t **keys, uint32_t **vals, uint32_t **key
     const size_t words = OS_STATUS + (size_t)P * tiles * OS_RADIX;
     const size_t fb = std::min<size_t>((words + 255) / 256, 4096);
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)fb), dim3(256), 0, st, temp, words, 0u);
-    const int hb = std::max(1, std::min(tiles, 1024));
+    const int hb = std::max(1, std::min(tiles, 256)); // one workgroup per CU: fewer same-address global adds
     const int widest = os_width(end_bit, P, 0);
     if (small) {
         OS_DISPATCH(widest, (os_launch_hist<BB, OS_ITEMS_MIN>(st, *keys, n_host, n_dev, hb, end_bit, P, temp)));
