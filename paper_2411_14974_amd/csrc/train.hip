@@ -251,33 +251,66 @@ struct AdamArgs {
 };
 
 // Elements e with row > 0 and e % row >= first take the second rate.
+// One parameter element: the activation's derivative at the current raw
+// value, the moment updates and the step on the raw value.
+template <int ACT>
+__device__ __forceinline__ void adam_element(size_t e, size_t n, float r, float gact, float m0, float v0, int row,
+                                             int first, const AdamArgs &a, float &rn, float &mm, float &vv)
+{
+    float da = 1.0f; // d activated / d raw at the current raw value
+    if constexpr (ACT == ACT_EXP) da = expf(r);
+    else if constexpr (ACT == ACT_SIGMOID) {
+        const float s = 1.0f / (1.0f + expf(-r));
+        da = s * (1.0f - s);
+    }
+    const float g = gact * da;
+    mm = m0 + a.omb1 * (g - m0);
+    vv = a.beta2 * v0 + a.omb2 * (g * g);
+    const float denom = sqrtf(vv) / a.bc2_sqrt + a.eps;
+    // position in the row (32-bit arithmetic when the index fits: a 64-bit
+    // remainder is a long software sequence)
+    const uint32_t col = row <= 0 ? 0u : (n >> 32) == 0 ? (uint32_t)e % (uint32_t)row : (uint32_t)(e % (size_t)row);
+    const float ss = (row > 0 && (int)col >= first) ? a.step_size2 : a.step_size;
+    rn = r - ss * (mm / denom);
+}
+
 template <int ACT>
 __global__ __launch_bounds__(256) void adam_kernel(size_t n, const float *__restrict__ g_act, float *__restrict__ raw,
                                                    float *__restrict__ m, float *__restrict__ v,
                                                    float *__restrict__ act_out, int row, int first, AdamArgs a)
 {
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        const float r = raw[e];
-        float da = 1.0f; // d activated / d raw at the current raw value
-        if constexpr (ACT == ACT_EXP) da = expf(r);
-        else if constexpr (ACT == ACT_SIGMOID) {
-            const float s = 1.0f / (1.0f + expf(-r));
-            da = s * (1.0f - s);
-        }
-        const float g = g_act[e] * da;
-        const float m0 = m[e];
-        const float mm = m0 + a.omb1 * (g - m0);
-        const float vv = a.beta2 * v[e] + a.omb2 * (g * g);
-        const float denom = sqrtf(vv) / a.bc2_sqrt + a.eps;
-        // position in the row (32-bit arithmetic when the index fits: a 64-bit
-        // remainder is a long software sequence)
-        const uint32_t col = row <= 0 ? 0u : (n >> 32) == 0 ? (uint32_t)e % (uint32_t)row : (uint32_t)(e % (size_t)row);
-        const float ss = (row > 0 && (int)col >= first) ? a.step_size2 : a.step_size;
-        const float rn = r - ss * (mm / denom);
+        float rn, mm, vv;
+        adam_element<ACT>(e, n, raw[e], g_act[e], m[e], v[e], row, first, a, rn, mm, vv);
         raw[e] = rn;
         m[e] = mm;
         v[e] = vv;
         if (act_out) act_out[e] = activate<ACT>(rn);
+    }
+}
+
+// The same update, four elements per thread in 16-byte accesses (every array
+// 16-byte aligned and n a multiple of 4); the arithmetic per element is the
+// scalar kernel's, so the results are identical.
+template <int ACT>
+__global__ __launch_bounds__(256) void adam4_kernel(size_t n, const float4 *__restrict__ g_act, float4 *__restrict__ raw,
+                                                    float4 *__restrict__ m, float4 *__restrict__ v,
+                                                    float4 *__restrict__ act_out, int row, int first, AdamArgs a)
+{
+    const size_t n4 = n / 4;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n4; q += (size_t)gridDim.x * blockDim.x) {
+        const float4 r4 = raw[q], g4 = g_act[q], m4 = m[q], v4 = v[q];
+        const float rr[4] = {r4.x, r4.y, r4.z, r4.w}, gg[4] = {g4.x, g4.y, g4.z, g4.w};
+        const float mi[4] = {m4.x, m4.y, m4.z, m4.w}, vi[4] = {v4.x, v4.y, v4.z, v4.w};
+        float rn[4], mm[4], vv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) adam_element<ACT>(4 * q + j, n, rr[j], gg[j], mi[j], vi[j], row, first, a, rn[j], mm[j], vv[j]);
+        raw[q] = make_float4(rn[0], rn[1], rn[2], rn[3]);
+        m[q] = make_float4(mm[0], mm[1], mm[2], mm[3]);
+        v[q] = make_float4(vv[0], vv[1], vv[2], vv[3]);
+        if (act_out)
+            act_out[q] = make_float4(activate<ACT>(rn[0]), activate<ACT>(rn[1]), activate<ACT>(rn[2]),
+                                     activate<ACT>(rn[3]));
     }
 }
 
@@ -286,6 +319,13 @@ void launch_adam(hipStream_t st, size_t n, const float *g, float *raw, float *m,
                  int first, const AdamArgs &a)
 {
     if (n == 0) return;
+    auto al = [](const void *p) { return ((uintptr_t)p & 15u) == 0; };
+    if (n % 4 == 0 && al(g) && al(raw) && al(m) && al(v) && (!act || al(act))) {
+        const size_t blocks = std::min<size_t>((n / 4 + 255) / 256, 8192);
+        hipLaunchKernelGGL(adam4_kernel<ACT>, dim3((unsigned)blocks), dim3(256), 0, st, n, (const float4 *)g,
+                           (float4 *)raw, (float4 *)m, (float4 *)v, (float4 *)act, row, first, a);
+        return;
+    }
     const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
     hipLaunchKernelGGL(adam_kernel<ACT>, dim3((unsigned)blocks), dim3(256), 0, st, n, g, raw, m, v, act, row, first,
                        a);
