@@ -85,3 +85,36 @@ def test_identity_when_nothing_passes():
     assert np.array_equal(src, np.arange(25))
     np.testing.assert_array_equal(pts, s.points.astype(np.float64))
     np.testing.assert_array_equal(sh, s.sh)
+
+
+def test_decisions_agree_with_float64_wherever_rounding_cannot_decide():
+    """The oracle decides in float32 in the kernel's operation order; this pin
+    shares neither.  Decisions are recomputed in float64 from the definitions
+    (radius about the point mean, opacity, mean statistic) on random scenes
+    with thresholds placed inside the value distributions, and must agree on
+    every convex whose values sit farther from a threshold than float32
+    rounding can move them (relative 1e-5)."""
+    rng = np.random.default_rng(4711)
+    n = 20000
+    s = scenes.convexes_around(rng, scenes.uniform_centres(rng, n), 6, 0)
+    s.opacity[:] = rng.uniform(0.0, 0.1, n).astype(np.float32)
+    accum = rng.uniform(0, 2e-5, n).astype(np.float32)
+    denom = rng.integers(0, 4, n).astype(np.float32)
+    P = s.points.astype(np.float64)
+    r64 = np.linalg.norm(P - P.mean(axis=1, keepdims=True), axis=2).max(axis=1)
+    o64 = s.opacity.astype(np.float64)
+    size_max = float(np.median(r64))
+    opacity_min, thr = 0.03, 4e-6
+    with np.errstate(divide="ignore", invalid="ignore"):
+        mean64 = np.where(denom > 0, accum.astype(np.float64) / np.maximum(denom, 1), 0.0)
+    prune64 = (o64 < opacity_min) | (r64 > size_max)
+    split64 = (denom > 0) & (mean64 > thr)
+    want = np.where(prune64, D.PRUNE, np.where(split64, D.SPLIT, D.KEEP))
+    got = D.classify(s, accum, denom, opacity_min, size_max, thr)
+    rel = 1e-5
+    clear = (np.abs(o64 - opacity_min) > rel * opacity_min) & (np.abs(r64 - size_max) > rel * size_max) & \
+        ((denom == 0) | (np.abs(mean64 - thr) > rel * thr))
+    assert clear.sum() > 0.99 * n
+    assert np.array_equal(got[clear], want[clear]), np.nonzero(got[clear] != want[clear])[0][:10]
+    # every outcome occurs, so each comparison is exercised
+    assert all((want == c).sum() > 1000 for c in (D.PRUNE, D.KEEP, D.SPLIT))
