@@ -2,7 +2,8 @@
 
 Each served image must equal the same view rendered alone by the plain path
 (bit-identical: a batch evaluates every pixel exactly like a single view),
-whatever batch it landed in; admission and queue limits return their codes.
+whatever batch it landed in, and match the FP64 oracle within 1e-4 (one image
+of each scene and resolution); admission and queue limits return their codes.
 """
 import numpy as np
 import pytest
@@ -22,17 +23,23 @@ def R():
     r.close()
 
 
-def two_scenes():
-    from paper_2411_14974_amd.binding import DeviceScene
+def host_scenes():
     out = []
     for i, n in enumerate((8000, 20000)):
         rng = np.random.default_rng(5000 + i)
-        out.append(DeviceScene.from_scene(scenes.convexes_around(rng, scenes.gmm_centres(rng, n), 6, 3), "cuda:0"))
+        out.append(scenes.convexes_around(rng, scenes.gmm_centres(rng, n), 6, 3))
     return out
 
 
+def two_scenes():
+    from paper_2411_14974_amd.binding import DeviceScene
+    return [DeviceScene.from_scene(s, "cuda:0") for s in host_scenes()]
+
+
 def test_served_equals_alone_in_the_mix(R):
+    import oracle
     from paper_2411_14974_amd.binding import make_params
+    host = host_scenes()
     ds = two_scenes()
     R.serve_start(workers=3, max_batch=6, start_paused=True)
     try:
@@ -55,6 +62,17 @@ def test_served_equals_alone_in_the_mix(R):
             alone, _ = R.forward(ds[s], cam, make_params())
             torch.cuda.synchronize()
             assert torch.equal(out, alone)
+        # served images against the FP64 oracle: both scenes, every resolution
+        seen = {}
+        for s, cam, out, _ in reqs:
+            seen.setdefault((s, cam.width, cam.height), []).append((cam, out))
+        assert len(seen) == 6, sorted(seen)
+        for (s, w, h), lst in sorted(seen.items()):
+            cam, out = lst[0]
+            ref, _, _ = oracle.render(host[s], cam, mode=oracle.MODE_MATCHED)
+            err = float(np.abs(out.cpu().numpy() - ref).max())
+            print(f"[serve] scene {s} {w}x{h}: max |served - oracle| {err:.2e}", flush=True)
+            assert err <= 1e-4
         # while requests run, more arrive and join later batches
         more = []
         for i in range(30):
