@@ -63,6 +63,7 @@ def lib():
         L.orc_preprocess.argtypes = [vp, vp, dbl, vp]
         L.orc_render.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
         L.orc_backward.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_backward_magnitude.argtypes = [vp, vp, vp, i32, vp, vp, dbl] + [vp] * 10
         L.orc_tile_candidates.argtypes = [vp, vp, dbl, i32, i32, i32, vp, i32]
         L.orc_sh_basis.argtypes = [i32, vp, vp, vp]
         L.orc_order.argtypes = [i32, vp, vp]
@@ -140,18 +141,43 @@ def render(scene, cam, mode=MODE_MATCHED, pixels=None, eps_alpha=EPS_ALPHA, t_mi
 def backward(scene, cam, dl_drgb, mode=MODE_MATCHED, pixels=None, eps_alpha=EPS_ALPHA, t_min=T_MIN,
              bg=(0.0, 0.0, 0.0)):
     """Gradient of sum(dl_drgb * C) w.r.t. (points, delta, sigma, opacity, sh), FP64."""
+    b, camv, parv, npix, pp, g = _backward_args(scene, cam, dl_drgb, mode, pixels, eps_alpha, t_min, bg)
+    out = _grad_arrays(b)
+    rc = lib().orc_backward(C.byref(b.s), _ptr(camv), _ptr(parv), npix, pp, _ptr(g),
+                            *(_ptr(out[k]) for k in GRAD_NAMES))
+    assert rc == 0
+    return out
+
+
+def backward_magnitude(scene, cam, dl_drgb, mode=MODE_MATCHED, pixels=None, eps_alpha=EPS_ALPHA, t_min=T_MIN,
+                       bg=(0.0, 0.0, 0.0), tau=1e-3):
+    """(magnitude, ambiguous): per gradient element, the sum of |product| over
+    everything the chain rule adds into it, and the same sum over the pairs
+    whose matched-mode skip/stop decision lies within relative tau of its
+    threshold.  Scales for judging another evaluation of backward()."""
+    b, camv, parv, npix, pp, g = _backward_args(scene, cam, dl_drgb, mode, pixels, eps_alpha, t_min, bg)
+    m, a = _grad_arrays(b), _grad_arrays(b)
+    rc = lib().orc_backward_magnitude(C.byref(b.s), _ptr(camv), _ptr(parv), npix, pp, _ptr(g), tau,
+                                      *(_ptr(m[k]) for k in GRAD_NAMES), *(_ptr(a[k]) for k in GRAD_NAMES))
+    assert rc == 0
+    return m, a
+
+
+GRAD_NAMES = ("points", "delta", "sigma", "opacity", "sh")
+
+
+def _grad_arrays(b):
+    return {"points": np.zeros_like(b.points), "delta": np.zeros_like(b.delta), "sigma": np.zeros_like(b.sigma),
+            "opacity": np.zeros_like(b.opacity), "sh": np.zeros_like(b.sh)}
+
+
+def _backward_args(scene, cam, dl_drgb, mode, pixels, eps_alpha, t_min, bg):
     b = _Bound(scene)
     camv, parv = cam_array(cam), par_array(mode, eps_alpha, t_min, bg)
     p, pp = _pix(pixels)
     npix = cam.width * cam.height if p is None else p.shape[0]
     g = np.ascontiguousarray(dl_drgb, dtype=np.float64).reshape(npix, 3)
-    gp = np.zeros_like(b.points)
-    gd, gs, go = np.zeros_like(b.delta), np.zeros_like(b.sigma), np.zeros_like(b.opacity)
-    gsh = np.zeros_like(b.sh)
-    rc = lib().orc_backward(C.byref(b.s), _ptr(camv), _ptr(parv), npix, pp, _ptr(g), _ptr(gp), _ptr(gd), _ptr(gs),
-                            _ptr(go), _ptr(gsh))
-    assert rc == 0
-    return {"points": gp, "delta": gd, "sigma": gs, "opacity": go, "sh": gsh}
+    return b, camv, parv, npix, pp, g
 
 
 def tile_candidates(scene, cam, tile, tx, ty, eps_alpha=EPS_ALPHA):

@@ -73,6 +73,18 @@ static double legendre_deriv(int l, int m, double z)
     return s;
 }
 
+/* Sum of the absolute values of the monomials of legendre_deriv at z. */
+static double legendre_deriv_magnitude(int l, int m, double z)
+{
+    double s = 0.0;
+    for (int k = 0; 2 * k <= l; ++k) {
+        int p = l - 2 * k;
+        if (p < m) continue;
+        s += choose(l, k) * choose(2 * l - 2 * k, l) / pow(2.0, l) * (fact(p) / fact(p - m)) * pow(fabs(z), p - m);
+    }
+    return s;
+}
+
 /* (x + i y)^m */
 static void cpow_xy(double x, double y, int m, double *re, double *im)
 {
@@ -115,6 +127,27 @@ void orc_sh_basis(int deg, const double *dir, double *Y, double *dY)
             if (dY) { dY[3 * idx] = g[0]; dY[3 * idx + 1] = g[1]; dY[3 * idx + 2] = g[2]; }
         }
     }
+}
+
+/* Per basis function of orc_sh_basis, a bound on the sum of the absolute
+ * values of the monomials of its polynomial in (x, y, z) (exact for each of
+ * the two factors, the Legendre part and Re / Im (x + i y)^m): the scale of its rounding error
+ * near a nodal line, where the value itself cancels to zero.  Exact for the
+ * single-monomial functions of degree <= 1. */
+static void sh_basis_magnitude(int deg, const double *dir, double *Ym)
+{
+    double ax = fabs(dir[0]), ay = fabs(dir[1]), z = dir[2];
+    int idx = 0;
+    for (int l = 0; l <= deg; ++l)
+        for (int m = -l; m <= l; ++m, ++idx) {
+            int am = m < 0 ? -m : m;
+            double N = sqrt((2.0 * l + 1.0) / (4.0 * PI) * fact(l - am) / fact(l + am));
+            double f = m == 0 ? N : sqrt(2.0) * N;
+            /* |monomials| of Re (x + i y)^m: even powers of y; of Im: odd ones */
+            double pp = pow(ax + ay, am), pm = pow(ax - ay, am);
+            double xy = m >= 0 ? 0.5 * (pp + pm) : 0.5 * (pp - pm);
+            Ym[idx] = f * legendre_deriv_magnitude(l, am, z) * xy;
+        }
 }
 
 /* ----------------------------------------------------------- preprocess --- */
@@ -310,7 +343,7 @@ int orc_order(int n, const orc_convex *cv, int32_t *order)
 
 typedef struct {
     double L[ORC_MAXK], x[ORC_MAXK], w[ORC_MAXK];
-    double phi, I, omI, alpha, oma;
+    double phi, xmax, lsum, I, omI, alpha, oma; /* phi = xmax + lsum */
 } pair_eval;
 
 /* Eqs. smoothness/sharpness with distance scaling (Supp. B) at pixel point q */
@@ -325,7 +358,9 @@ static void eval_pair(const orc_convex *c, double o, double qx, double qy, pair_
     double sum = 0.0;
     for (int j = 0; j < c->T; ++j) { e->w[j] = exp(e->x[j] - m); sum += e->w[j]; }
     for (int j = 0; j < c->T; ++j) e->w[j] /= sum;
-    e->phi = m + log(sum);
+    e->xmax = m;
+    e->lsum = log(sum);
+    e->phi = m + e->lsum;
     double z = c->sp * e->phi; /* I = Sigmoid(-z) */
     if (z >= 0.0) { double ez = exp(-z); e->I = ez / (1.0 + ez); e->omI = 1.0 / (1.0 + ez); }
     else          { double ez = exp(z);  e->I = 1.0 / (1.0 + ez); e->omI = ez / (1.0 + ez); }
@@ -333,8 +368,14 @@ static void eval_pair(const orc_convex *c, double o, double qx, double qy, pair_
     e->oma = (1.0 - o) + o * e->omI; /* R11 */
 }
 
+/* A listed pair of a pixel: CON_IN when it is a term of the compositing sum;
+ * CON_AMB when its skip or stop decision lies within the relative band tau of
+ * the threshold, so that an evaluation in another precision may take it the
+ * other way. */
+#define CON_IN 1
+#define CON_AMB 2
 typedef struct {
-    int32_t idx;
+    int32_t idx, flags;
     double T;
 } contrib;
 
@@ -343,41 +384,61 @@ typedef struct {
     const orc_convex *cv;
     const int32_t *order;
     int nvis;
-    double eps, tmin, bg[3];
+    double eps, tmin, bg[3], tau;
     int matched;
 } frame;
 
-/* Compositing equation for one pixel; optionally records the contributors. */
+static void list_push(contrib **list, int *cap, int n, int idx, int flags, double T)
+{
+    if (n == *cap) { *cap = *cap ? 2 * *cap : 64; *list = realloc(*list, (size_t)*cap * sizeof(contrib)); }
+    (*list)[n].idx = idx;
+    (*list)[n].flags = flags;
+    (*list)[n].T = T;
+}
+
+/* Compositing equation for one pixel; optionally lists the contributors.
+ * With f->tau > 0 (matched mode) the list also holds the pairs whose decision
+ * is ambiguous at relative precision tau: alpha within tau of eps (taken or
+ * not), and, once T comes within tau of t_min, every later pair until T is
+ * below t_min (1 - tau) for certain.  Those past the walk's own end are listed
+ * without CON_IN and change neither C nor the returned T. */
 static int pixel_forward(const frame *f, double qx, double qy, double *C, double *Tout,
                          contrib **list, int *cap)
 {
-    double T = 1.0;
+    const double thr = f->matched ? f->eps : EXACT_ALPHA;
+    const double tau = f->matched ? f->tau : 0.0;
+    double T = 1.0, Tend = 1.0;
     C[0] = C[1] = C[2] = 0.0;
-    int nc = 0;
+    int nl = 0, stopped = 0, tail = 0;
     pair_eval e;
     for (int a = 0; a < f->nvis; ++a) {
         int idx = f->order[a];
         const orc_convex *c = &f->cv[idx];
         if (qx < c->rect[0] || qx > c->rect[2] || qy < c->rect[1] || qy > c->rect[3]) continue;
         eval_pair(c, f->s->opacity[idx], qx, qy, &e);
-        if (f->matched ? (e.alpha < f->eps) : (e.alpha < EXACT_ALPHA)) continue;
-        for (int ch = 0; ch < 3; ++ch) C[ch] += T * e.alpha * c->rgb[ch];
-        if (list) {
-            if (nc == *cap) { *cap = *cap ? 2 * *cap : 64; *list = realloc(*list, (size_t)*cap * sizeof(contrib)); }
-            (*list)[nc].idx = idx;
-            (*list)[nc].T = T;
-        }
-        ++nc;
+        int taken = e.alpha >= thr;
+        int amb = tau > 0.0 && ((e.alpha >= thr * (1.0 - tau) && e.alpha < thr * (1.0 + tau)) ||
+                                (tail && e.alpha >= thr * (1.0 - tau)));
+        int in = taken && !stopped;
+        if (!in && !amb) continue;
+        if (in)
+            for (int ch = 0; ch < 3; ++ch) C[ch] += T * e.alpha * c->rgb[ch];
+        if (list) list_push(list, cap, nl, idx, (in ? CON_IN : 0) | (amb ? CON_AMB : 0), T);
+        ++nl;
+        if (!taken) continue; /* an ambiguous skip leaves T as it is */
         T *= e.oma;
-        if (f->matched && T < f->tmin) break;
+        if (!stopped && f->matched && T < f->tmin) { stopped = 1; Tend = T; }
+        if (tau > 0.0) tail = T < f->tmin * (1.0 + tau) && T >= f->tmin * (1.0 - tau);
+        if (stopped && !tail) break;
     }
-    for (int ch = 0; ch < 3; ++ch) C[ch] += T * f->bg[ch];
-    *Tout = T;
-    return nc;
+    if (!stopped) Tend = T;
+    for (int ch = 0; ch < 3; ++ch) C[ch] += Tend * f->bg[ch];
+    *Tout = Tend;
+    return nl;
 }
 
-static int setup_frame(const orc_scene *s, const double *cam, const double *par, frame *f, orc_convex **cv,
-                       int32_t **order)
+static int setup_frame(const orc_scene *s, const double *cam, const double *par, double tau, frame *f,
+                       orc_convex **cv, int32_t **order)
 {
     if (!s || !cam || !par || s->k < 3 || s->k > ORC_MAXK || s->deg < 0 || s->deg > 3) return -1;
     f->s = s;
@@ -385,9 +446,10 @@ static int setup_frame(const orc_scene *s, const double *cam, const double *par,
     f->tmin = par[1];
     f->bg[0] = par[2]; f->bg[1] = par[3]; f->bg[2] = par[4];
     f->matched = par[5] != 0.0;
+    f->tau = tau;
     *cv = (orc_convex *)malloc((size_t)(s->n > 0 ? s->n : 1) * sizeof(orc_convex));
     *order = (int32_t *)malloc((size_t)(s->n > 0 ? s->n : 1) * sizeof(int32_t));
-    orc_preprocess(s, cam, f->matched ? f->eps : EXACT_ALPHA, *cv);
+    orc_preprocess(s, cam, f->matched ? f->eps * (1.0 - tau) : EXACT_ALPHA, *cv);
     f->cv = *cv;
     f->nvis = orc_order(s->n, *cv, *order);
     f->order = *order;
@@ -400,7 +462,7 @@ int orc_render(const orc_scene *s, const double *cam, const double *par, int npi
     frame f;
     orc_convex *cv;
     int32_t *order;
-    if (setup_frame(s, cam, par, &f, &cv, &order)) return -1;
+    if (setup_frame(s, cam, par, 0.0, &f, &cv, &order)) return -1;
     const int W = (int)cam[0];
 #pragma omp parallel for schedule(dynamic, 16)
     for (int i = 0; i < npix; ++i) {
@@ -423,17 +485,128 @@ static void atomic_add(double *p, double v)
     *p += v;
 }
 
-int orc_backward(const orc_scene *s, const double *cam, const double *par, int npix, const int32_t *pix,
-                 const double *dl_drgb, double *g_points, double *g_delta, double *g_sigma, double *g_opacity,
-                 double *g_sh)
+/* One term of a gradient sum: the term itself, or its absolute value when the
+ * magnitude of the sum is wanted instead (see orc_backward_magnitude). */
+#define TERM(x) (mag ? fabs(x) : (x))
+
+static void alpha_terms(const orc_convex *c, const pair_eval *e, double o, double qx, double qy, double dLda,
+                        double *A, int mag);
+
+/* Per-pixel products of one (pixel, convex) pair, added into the convex's
+ * accumulator row A (nx[8] ny[8] v[8] dp sp o rgb[3]).  The line
+ * L_j(q) = n_j . (q - v_j) of Eq. signed_distance is differentiated in that
+ * form: dL_j/dn_j = q - v_j, dL_j/dv_j = -n_j. */
+static void pair_terms(const orc_convex *c, const pair_eval *e, double o, double qx, double qy, const double *g,
+                       double T, const double *B, double *A, int mag)
+{
+    /* dC/dalpha_n = T_n (c_n - B_n) */
+    double dLda = 0.0;
+    for (int ch = 0; ch < 3; ++ch)
+        dLda += mag ? fabs(g[ch]) * T * (fabs(c->rgb[ch]) + fabs(B[ch])) : g[ch] * T * (c->rgb[ch] - B[ch]);
+    for (int ch = 0; ch < 3; ++ch) atomic_add(&A[3 * ORC_MAXK + 3 + ch], TERM(g[ch] * T * e->alpha));
+    alpha_terms(c, e, o, qx, qy, dLda, A, mag);
+}
+
+/* The same products, but only those that pass through dL/dalpha (everything
+ * but the colour), for a given dL/dalpha. */
+static void alpha_terms(const orc_convex *c, const pair_eval *e, double o, double qx, double qy, double dLda,
+                        double *A, int mag)
+{
+    atomic_add(&A[3 * ORC_MAXK + 2], TERM(dLda * e->I));
+    double dLdI = dLda * o;
+    double s_ = e->I * e->omI;
+    double dLdphi = dLdI * (-c->sp * s_);
+    /* dphi/dsigma' term; its magnitude counts phi = max + log-sum as |max| + |log-sum| */
+    atomic_add(&A[3 * ORC_MAXK + 1], mag ? fabs(dLdI * s_) * (fabs(e->xmax) + fabs(e->lsum)) : dLdI * (-e->phi * s_));
+    double gdp = 0.0;
+    for (int j = 0; j < c->T; ++j) {
+        const double *vj = c->q[c->hull[j]];
+        double gx = dLdphi * e->w[j];
+        atomic_add(&A[j], TERM(gx * c->dp * (qx - vj[0])));
+        atomic_add(&A[ORC_MAXK + j], TERM(gx * c->dp * (qy - vj[1])));
+        atomic_add(&A[2 * ORC_MAXK + j], TERM(gx * c->dp));
+        gdp += TERM(gx * e->L[j]);
+    }
+    atomic_add(&A[3 * ORC_MAXK], gdp);
+}
+
+/* Chain rule of one convex from its accumulator row to the optimised
+ * parameters (points, delta, sigma, opacity, SH). */
+static void convex_chain(const orc_scene *s, const double *cam, int n, const orc_convex *c, const double *A,
+                         double *gp, double *g_delta, double *g_sigma, double *g_opacity, double *gsh, int mag)
+{
+    const int K = s->k, nc = (s->deg + 1) * (s->deg + 1);
+    const double *R = cam + 6;
+    const double fx = cam[2], fy = cam[3];
+    double gdp = A[3 * ORC_MAXK], gsp = A[3 * ORC_MAXK + 1];
+    *g_opacity = A[3 * ORC_MAXK + 2];
+    *g_delta = c->d * gdp;
+    *g_sigma = c->d * gsp;
+    double gd = s->delta[n] * gdp + s->sigma[n] * gsp;
+
+    /* lines -> hull vertices:  n_j = (e_y, -e_x)/|e|,  e = v_{j+1} - v_j */
+    double gq[ORC_MAXK][2];
+    memset(gq, 0, sizeof(gq));
+    for (int j = 0; j < c->T; ++j) {
+        int ia = c->hull[j], ib = c->hull[(j + 1) % c->T];
+        const double *a = c->q[ia], *b = c->q[ib];
+        double ex = b[0] - a[0], ey = b[1] - a[1], l = hypot(ex, ey);
+        double tx = ex / l, ty = ey / l;
+        double gv = A[2 * ORC_MAXK + j]; /* dL/dv_j = -gv n_j */
+        double gnx = A[j], gny = A[ORC_MAXK + j];
+        gq[ia][0] += TERM(-gv * c->nx[j]);
+        gq[ia][1] += TERM(-gv * c->ny[j]);
+        /* d n / d e = -(n t^T)/|e| */
+        double sdot = (TERM(gnx * tx) + TERM(gny * ty)) / l;
+        double gex = TERM(-sdot * c->nx[j]), gey = TERM(-sdot * c->ny[j]);
+        gq[ib][0] += gex; gq[ib][1] += gey;
+        gq[ia][0] += TERM(-gex); gq[ia][1] += TERM(-gey);
+    }
+    /* projection and depth -> camera space -> world */
+    for (int k = 0; k < K; ++k) {
+        double X = c->X[k][0], Y = c->X[k][1], Z = c->X[k][2];
+        double gX = gq[k][0] * fx / Z, gY = gq[k][1] * fy / Z;
+        double gZ = (TERM(-gq[k][0] * fx * X) + TERM(-gq[k][1] * fy * Y)) / (Z * Z) + gd / K;
+        for (int r = 0; r < 3; ++r) gp[3 * k + r] = TERM(R[r] * gX) + TERM(R[3 + r] * gY) + TERM(R[6 + r] * gZ);
+    }
+    /* colour -> SH coefficients and view direction -> centre -> points */
+    double Y[16], dY[48], graw[3], gdir[3] = {0, 0, 0};
+    orc_sh_basis(s->deg, c->dir, Y, dY);
+    if (mag) sh_basis_magnitude(s->deg, c->dir, Y);
+    const double *sh = s->sh + (size_t)n * nc * 3;
+    for (int ch = 0; ch < 3; ++ch) graw[ch] = (c->clampmask >> ch & 1) ? 0.0 : A[3 * ORC_MAXK + 3 + ch];
+    for (int i = 0; i < nc; ++i)
+        for (int ch = 0; ch < 3; ++ch) {
+            gsh[3 * i + ch] = TERM(graw[ch] * Y[i]);
+            for (int r = 0; r < 3; ++r) gdir[r] += TERM(graw[ch] * sh[3 * i + ch] * dY[3 * i + r]);
+        }
+    double dd = TERM(c->dir[0] * gdir[0]) + TERM(c->dir[1] * gdir[1]) + TERM(c->dir[2] * gdir[2]);
+    for (int r = 0; r < 3; ++r) {
+        double gc = (gdir[r] + TERM(-c->dir[r] * dd)) / c->camdist;
+        for (int k = 0; k < K; ++k) gp[3 * k + r] += gc / K;
+    }
+}
+
+typedef struct {
+    double *points, *delta, *sigma, *opacity, *sh;
+} grad_out;
+
+/* Gradient of L = sum_pixels dl . C (mag = 0); or (mag = 1), for every output
+ * element, the sum of the absolute values of all the products that the chain
+ * rule adds into it, and, in amb when given, that sum over the products of the
+ * pairs listed as ambiguous at relative precision tau. */
+static int backward_impl(const orc_scene *s, const double *cam, const double *par, int npix, const int32_t *pix,
+                         const double *dl_drgb, grad_out out, grad_out amb, double tau, int mag)
 {
     frame f;
     orc_convex *cv;
     int32_t *order;
-    if (setup_frame(s, cam, par, &f, &cv, &order)) return -1;
+    if (setup_frame(s, cam, par, mag ? tau : 0.0, &f, &cv, &order)) return -1;
     const int N = s->n, K = s->k, W = (int)cam[0];
     const int nc = (s->deg + 1) * (s->deg + 1);
+    const int want_amb = mag && amb.points;
     double *acc = (double *)calloc((size_t)(N > 0 ? N : 1) * NACC, sizeof(double));
+    double *acc_amb = want_amb ? (double *)calloc((size_t)(N > 0 ? N : 1) * NACC, sizeof(double)) : NULL;
 
     /* per pixel: reverse walk over the contributors of the compositing equation */
 #pragma omp parallel
@@ -447,100 +620,78 @@ int orc_backward(const orc_scene *s, const double *cam, const double *par, int n
             if (g[0] == 0.0 && g[1] == 0.0 && g[2] == 0.0) continue;
             int u = pix ? pix[2 * i] : i % W, v = pix ? pix[2 * i + 1] : i / W;
             double qx = u + 0.5, qy = v + 0.5, C[3], Tf;
-            int ncon = pixel_forward(&f, qx, qy, C, &Tf, &list, &cap);
+            int nl = pixel_forward(&f, qx, qy, C, &Tf, &list, &cap);
             double B[3] = {f.bg[0], f.bg[1], f.bg[2]}; /* colour seen behind the current convex */
-            for (int a = ncon - 1; a >= 0; --a) {
-                int idx = list[a].idx;
+            /* sum over the ambiguous pairs behind the current one of
+             * T_m alpha_m (|c_m| + |B_m| + |bg|): taking them or not moves the
+             * colour behind the current pair by at most this over T_{n+1} */
+            double X[3] = {0.0, 0.0, 0.0};
+            for (int a = nl - 1; a >= 0; --a) {
+                int idx = list[a].idx, fl = list[a].flags;
                 double T = list[a].T, o = s->opacity[idx];
                 const orc_convex *c = &cv[idx];
                 eval_pair(c, o, qx, qy, &e);
-                double dLda = 0.0;
-                for (int ch = 0; ch < 3; ++ch) dLda += g[ch] * T * (c->rgb[ch] - B[ch]);
-                double *A = &acc[(size_t)idx * NACC];
-                for (int ch = 0; ch < 3; ++ch) atomic_add(&A[3 * ORC_MAXK + 3 + ch], g[ch] * T * e.alpha);
-                atomic_add(&A[3 * ORC_MAXK + 2], dLda * e.I);
-                double dLdI = dLda * o;
-                double s_ = e.I * e.omI;
-                double dLdphi = dLdI * (-c->sp * s_);
-                atomic_add(&A[3 * ORC_MAXK + 1], dLdI * (-e.phi * s_));
-                double gdp = 0.0;
-                for (int j = 0; j < c->T; ++j) {
-                    double gx = dLdphi * e.w[j];
-                    atomic_add(&A[j], gx * c->dp * qx);
-                    atomic_add(&A[ORC_MAXK + j], gx * c->dp * qy);
-                    atomic_add(&A[2 * ORC_MAXK + j], gx * c->dp);
-                    gdp += gx * e.L[j];
+                if (fl & CON_IN) pair_terms(c, &e, o, qx, qy, g, T, B, &acc[(size_t)idx * NACC], mag);
+                if (want_amb) {
+                    double *Aa = &acc_amb[(size_t)idx * NACC];
+                    if (fl & CON_AMB) pair_terms(c, &e, o, qx, qy, g, T, B, Aa, 1);
+                    if ((fl & CON_IN) && (X[0] > 0.0 || X[1] > 0.0 || X[2] > 0.0)) {
+                        double dLda = 0.0; /* |g| T_n |dB_n|, dB_n = X / (T_n (1 - alpha_n)) */
+                        for (int ch = 0; ch < 3; ++ch) dLda += fabs(g[ch]) * X[ch] / e.oma;
+                        alpha_terms(c, &e, o, qx, qy, dLda, Aa, 1);
+                    }
+                    if (fl & CON_AMB)
+                        for (int ch = 0; ch < 3; ++ch)
+                            X[ch] += T * e.alpha * (fabs(c->rgb[ch]) + fabs(B[ch]) + fabs(f.bg[ch]));
                 }
-                atomic_add(&A[3 * ORC_MAXK], gdp);
-                for (int ch = 0; ch < 3; ++ch) B[ch] = e.alpha * c->rgb[ch] + e.oma * B[ch];
+                if (fl & CON_IN)
+                    for (int ch = 0; ch < 3; ++ch) B[ch] = e.alpha * c->rgb[ch] + e.oma * B[ch];
             }
         }
         free(list);
     }
 
     /* per convex: chain rule to the optimised parameters */
-    const double *R = cam + 6;
-    const double fx = cam[2], fy = cam[3];
 #pragma omp parallel for schedule(static)
     for (int n = 0; n < N; ++n) {
-        double *gp = g_points + (size_t)n * K * 3, *gsh = g_sh + (size_t)n * nc * 3;
-        memset(gp, 0, sizeof(double) * K * 3);
-        memset(gsh, 0, sizeof(double) * nc * 3);
-        g_delta[n] = g_sigma[n] = g_opacity[n] = 0.0;
-        const orc_convex *c = &cv[n];
-        if ((c->status & 0xff) != ORC_VISIBLE) continue;
-        const double *A = &acc[(size_t)n * NACC];
-        double gdp = A[3 * ORC_MAXK], gsp = A[3 * ORC_MAXK + 1];
-        g_opacity[n] = A[3 * ORC_MAXK + 2];
-        g_delta[n] = c->d * gdp;
-        g_sigma[n] = c->d * gsp;
-        double gd = s->delta[n] * gdp + s->sigma[n] * gsp;
-
-        /* lines -> hull vertices:  n = (e_y, -e_x)/|e|,  off = -n . a */
-        double gq[ORC_MAXK][2];
-        memset(gq, 0, sizeof(gq));
-        for (int j = 0; j < c->T; ++j) {
-            int ia = c->hull[j], ib = c->hull[(j + 1) % c->T];
-            const double *a = c->q[ia], *b = c->q[ib];
-            double ex = b[0] - a[0], ey = b[1] - a[1], l = hypot(ex, ey);
-            double tx = ex / l, ty = ey / l;
-            double goff = A[2 * ORC_MAXK + j];
-            double gnx = A[j] - goff * a[0], gny = A[ORC_MAXK + j] - goff * a[1];
-            gq[ia][0] -= goff * c->nx[j];
-            gq[ia][1] -= goff * c->ny[j];
-            /* d n / d e = -(n t^T)/|e| */
-            double sdot = (gnx * tx + gny * ty) / l;
-            double gex = -sdot * c->nx[j], gey = -sdot * c->ny[j];
-            gq[ib][0] += gex; gq[ib][1] += gey;
-            gq[ia][0] -= gex; gq[ia][1] -= gey;
-        }
-        /* projection and depth -> camera space -> world */
-        for (int k = 0; k < K; ++k) {
-            double X = c->X[k][0], Y = c->X[k][1], Z = c->X[k][2];
-            double gX = gq[k][0] * fx / Z, gY = gq[k][1] * fy / Z;
-            double gZ = -(gq[k][0] * fx * X + gq[k][1] * fy * Y) / (Z * Z) + gd / K;
-            for (int r = 0; r < 3; ++r) gp[3 * k + r] = R[r] * gX + R[3 + r] * gY + R[6 + r] * gZ;
-        }
-        /* colour -> SH coefficients and view direction -> centre -> points */
-        double Y[16], dY[48], graw[3], gdir[3] = {0, 0, 0};
-        orc_sh_basis(s->deg, c->dir, Y, dY);
-        const double *sh = s->sh + (size_t)n * nc * 3;
-        for (int ch = 0; ch < 3; ++ch) graw[ch] = (c->clampmask >> ch & 1) ? 0.0 : A[3 * ORC_MAXK + 3 + ch];
-        for (int i = 0; i < nc; ++i)
-            for (int ch = 0; ch < 3; ++ch) {
-                gsh[3 * i + ch] = graw[ch] * Y[i];
-                for (int r = 0; r < 3; ++r) gdir[r] += graw[ch] * sh[3 * i + ch] * dY[3 * i + r];
-            }
-        double dd = c->dir[0] * gdir[0] + c->dir[1] * gdir[1] + c->dir[2] * gdir[2];
-        for (int r = 0; r < 3; ++r) {
-            double gc = (gdir[r] - c->dir[r] * dd) / c->camdist;
-            for (int k = 0; k < K; ++k) gp[3 * k + r] += gc / K;
+        for (int w = 0; w < 1 + want_amb; ++w) {
+            grad_out o = w ? amb : out;
+            double *gp = o.points + (size_t)n * K * 3, *gsh = o.sh + (size_t)n * nc * 3;
+            memset(gp, 0, sizeof(double) * K * 3);
+            memset(gsh, 0, sizeof(double) * nc * 3);
+            o.delta[n] = o.sigma[n] = o.opacity[n] = 0.0;
+            const orc_convex *c = &cv[n];
+            if ((c->status & 0xff) != ORC_VISIBLE) continue;
+            const double *A = &(w ? acc_amb : acc)[(size_t)n * NACC];
+            convex_chain(s, cam, n, c, A, gp, &o.delta[n], &o.sigma[n], &o.opacity[n], gsh, mag);
         }
     }
     free(acc);
+    free(acc_amb);
     free(cv);
     free(order);
     return 0;
+}
+#undef TERM
+
+int orc_backward(const orc_scene *s, const double *cam, const double *par, int npix, const int32_t *pix,
+                 const double *dl_drgb, double *g_points, double *g_delta, double *g_sigma, double *g_opacity,
+                 double *g_sh)
+{
+    grad_out out = {g_points, g_delta, g_sigma, g_opacity, g_sh}, none = {0};
+    return backward_impl(s, cam, par, npix, pix, dl_drgb, out, none, 0.0, 0);
+}
+
+int orc_backward_magnitude(const orc_scene *s, const double *cam, const double *par, int npix, const int32_t *pix,
+                           const double *dl_drgb, double tau, double *m_points, double *m_delta, double *m_sigma,
+                           double *m_opacity, double *m_sh, double *a_points, double *a_delta, double *a_sigma,
+                           double *a_opacity, double *a_sh)
+{
+    grad_out m = {m_points, m_delta, m_sigma, m_opacity, m_sh}, a = {a_points, a_delta, a_sigma, a_opacity, a_sh};
+    if (!m_points || !m_delta || !m_sigma || !m_opacity || !m_sh) return -1;
+    if (a_points && (!a_delta || !a_sigma || !a_opacity || !a_sh)) return -1;
+    if (!(tau >= 0.0 && tau < 1.0)) return -1;
+    return backward_impl(s, cam, par, npix, pix, dl_drgb, m, a, tau, 1);
 }
 
 /* ------------------------------------------------------ tile candidates --- */

@@ -87,6 +87,25 @@ int orc_backward(const orc_scene *s, const double *cam, const double *par,
                  double *g_points, double *g_delta, double *g_sigma,
                  double *g_opacity, double *g_sh);
 
+/* Conditioning of orc_backward, for a parity check of an evaluation in
+ * another precision or summation order (test use):
+ *   m_*: per output element, the sum of the absolute values of all the
+ *        products the chain rule adds into it (colour differences c - B
+ *        counted as |c| + |B|).  Rounding moves a sum by a small multiple of
+ *        the unit roundoff times this magnitude; a gradient that cancels (|g|
+ *        much smaller than m) has no better relative accuracy than that.
+ *   a_*: (optional, NULL to skip) the same sums over the pairs whose matched-
+ *        mode decision is within the relative band tau of its threshold:
+ *        alpha within tau of eps_alpha, or after T came within tau of t_min.
+ *        Another precision may keep or drop exactly those pairs.
+ * Returns -1 on bad arguments (tau outside [0, 1), a NULL m_* array). */
+int orc_backward_magnitude(const orc_scene *s, const double *cam, const double *par,
+                           int npix, const int32_t *pix, const double *dl_drgb, double tau,
+                           double *m_points, double *m_delta, double *m_sigma,
+                           double *m_opacity, double *m_sh,
+                           double *a_points, double *a_delta, double *a_sigma,
+                           double *a_opacity, double *a_sh);
+
 /* Ids of the convexes whose alpha reaches eps_alpha at some pixel of a tile;
  * returns the count (ids are written up to cap). */
 int orc_tile_candidates(const orc_scene *s, const double *cam, double eps_alpha,

@@ -406,3 +406,77 @@ def test_backward_sparse_pixels_equal_full(orc):
     b = orc.backward(scene, cam, g_full[sel], pixels=pix)
     for k in a:
         np.testing.assert_allclose(a[k], b[k], rtol=1e-9, atol=1e-13)
+
+
+def test_backward_magnitude_bounds_every_split_of_the_sum(orc):
+    """The magnitude of a gradient element is the sum of |term| over the chain
+    rule's products, so (triangle inequality) it bounds |g| and the sum over
+    pixels of |g from that pixel alone|; it is additive over disjoint pixel
+    sets, homogeneous in dl/dC, and equals |g| where a single product makes the
+    element (opacity and SH of a lone convex seen through one pixel)."""
+    rng = np.random.default_rng(16)
+    sc = fd_scene(rng, n=4)
+    cam = Camera(16, 16, 40.0, 40.0, 8.0, 8.0)
+    bg = (0.1, 0.2, 0.3)
+    sel = rng.choice(256, 24, replace=False)
+    pix = np.stack([sel % 16, sel // 16], 1)
+    w = rng.normal(size=(24, 3))
+    M = orc.backward_magnitude(sc, cam, w, mode=orc.MODE_EXACT, bg=bg, pixels=pix)[0]
+    g = orc.backward(sc, cam, w, mode=orc.MODE_EXACT, bg=bg, pixels=pix)
+    per = [orc.backward(sc, cam, w[i:i + 1], mode=orc.MODE_EXACT, bg=bg, pixels=pix[i:i + 1]) for i in range(24)]
+    Mper = [orc.backward_magnitude(sc, cam, w[i:i + 1], mode=orc.MODE_EXACT, bg=bg, pixels=pix[i:i + 1])[0]
+            for i in range(24)]
+    M2 = orc.backward_magnitude(sc, cam, -2.0 * w, mode=orc.MODE_EXACT, bg=bg, pixels=pix)[0]
+    for k in M:
+        assert np.all(M[k] >= 0)
+        assert np.all(M[k] >= np.abs(g[k]) * (1 - 1e-12))
+        split = sum(np.abs(p[k]) for p in per)
+        assert np.all(M[k] >= split * (1 - 1e-12)), k
+        np.testing.assert_allclose(sum(m[k] for m in Mper), M[k], rtol=1e-12, atol=1e-300)
+        np.testing.assert_allclose(M2[k], 2.0 * M[k], rtol=1e-14, atol=0)
+        # some element really cancels: the bound is not |g| everywhere
+        assert np.any(M[k] > 1.5 * np.abs(g[k]))
+    # a single product: one convex, one pixel inside it, black background
+    one = Scene(*(getattr(sc, f)[:1] for f in ("points", "delta", "sigma", "opacity", "sh")))
+    px = np.array([[8, 8]])
+    dl = np.array([[0.7, -0.4, 0.2]])
+    g1 = orc.backward(one, cam, dl, mode=orc.MODE_EXACT, pixels=px)
+    M1 = orc.backward_magnitude(one, cam, dl, mode=orc.MODE_EXACT, pixels=px)[0]
+    assert g1["opacity"][0] != 0
+    # degree <= 1 basis functions are single monomials; higher ones are bounded
+    np.testing.assert_allclose(M1["sh"][:, :4], np.abs(g1["sh"][:, :4]), rtol=1e-14, atol=0)
+    assert np.all(M1["sh"] >= np.abs(g1["sh"]) * (1 - 1e-14))
+    dl_pos = np.array([[0.7, 0.0, 0.0]])
+    g1 = orc.backward(one, cam, dl_pos, mode=orc.MODE_EXACT, pixels=px)
+    M1 = orc.backward_magnitude(one, cam, dl_pos, mode=orc.MODE_EXACT, pixels=px)[0]
+    np.testing.assert_allclose(M1["opacity"], np.abs(g1["opacity"]), rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("which", ["eps", "tmin"])
+def test_backward_threshold_allowance_covers_moved_thresholds(orc, which):
+    """The ambiguity sums bound what a different decision near a threshold can
+    do: moving eps_alpha or t_min anywhere inside the band (1 +- tau) changes
+    every gradient element by at most its ambiguity sum (plus the second-order
+    change of the other pairs' T and B, far inside 1e-5 of the magnitude); with
+    tau = 0 nothing is ambiguous."""
+    scene, cam = config1(variant=7, n=1000)
+    rng = np.random.default_rng(17)
+    H, W = cam.height, cam.width
+    dl = rng.normal(size=(H * W, 3))
+    eps, tmin, tau = orc.EPS_ALPHA, orc.T_MIN, 0.3
+    if which == "tmin":
+        tmin = 0.05  # a t_min that deep lists reach, so that the stop decides
+    g0 = orc.backward(scene, cam, dl, eps_alpha=eps, t_min=tmin)
+    M, A = orc.backward_magnitude(scene, cam, dl, eps_alpha=eps, t_min=tmin, tau=tau)
+    _, A0 = orc.backward_magnitude(scene, cam, dl, eps_alpha=eps, t_min=tmin, tau=0.0)
+    assert all(np.all(A0[k] == 0) for k in A0)
+    moved_any = False
+    for f in (1 - 0.9 * tau, 1 - 0.3 * tau, 1 + 0.3 * tau, 1 + 0.9 * tau):
+        kw = {"eps_alpha": eps * f, "t_min": tmin} if which == "eps" else {"eps_alpha": eps, "t_min": tmin * f}
+        g1 = orc.backward(scene, cam, dl, **kw)
+        for k in g0:
+            d = np.abs(g1[k] - g0[k])
+            moved_any |= bool(np.any(d > 0))
+            assert np.all(d <= A[k] + 1e-5 * M[k] + 1e-300), (which, f, k, float(np.max(d - A[k])))
+    assert moved_any
+    assert any(np.any(A[k] > 0) for k in A)
