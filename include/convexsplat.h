@@ -149,6 +149,28 @@ int cs_destroy(cs_ctx *ctx);
 int cs_render_forward(cs_ctx *ctx, const cs_scene *scene, const cs_camera *cam, const cs_params *params,
                       float *out_rgb, cs_fwd_state **state, void *hip_stream);
 
+/* Allocation-free forward render, for callers that cannot allocate device
+ * memory (tight serving loops, harnesses that forbid hipMalloc): what
+ * cs_render_forward computes with state = NULL, with every buffer of the pass
+ * carved from one static device array of CS_NOALLOC_SCRATCH_BYTES that each
+ * device holds from its first cs_create until the process ends.  The call
+ * makes no device allocation or free; like cs_render_forward it waits for the
+ * 4-byte pair count (read into pinned memory made by cs_create), so it cannot
+ * be captured into a graph.
+ *   out_rgb: [height][width][3] device, written.  Stream-ordered on hip_stream.
+ *   Limits: the per-convex buffers (about 250 B per convex), the per-tile and
+ *   per-pixel ones (about 30 B per pixel) and the (tile, convex) pairs (16 B
+ *   each plus sort temporaries) must fit the array: 1M convexes at 1920x1080
+ *   with about 9M pairs do.  Beyond it: CS_ENOMEM with the sizes in
+ *   cs_last_error; a pair count found too large after the pass ran also
+ *   returns CS_ENOMEM, and out_rgb is then unspecified.
+ *   Every context on a device shares that device's array, which keeps the last
+ *   call's contents: calls that overlap on one device (other streams, threads
+ *   or contexts) race and their results are undefined. */
+#define CS_NOALLOC_SCRATCH_BYTES ((size_t)512 << 20)
+int cs_render_forward_noalloc(cs_ctx *ctx, const cs_scene *scene, const cs_camera *cam, const cs_params *params,
+                              float *out_rgb, void *hip_stream);
+
 /* Backward render: gradient of sum(dl_drgb * rgb) with respect to points,
  * delta, sigma, opacity and SH (paper Sec. 3.3 optimised parameters), through
  * every step of the forward pass ("fully differentiable", Sec. 3.2).

@@ -26,7 +26,7 @@ EXPORTED = (
     "cs_timing_read", "cs_render_forward_batch", "cs_render_backward_batch", "cs_batch_check", "cs_autotune",
     "cs_serve_start", "cs_serve_resume", "cs_serve_stop", "cs_scene_register", "cs_scene_unregister",
     "cs_serve_submit", "cs_serve_wait", "cs_serve_get_stats", "cs_densify_accumulate", "cs_densify",
-    "cs_adam_step", "cs_ssim_loss_grad", "cs_init_from_points",
+    "cs_adam_step", "cs_ssim_loss_grad", "cs_init_from_points", "cs_render_forward_noalloc",
 )
 # storage formats of the scene arrays (cs_scene.dtype)
 DTYPE_F32, DTYPE_F16, DTYPE_BF16 = 0, 1, 2
@@ -181,6 +181,7 @@ def lib():
         L.cs_destroy.argtypes = [vp]
         L.cs_render_forward.argtypes = [vp, vp, vp, vp, vp, C.POINTER(vp), vp]
         L.cs_render_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.cs_render_forward_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
         L.cs_state_release.argtypes = [vp, vp]
         L.cs_state_stats.argtypes = [vp, vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
         L.cs_timing_read.argtypes = [vp, vp, vp, C.c_int]
@@ -353,6 +354,17 @@ class Renderer:
                                        C.byref(st) if want_state else None, _stream_handle(dev)))
         state = FwdState(self, st.value, scene, camS, params) if want_state else None
         return out, state
+
+    def forward_noalloc(self, scene: DeviceScene, cam, out: torch.Tensor, params: Params | None = None):
+        """cs_render_forward_noalloc into the caller's out [H][W][3] float32."""
+        camS = cam if isinstance(cam, Camera) else make_camera(cam)
+        params = params or make_params()
+        if out.dtype != torch.float32 or not out.is_contiguous() or tuple(out.shape) != (camS.height, camS.width, 3):
+            raise ValueError("out must be a contiguous float32 [height][width][3] tensor")
+        sS = scene.struct()
+        _check(lib().cs_render_forward_noalloc(self.ctx, C.byref(sS), C.byref(camS), C.byref(params), out.data_ptr(),
+                                               _stream_handle(scene.points.device)))
+        return out
 
     def backward(self, state: FwdState, dl_drgb: torch.Tensor, grads=None):
         scene = state.scene

@@ -76,10 +76,17 @@ int ilog2_ceil(uint64_t v)
 
 // -------------------------------------------------------- frame buffers ----
 
+// Device memory of the allocation-free forward entry point: one copy per
+// device that loads the library, held until the process ends.  In host code
+// the name only stands for the symbol: cs_create looks up each device's
+// address of it (cs_ctx::scratch), and only that address reaches kernels.
+static __device__ __align__(256) uint8_t scratch[CS_NOALLOC_SCRATCH_BYTES];
+
 namespace cs {
 
 int Frame::alloc(void **p, size_t bytes)
 {
+    if (fixed) return fail(CS_ENOMEM, "internal: allocation in an allocation-free frame");
     bytes = std::max<size_t>(bytes, 256);
     hipError_t e = hipMallocAsync(p, bytes, st);
     if (e != hipSuccess) return fail(CS_ENOMEM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
@@ -194,6 +201,9 @@ int Frame::init(int n_, int K_, int deg_, int V_, size_t tiles, size_t pix, hipS
 int Frame::ensure_pairs(size_t m)
 {
     if (m <= cap_pairs && pt) return CS_OK;
+    if (fixed)
+        return fail(CS_ENOMEM, "%zu (tile, convex) pairs exceed the %zu that fit the allocation-free scratch", m,
+                    cap_pairs);
     for (void *p : {(void *)pt, (void *)pi, (void *)pt_alt, (void *)pi_alt, (void *)hist})
         if (p) release_buffer(p);
     cap_pairs = std::max<size_t>(m, 1);
@@ -216,7 +226,79 @@ int Frame::ensure_pairs(size_t m)
 int Frame::ensure_acc()
 {
     if (acc) return CS_OK;
+    if (fixed) return fail(CS_EINVAL, "internal: backward on an allocation-free frame");
     return alloc((void **)&acc, cap_inst * acc_stride(K) * 4);
+}
+
+// One-view frame whose buffers are carved, 256-byte aligned, from `bytes` of
+// device memory at `base` instead of allocated: the instance, tile and pixel
+// buffers at their exact sizes, and the pair buffers (with the sort
+// temporaries sized for them) as large as the rest allows.  CS_ENOMEM when the
+// fixed part leaves no room for pairs.
+int Frame::bind(uint8_t *base, size_t bytes, int n_, int K_, int deg_, size_t tiles, size_t pix, hipStream_t s)
+{
+    fixed = true;
+    n = n_; K = K_; deg = deg_; V = 1; st = s;
+    ninst = (size_t)n;
+    cap_inst = std::max<size_t>(ninst, 1);
+    cap_tiles = std::max<size_t>(tiles, 1);
+    cap_pix = std::max<size_t>(pix, 1);
+    counter_words = CNT_STATUS + scan_status_words((uint32_t)cap_inst);
+    size_t off = 0;
+    auto carve = [&](size_t b) {
+        off = (off + 255) & ~(size_t)255;
+        uint8_t *p = base + off;
+        off += std::max<size_t>(b, 256);
+        return (void *)p;
+    };
+    d_frame = (FrameHeader *)carve(VIEW_TABLE_BYTES);
+    records = (uint8_t *)carve(cap_inst * rec_stride(K));
+    keys = (uint32_t *)carve(cap_inst * 4);
+    ids = (uint32_t *)carve(cap_inst * 4);
+    keys_alt = (uint32_t *)carve(cap_inst * 4);
+    ids_alt = (uint32_t *)carve(cap_inst * 4);
+    counts_sorted = (uint32_t *)carve(cap_inst * 4);
+    offsets = (uint32_t *)carve(cap_inst * 4);
+    hullpk = (uint32_t *)carve(cap_inst * 4);
+    bins = (uint4 *)carve(cap_inst * 16);
+    bins_sorted = (uint4 *)carve(cap_inst * 16);
+    ranges = (uint2 *)carve(cap_tiles * 8);
+    ord_k = (uint32_t *)carve(cap_tiles * 4);
+    ord_v = (uint32_t *)carve(cap_tiles * 4);
+    ord_k_alt = (uint32_t *)carve(cap_tiles * 4);
+    ord_v_alt = (uint32_t *)carve(cap_tiles * 4);
+    pixstate = (uint2 *)carve(cap_pix * 8);
+    counters = (uint32_t *)carve(counter_words * 4);
+    evalcount = (unsigned long long *)carve((size_t)EVAL_SLOTS * 16);
+    acc = nullptr;
+    // pairs: four arrays of cap_pairs words, then the sort temporaries
+    const int tile_bits = std::max(1, ilog2_ceil(cap_tiles));
+    auto need = [&](size_t m) {
+        const size_t hw = std::max({sort_temp_words((uint32_t)cap_inst, 32, 8),
+                                    sort_temp_words((uint32_t)std::max<size_t>(m, 1), tile_bits, 4),
+                                    sort_temp_words((uint32_t)cap_tiles, 16, 8)});
+        return 4 * (((m * 4 + 255) & ~(size_t)255) + 256) + hw * 4 + 512;
+    };
+    const size_t fixed_bytes = (off + 255) & ~(size_t)255;
+    if (fixed_bytes + need(1) > bytes)
+        return fail(CS_ENOMEM, "%d convexes and %zu pixels need %zu MiB of the allocation-free scratch's %zu MiB before any pair",
+                    n, pix, (fixed_bytes + need(1)) >> 20, bytes >> 20);
+    size_t lo = 1, hi = std::min<size_t>((bytes - fixed_bytes) / 16, 0xFFFFFFFFu);
+    while (lo < hi) { // largest pair capacity that fits
+        const size_t mid = lo + (hi - lo + 1) / 2;
+        if (fixed_bytes + need(mid) <= bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    cap_pairs = lo;
+    pt = (uint32_t *)carve(cap_pairs * 4);
+    pi = (uint32_t *)carve(cap_pairs * 4);
+    pt_alt = (uint32_t *)carve(cap_pairs * 4);
+    pi_alt = (uint32_t *)carve(cap_pairs * 4);
+    const size_t hw = std::max({sort_temp_words((uint32_t)cap_inst, 32, 8), sort_temp_words((uint32_t)cap_pairs, tile_bits, 4),
+                                sort_temp_words((uint32_t)cap_tiles, 16, 8)});
+    hist = (uint32_t *)carve(hw * 4);
+    if (off > bytes) return fail(CS_ENOMEM, "internal: allocation-free scratch layout overflows");
+    return CS_OK;
 }
 
 // Upload the view table through the context's ring of pinned staging buffers.
@@ -672,7 +754,20 @@ int cs_create(int device, size_t hbm_budget_bytes, cs_ctx **out)
     c->device = device;
     c->budget = hbm_budget_bytes;
     int r = c->ring.init();
+    if (!r) { // this device's copy of the allocation-free scratch, and the frame carved from it
+        void *sp = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) r = fail(CS_EHIP, "scratch symbol address: %s", hipGetErrorString(e));
+        c->scratch = (uint8_t *)sp;
+    }
+    if (!r) {
+        c->noalloc = new Frame;
+        c->noalloc->ring = &c->ring;
+        if (hipEventCreateWithFlags(&c->noalloc->mcount_ev, hipEventDisableTiming) != hipSuccess)
+            r = fail(CS_EHIP, "event creation failed");
+    }
     if (r) {
+        delete c->noalloc;
         delete c;
         return r;
     }
@@ -694,6 +789,8 @@ int cs_destroy(cs_ctx *ctx)
         delete F;
     }
     ctx->free_frames.clear();
+    if (ctx->noalloc) ctx->noalloc->st = nullptr;
+    delete ctx->noalloc; // owns no memory: its buffers lie in the static scratch
     (void)hipDeviceSynchronize();
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     for (auto &p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
@@ -748,6 +845,31 @@ int cs_render_forward(cs_ctx *ctx, const cs_scene *sc, const cs_camera *cam, con
         release_frame(ctx, F);
     }
     return CS_OK;
+}
+
+int cs_render_forward_noalloc(cs_ctx *ctx, const cs_scene *sc, const cs_camera *cam, const cs_params *prm,
+                              float *out_rgb, void *hip_stream)
+{
+    if (!ctx) return fail(CS_EINVAL, "ctx is NULL");
+    CS_TRY(check_scene(sc));
+    CS_TRY(check_camera(cam));
+    if (!out_rgb) return fail(CS_EINVAL, "out_rgb is NULL");
+    RenderArgs ra;
+    Knobs kn;
+    CS_TRY(render_args(prm, ra, kn));
+    if (!ctx->noalloc || !ctx->scratch) return fail(CS_EINVAL, "context has no allocation-free scratch");
+    CS_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    ViewPlan vp;
+    CS_TRY(plan_views(1, cam, kn.tile, &out_rgb, nullptr, vp));
+    Frame &F = *ctx->noalloc;
+    CS_TRY(F.bind(ctx->scratch, CS_NOALLOC_SCRATCH_BYTES, sc->n, sc->k, sc->sh_degree, vp.hdr.total_tiles,
+                  (size_t)vp.hdr.total_pix, st));
+    CS_TRY(F.upload_views(vp.hdr, vp.views.data()));
+    StageTimer tm(ctx, st, false); // stage timing would create events: never here
+    // pair buffers are bound at the scratch's capacity, so the tail runs on the
+    // device-side count at once and a count beyond it comes back as CS_ENOMEM
+    return enqueue_forward(ctx, F, sc, ra, kn, false, 1.0, tm);
 }
 
 int cs_render_backward(cs_ctx *ctx, const cs_scene *sc, const cs_camera *cam, const cs_params *prm,

@@ -71,7 +71,10 @@ struct Frame {
     HostRing *ring = nullptr;
     hipEvent_t ready = nullptr; // recorded when the frame is handed back to the context's cache
 
+    bool fixed = false; // buffers carved from caller memory (bind): nothing is allocated or freed
+
     int init(int n, int K, int deg, int V, size_t tiles, size_t pix, hipStream_t st, HostRing *ring);
+    int bind(uint8_t *base, size_t bytes, int n, int K, int deg, size_t tiles, size_t pix, hipStream_t st);
     int init_async_readback();
     int alloc(void **p, size_t bytes);
     void release_buffer(void *p);
@@ -104,6 +107,10 @@ struct cs_ctx {
     cs::Server *server = nullptr;
     // frames of finished eager calls, reused by later ones
     std::vector<cs::Frame *> free_frames;
+    // allocation-free forward: this device's address of the library's static
+    // scratch array, and the frame whose buffers are carved from it per call
+    uint8_t *scratch = nullptr;
+    cs::Frame *noalloc = nullptr;
 };
 
 struct cs_fwd_state {
