@@ -43,9 +43,21 @@ def workload(name):
     return scene, cam, target, desc
 
 
-def stage_work(stage, n, m, K, T_mean, deg, stats, npix):
-    """Algorithmic bytes (or VALU lane-ops) of one launch of a stage."""
+def pair_cost(stage, T):
+    """VALU lane-operations of one full (pixel, convex) pair evaluation with T
+    hull lines, a transcendental counted as 4 full-rate operations:
+    forward (T + 3) transcendentals, 2T FP64 FMA, 3T + 12 FP32 operations;
+    backward (T + 4) transcendentals, 2T FP64 FMA, 12T + 30 FP32 operations."""
+    if stage == "render_fwd":
+        return 4 * (T + 3) + 2 * T + (3 * T + 12)
+    return 4 * (T + 4) + 2 * T + (12 * T + 30)
+
+
+def stage_work(stage, n, m, K, deg, cnt):
+    """Algorithmic bytes (or VALU lane-operations) of one launch of a stage;
+    cnt: the device work counters of the step (cs_state_counters)."""
     nc = (deg + 1) ** 2
+    T_mean = cnt["sum_T_full"] / max(cnt["full_bwd"], 1)
     rec = 48 + 24 * T_mean  # header + the T hull lines written
     if stage == "preprocess":  # read points, delta, sigma, opacity, SH; write record, key, id, binning record, hull
         return "hbm", n * (12 * K + 12 + 12 * nc + rec + 4 + 4 + 16 + 4)
@@ -59,16 +71,25 @@ def stage_work(stage, n, m, K, T_mean, deg, stats, npix):
         return "hbm", m * (4 + 2 * 16)
     if stage == "ranges":
         return "hbm", m * 4
-    if stage == "render_fwd":  # per tested pair: 2T DFMA + (T-1) max + 4; full pairs: 7T + 24 (4 per transcendental)
-        ev, full = stats["evaluated"], stats["full"]
-        return "alu", ev * (3 * T_mean + 4) + full * (7 * T_mean + 24)
-    if stage == "render_bwd":  # same evaluation plus the gradient (12T + 30) on the full pairs
-        ev, full = stats["evaluated"], stats["full"]
-        return "alu", ev * (3 * T_mean + 4) + full * (7 * T_mean + 24 + 12 * T_mean + 30)
+    if stage == "render_fwd":  # full pairs x the forward per-pair cost at the measured mean hull size
+        return "alu", cnt["full"] * pair_cost(stage, T_mean)
+    if stage == "render_bwd":
+        return "alu", cnt["full_bwd"] * pair_cost(stage, T_mean)
     if stage == "preprocess_bwd":  # read accumulators, points, delta, sigma, SH, hull; write gradients
         acc = 4 * (3 * K + 6)
         return "hbm", n * (acc + 12 * K + 8 + 12 * nc + 4 + 12 * K + 12 + 12 * nc)
     return "hbm", 0
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_batched(steps, warmup):
@@ -137,6 +158,14 @@ def bench_batched(steps, warmup):
     }
 
 
+def window_mean(st0, st1, key):
+    """Mean of a per-request server statistic over the requests finished
+    between two snapshots (the server reports running means)."""
+    n0 = st0["completed"] + st0["failed"]
+    n1 = st1["completed"] + st1["failed"]
+    return (st1[key] * n1 - st0[key] * n0) / max(n1 - n0, 1)
+
+
 def bench_serving(rates, duration, max_batch=4, workers=2):
     """Poisson request streams against 4 resident scenes (0.2/0.5/1/2 M convexes), forward only:
     continuous batching (worker streams taking batches of one scene's queued requests) vs plain FIFO one
@@ -195,7 +224,11 @@ def bench_serving(rates, duration, max_batch=4, workers=2):
             nr = (st["completed"] + st["failed"]) - (st0["completed"] + st0["failed"])
             rows.append({"rate_rps": rate, "requests": len(ids), "p50_ms": float(np.percentile(lat, 50)),
                          "p99_ms": float(np.percentile(lat, 99)), "mpixels_per_s": pix / wall / 1e6,
-                         "mean_batch": nr / nb if nb else 0.0})
+                         "mean_batch": nr / nb if nb else 0.0,
+                         "frames_created": st["frames_created"] - st0["frames_created"],
+                         "mean_queue_ms": window_mean(st0, st, "mean_queue_ms"),
+                         "mean_run_ms": window_mean(st0, st, "mean_run_ms"),
+                         "frame_gb": st["frame_bytes"] / 1e9})
         R.serve_stop()
         out["modes"][mode] = rows
     R.close()
@@ -356,6 +389,76 @@ def counter_traffic(stage, workload):
     return None
 
 
+def bench_small_configs(steps, warmup, with_oracle):
+    """The two smaller workloads: 1k convexes at 128x128, forward only, and
+    100k convexes at 1297x840, forward + L1 backward; GPU Mpixels/s of the plain
+    renderer, and the FP64 oracle's Mpixels/s (1k: the whole frame; 100k: a
+    seeded 2 % pixel sample, extrapolated like the main CPU baseline)."""
+    import torch
+
+    from paper_2411_14974_amd import scenes
+    from paper_2411_14974_amd.binding import DeviceScene, Renderer, make_params
+    dev = torch.device("cuda:0")
+    R = Renderer(0)
+    out = {}
+    for name in ("c1", "c2"):
+        if name == "c1":
+            scene, cam = scenes.config1()
+            target = None
+        else:
+            scene, cam, target = scenes.config2()
+        W, H = cam.width, cam.height
+        ds = DeviceScene.from_scene(scene, dev)
+        rgb = torch.empty((H, W, 3), device=dev)
+        dl = torch.empty_like(rgb)
+        tgt = torch.from_numpy(target).to(dev) if target is not None else None
+        grads = {k: torch.empty_like(getattr(ds, k)) for k in ("points", "delta", "sigma", "opacity", "sh")}
+
+        def step():
+            if tgt is None:
+                R.forward(ds, cam, make_params(), out=rgb)
+                return None
+            o, st = R.forward(ds, cam, make_params(), want_state=True, out=rgb)
+            R.l1_loss_grad(o, tgt, grad=dl)
+            R.backward(st, dl, grads=grads)
+            return st
+
+        def run(k):
+            held = []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(k):
+                held.append(step())
+                if len(held) > 2 and held[0] is not None:
+                    held.pop(0).release()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for s_ in held:
+                if s_ is not None:
+                    s_.release()
+            return (t1 - t0) * 1e3 / k
+
+        run(max(warmup, 3))
+        ms = run(steps)
+        d = {"workload": ("1k convexes K=6 SH0, 128x128, forward only" if name == "c1"
+                          else "100k convexes K=6 SH3, 1297x840, fwd+bwd (L1)"),
+             "ms_per_step": ms, "mpixels_per_s": W * H / (ms / 1e3) / 1e6}
+        if with_oracle:
+            import oracle
+            if name == "c1":
+                t0 = time.perf_counter()
+                oracle.render(scene, cam, mode=oracle.MODE_MATCHED)
+                d["oracle_mpixels_per_s"] = W * H / (time.perf_counter() - t0) / 1e6
+                d["oracle_sample"] = "whole frame, forward"
+            else:
+                cb = cpu_baseline(scene, cam, target, (W * H) // 50)
+                d["oracle_mpixels_per_s"] = cb["value"]
+                d["oracle_sample"] = cb["sample"]
+        out[name] = d
+    R.close()
+    return out
+
+
 def cpu_baseline(scene, cam, target, sample):
     """The FP64 oracle, as it stands, on a seeded pixel sample of the workload."""
     import oracle
@@ -378,7 +481,7 @@ def cpu_baseline(scene, cam, target, sample):
     full = 2 * t_pre + W * H * per_pixel
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
-        "value": W * H / full / 1e6, "unit": "Mpixels/s", "cores": cores, "kind": "oracle",
+        "value": W * H / full / 1e6, "unit": "Mpixels/s", "cores": cores, "kind": "oracle", "cpu": cpu_model(),
         "sample": (f"{sample} seeded pixels of the same frame, fwd+bwd, matched mode; full-frame time "
                    f"extrapolated as 2 x per-convex pass ({t_pre:.2f} s) + W*H x per-pixel cost "
                    f"({per_pixel * 1e3:.3f} ms); measured {t_pre + t_fwd + t_bwd:.1f} s of CPU work"),
@@ -388,16 +491,18 @@ def cpu_baseline(scene, cam, target, sample):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--cpu-sample", type=int, default=163840)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
-    ap.add_argument("--forms", default="plain,light,train,densify,batched,serving",
-                    help="comma list of plain, light (16-bit scene), train, densify, batched, serving")
-    ap.add_argument("--serve-rates", default="50,200,800,2000", help="request rates (req/s) of the serving sweep")
-    ap.add_argument("--serve-seconds", type=float, default=1.5)
+    ap.add_argument("--forms", default="plain,configs,light,train,densify,batched,serving",
+                    help="comma list of plain, configs (the 1k and 100k workloads), light (16-bit scene), train, "
+                         "densify, batched, serving")
+    ap.add_argument("--serve-rates", default="50,100,200,500,1000,2000,4000",
+                    help="request rates (req/s) of the serving sweep (4000: beyond both modes' capacity)")
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--serve-max-batch", type=int, default=4, help="requests per batch of continuous batching")
     ap.add_argument("--serve-workers", type=int, default=2, help="worker streams of continuous batching")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -430,19 +535,25 @@ def main():
         return st
 
     def run(params):
+        """Exactly args.steps steps between two synchronisations; per-step HIP
+        events on the call stream give the step-time distribution."""
         states = []
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        ev[0].record()
+        for i in range(args.steps):
             states.append(step(params))
+            ev[i + 1].record()
             if len(states) > 2:
                 states.pop(0).release()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        stats = states[-1].stats()
+        cnt = states[-1].counters()
         for s in states:
             s.release()
-        return (t1 - t0) * 1e3 / args.steps, stats
+        per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+        return (t1 - t0) * 1e3 / args.steps, cnt, per
 
     # warm-up in the timed loop's pattern (two states held), so that the
     # context's frame cache reaches its steady state before timing
@@ -454,17 +565,16 @@ def main():
     for s in held:
         s.release()
     # the step time: no stage events in the stream
-    ms, stats = run(plain_params)
+    ms, cnt, per_step = run(plain_params)
     # per-stage kernel times: the same steps again, with HIP events around each stage
     R.timing(reset=True)
-    ms_timed, _ = run(timed_params)
+    ms_timed, _, _ = run(timed_params)
     timing = R.timing(reset=True)
 
     n, K, deg = scene.n, scene.k, scene.deg
-    T_mean = 4.92 if K == 6 else float(K)
     avg = {s: (t / c if c else 0.0) for s, (t, c) in timing.items()}
     dom = max(avg, key=avg.get)
-    bound, work = stage_work(dom, n, stats["pairs"], K, T_mean, deg, stats, W * H)
+    bound, work = stage_work(dom, n, cnt["pairs"], K, deg, cnt)
     sec = avg[dom] / 1e3
     if bound == "hbm":
         achieved, peak, unit = work / sec / 1e9, HBM_PEAK_GBS, "GB/s"
@@ -473,7 +583,13 @@ def main():
     if args.stages:
         for s in avg:
             print(f"  {s:15s} {avg[s]:8.3f} ms", file=sys.stderr)
-        print(f"  pairs {stats['pairs']}, evaluated {stats['evaluated']}, full {stats['full']}", file=sys.stderr)
+        print(f"  counters {cnt}", file=sys.stderr)
+    work_counts = {
+        "pairs": cnt["pairs"], "tested": cnt["tested"], "full": cnt["full"], "full_bwd": cnt["full_bwd"],
+        "T_mean": cnt["sum_T_full"] / max(cnt["full_bwd"], 1),
+        "wave_evals": cnt["wave_evals"],
+        "lane_utilisation": cnt["full_bwd"] / max(64 * cnt["wave_evals"], 1),
+    }
 
     line = {
         "metric": "Mpixels/s fwd+bwd @1M convexes 1080p vs plain; p50/p99 served frame latency",
@@ -490,9 +606,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "convexes": n, "k": K, "sh_degree": deg, "width": W, "height": H,
                    "form": "plain (one view per launch)", "tile": 16},
+        "step_ms": {"p10": float(np.percentile(per_step, 10)), "p50": float(np.median(per_step)),
+                    "p90": float(np.percentile(per_step, 90)), "steps": int(per_step.size)},
         "stages_ms": {s: round(v, 4) for s, v in avg.items()},
         "ms_per_step_with_stage_events": ms_timed,
-        "work": {"pairs": stats["pairs"], "evaluated": stats["evaluated"], "full": stats["full"]},
+        "work": work_counts,
         "roofline": {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                      "frac": achieved / peak, "traffic": counter_traffic(dom, args.workload)},
     }
@@ -503,6 +621,8 @@ def main():
         torch.cuda.synchronize()
     R.close()
     forms = set(args.forms.split(","))
+    if "configs" in forms:
+        line["other_configs"] = bench_small_configs(args.steps, args.warmup, not args.no_cpu_baseline)
     if "light" in forms:
         line["light_16bit"] = bench_light(scene, cam, target, args.steps, args.warmup, ms)
     if "train" in forms:

@@ -232,6 +232,25 @@ int cs_autotune(cs_ctx *ctx, const cs_scene *scene, int32_t n_views, const cs_ca
 int cs_state_stats(cs_ctx *ctx, const cs_fwd_state *state, int64_t *n_pairs, int64_t *n_evaluated,
                    int64_t *n_full);
 
+/* All work counters of the last forward (and backward, when one ran) on a
+ * state, summed over the compositing workgroups (synchronises the stream).
+ * They price the compositing kernels against their roofline (the per-pair
+ * work of Sec. 3.1 Eqs. smoothness/sharpness, T lines per pair):
+ *   pairs       (tile, convex) pairs binned
+ *   tested      (pixel, convex) pairs of the forward walk inside the record's pixel box
+ *   full        of those, the pairs past the max-line test (LogSumExp and sigmoid evaluated)
+ *   full_bwd    the same count in the backward walk, which visits the same pairs
+ *               (0 before a backward)
+ *   sum_T_full  sum of the hull size T over the backward's full pairs (mean T =
+ *               sum_T_full / full_bwd)
+ *   wave_evals  wavefront-level record evaluations of the backward walk (some lane
+ *               full); lane utilisation = full_bwd / (64 wave_evals).  The forward
+ *               walk makes the same evaluations; counting there would slow it. */
+typedef struct {
+    int64_t pairs, tested, full, full_bwd, sum_T_full, wave_evals;
+} cs_work_counters;
+int cs_state_counters(cs_ctx *ctx, const cs_fwd_state *state, cs_work_counters *out);
+
 /* Debug/parity: per-convex preprocess results copied to host memory `out`,
  * an array of n cs_debug_convex records (synchronises the stream). */
 typedef struct {
@@ -259,10 +278,16 @@ int cs_debug_tile_lists(cs_ctx *ctx, const cs_fwd_state *state, int32_t *ranges,
  * only).  Requests queue on the host; worker threads, each with its own HIP
  * stream, take every queued request of the oldest request's scene (up to
  * max_batch, arrival order) as one batched forward pass as soon as a worker
- * is free and the batch's estimated device memory fits the budget left by
- * the batches in flight.  Requests that arrive while others run join the
- * next batch, and batches on different workers overlap on the device.  A
- * request's latency runs from cs_serve_submit to the completion of its batch
+ * is free.  Requests that arrive while others run join the next batch, and
+ * batches on different workers overlap on the device.
+ * Device memory: the passes run on frames (per-pass buffers) that the server
+ * owns and its workers share; a batch reuses an idle frame of its scene,
+ * grown when the batch exceeds it, so a steady request mix allocates nothing.
+ * Every frame, idle or in use, counts against the budget: a batch that may
+ * need more memory than the budget leaves waits, after the least recently
+ * used idle frames of other scenes are freed, until running batches end (a
+ * batch always runs when none other does).
+ * A request's latency runs from cs_serve_submit to the completion of its batch
  * (host clock).  Its image equals a lone cs_render_forward of the same view. */
 typedef struct {
     int32_t workers;        /* concurrent batches (streams), >= 1 */
@@ -276,8 +301,12 @@ typedef struct {
 typedef struct {
     int64_t submitted, completed, failed, batches;
     double mean_batch;      /* requests per batch */
-    size_t peak_bytes;      /* largest estimated device memory in flight */
+    size_t peak_bytes;      /* largest device memory held by the server's frames */
     int64_t queued, running;
+    int64_t frames_created; /* frames allocated (or re-created larger) so far */
+    size_t frame_bytes;     /* device memory held by the frames now */
+    double mean_queue_ms;   /* mean time from submit to the start of the request's batch */
+    double mean_run_ms;     /* mean time from the start of the batch to its completion */
 } cs_serve_stats;
 
 /* Start the request loop of a context (one server per context). */

@@ -26,7 +26,7 @@ EXPORTED = (
     "cs_timing_read", "cs_render_forward_batch", "cs_render_backward_batch", "cs_batch_check", "cs_autotune",
     "cs_serve_start", "cs_serve_resume", "cs_serve_stop", "cs_scene_register", "cs_scene_unregister",
     "cs_serve_submit", "cs_serve_wait", "cs_serve_get_stats", "cs_densify_accumulate", "cs_densify",
-    "cs_adam_step", "cs_ssim_loss_grad", "cs_init_from_points", "cs_render_forward_noalloc",
+    "cs_adam_step", "cs_ssim_loss_grad", "cs_init_from_points", "cs_render_forward_noalloc", "cs_state_counters",
 )
 # storage formats of the scene arrays (cs_scene.dtype)
 DTYPE_F32, DTYPE_F16, DTYPE_BF16 = 0, 1, 2
@@ -149,7 +149,8 @@ class ServeConfig(C.Structure):
 class ServeStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64), ("batches", C.c_int64),
                 ("mean_batch", C.c_double), ("peak_bytes", C.c_size_t), ("queued", C.c_int64),
-                ("running", C.c_int64)]
+                ("running", C.c_int64), ("frames_created", C.c_int64), ("frame_bytes", C.c_size_t),
+                ("mean_queue_ms", C.c_double), ("mean_run_ms", C.c_double)]
 
 
 class Tuning(C.Structure):
@@ -184,6 +185,7 @@ def lib():
         L.cs_render_forward_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
         L.cs_state_release.argtypes = [vp, vp]
         L.cs_state_stats.argtypes = [vp, vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+        L.cs_state_counters.argtypes = [vp, vp, vp]
         L.cs_timing_read.argtypes = [vp, vp, vp, C.c_int]
         L.cs_debug_preprocess.argtypes = [vp, vp, vp, vp, vp, vp]
         L.cs_debug_tile_lists.argtypes = [vp, vp, vp, i64, vp, i64]
@@ -288,6 +290,10 @@ class DeviceScene:
                       self.sigma.data_ptr(), self.opacity.data_ptr(), self.sh.data_ptr(), _DTYPES[self.dtype])
 
 
+class WorkCounters(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("pairs", "tested", "full", "full_bwd", "sum_T_full", "wave_evals")]
+
+
 class FwdState:
     """Owns a cs_fwd_state; released when garbage-collected or released explicitly."""
 
@@ -298,6 +304,12 @@ class FwdState:
         pairs, evals, full = C.c_int64(), C.c_int64(), C.c_int64()
         _check(lib().cs_state_stats(self.renderer.ctx, self.handle, C.byref(pairs), C.byref(evals), C.byref(full)))
         return {"pairs": pairs.value, "evaluated": evals.value, "full": full.value}
+
+    def counters(self):
+        """cs_state_counters as a dict (forward and, once run, backward work)."""
+        w = WorkCounters()
+        _check(lib().cs_state_counters(self.renderer.ctx, self.handle, C.byref(w)))
+        return {name: getattr(w, name) for name, _ in WorkCounters._fields_}
 
     def tile_lists(self):
         cams = self.cam if isinstance(self.cam, (list, tuple)) else [self.cam]

@@ -88,6 +88,11 @@ constexpr int NUM_QUEUES = 8; // one work queue per XCD
 // workgroup of the persistent grid stores its sums in a slot of its own and
 // readers add the slots (same-address atomics from every wavefront serialise)
 constexpr int EVAL_SLOTS = 16384;
+// fields of a slot: pairs tested (pixel in the record's box), pairs past the
+// max-line test (full), the sum of the hull size T over the full pairs, and
+// wavefront-level record evaluations (some lane full); the backward's slots
+// follow the forward's EVAL_SLOTS
+enum : int { EV_TESTED = 0, EV_FULL = 1, EV_SUM_T = 2, EV_WAVES = 3, EVAL_FIELDS = 4 };
 
 // Device counters of one frame (u32 words).
 // Per-instance binning record (16 bytes): the tile rectangle, tx0 | ty0 << 16

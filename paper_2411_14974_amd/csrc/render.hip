@@ -21,6 +21,7 @@
 // workgroup's waves in LDS, and leave as one float atomic add per
 // (convex, value) and workgroup.
 #include <algorithm>
+#include <cstddef>
 #include <mutex>
 #include <unordered_map>
 #include <utility>
@@ -44,6 +45,21 @@ template <int K> struct PairEval {
     float x2[K]; // x2_j rounded to float
 };
 
+// Runs the statements with the compile-time constant NLL equal to the wave-
+// uniform hull size TV (3..K; records in tile lists always have T >= 3).
+#define CS_NL_CASE(n, K, ...) \
+    case n:                   \
+        if constexpr (n <= K) { \
+            constexpr int NLL = n; \
+            __VA_ARGS__;      \
+        }                     \
+        break;
+#define CS_DISPATCH_NL(K, TV, ...)                                                                               \
+    switch (TV) {                                                                                                \
+        CS_NL_CASE(3, K, __VA_ARGS__) CS_NL_CASE(4, K, __VA_ARGS__) CS_NL_CASE(5, K, __VA_ARGS__)                \
+        CS_NL_CASE(6, K, __VA_ARGS__) CS_NL_CASE(7, K, __VA_ARGS__) CS_NL_CASE(8, K, __VA_ARGS__) default: break; \
+    }
+
 // The one evaluation of a (pixel, convex) pair shared by both passes, called
 // by every lane of the wavefront (live: the pixel still takes convexes).
 // Returns whether the pair contributes: the pixel lies in the record's pixel
@@ -57,25 +73,32 @@ template <int K> struct PairEval {
 // round trips; slots past T hold null lines).  The lines are evaluated in FP64; the exponents are taken
 // as differences of the FP32-rounded values (phi already starts from the
 // rounded maximum, and where the sigmoid is sensitive |x2| is small).
-template <int K>
+// NL: the record's hull size T (its line count), a compile-time constant of
+// the caller's dispatch on the wave-uniform T, so that only the hull's lines
+// are read and evaluated.
+template <int K, int NL>
 __device__ __forceinline__ bool eval_pair(const uint8_t *rec, bool live, int u, int y, float pxf, float pyf,
                                           float eps, PairEval<K> &pe, bool &tested, bool &full)
 {
+    static_assert(NL >= 3 && NL <= K, "hull size out of range");
+    // the pixel box first: its test then waits for it alone, with the line
+    // reads still in flight
+    const uint2 box = *reinterpret_cast<const uint2 *>(rec + offsetof(RecHeader, box_u));
     const RecHeader h = *reinterpret_cast<const RecHeader *>(rec);
-    double L[3 * K + 1]; // one spare slot: odd 3K reads into the record's padding
+    double L[3 * NL + 1]; // one spare slot: odd 3 NL reads one double past the last line (still in the record)
     const double2 *l2 = reinterpret_cast<const double2 *>(rec + REC_HEADER);
 #pragma unroll
-    for (int q = 0; q < (3 * K + 1) / 2; ++q) {
+    for (int q = 0; q < (3 * NL + 1) / 2; ++q) {
         const double2 w = l2[q];
         L[2 * q] = w.x;
         L[2 * q + 1] = w.y;
     }
-    tested = live && in_box(h.box_u, h.box_v, u, y);
+    tested = live & in_box(box.x, box.y, u, y); // no short circuit: no branch around the box test
     const double dx = (double)(pxf - h.ox), dy = (double)(pyf - h.oy);
-    double x[K];
+    double x[NL];
     double m = -INFINITY;
 #pragma unroll
-    for (int j = 0; j < K; ++j) { // slots past T hold null lines: no test against T
+    for (int j = 0; j < NL; ++j) {
         x[j] = fma(L[3 * j], dx, fma(L[3 * j + 1], dy, L[3 * j + 2]));
         m = fmax(m, x[j]);
     }
@@ -85,7 +108,7 @@ __device__ __forceinline__ bool eval_pair(const uint8_t *rec, bool live, int u, 
     const float mf = (float)m;
     float s = 0.0f;
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
+    for (int j = 0; j < NL; ++j) {
         const float xf = (float)x[j];
         const float e = __builtin_amdgcn_exp2f(xf - mf);
         pe.e[j] = e;
@@ -290,6 +313,29 @@ __device__ __forceinline__ int find_view(const ViewDesc *__restrict__ views, int
     return lo;
 }
 
+// The workgroup's work counters (per-lane tested / full / hull-size sums and
+// the wavefront's evaluation count, which every lane of a wavefront holds),
+// stored in the workgroup's own slot of EVAL_FIELDS words.
+__device__ __forceinline__ void store_work_counts(unsigned long long *evalcount, unsigned long long *s_ev,
+                                                  uint32_t nevals, uint32_t nfull, uint32_t nsumT, uint32_t nwave)
+{
+    unsigned long long c = nevals, f = nfull, t = nsumT;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        c += __shfl_xor(c, o, 64);
+        f += __shfl_xor(f, o, 64);
+        t += __shfl_xor(t, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&s_ev[EV_TESTED], c);
+        atomicAdd(&s_ev[EV_FULL], f);
+        atomicAdd(&s_ev[EV_SUM_T], t);
+        atomicAdd(&s_ev[EV_WAVES], (unsigned long long)nwave);
+    }
+    __syncthreads();
+    if (threadIdx.x < EVAL_FIELDS) evalcount[EVAL_FIELDS * blockIdx.x + threadIdx.x] = s_ev[threadIdx.x];
+}
+
 } // namespace
 
 // Tiles the forward claims per queue atomic: its per-tile cost is even enough
@@ -312,9 +358,9 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4)))
     __shared__ uint4 lds[BATCH * CH];
     __shared__ uint32_t s_ids[2][BATCH];
     __shared__ uint32_t s_item;
-    __shared__ unsigned long long s_ev[2];
+    __shared__ unsigned long long s_ev[EVAL_FIELDS];
     const int lane = threadIdx.x & 63, wbit = threadIdx.x >> 6;
-    if (threadIdx.x == 0) s_ev[0] = s_ev[1] = 0ull;
+    if (threadIdx.x < EVAL_FIELDS) s_ev[threadIdx.x] = 0ull;
     constexpr int NL = pipe_regs<K, NT, BATCH>();
     u32x4 pre[NL];
     uint32_t idr = 0;
@@ -323,7 +369,10 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4)))
     const uint32_t total_tiles = frame->total_tiles;
     int q = blockIdx.x % NUM_QUEUES, tried = 0;
     uint32_t cnext = 0, cend = 0;
-    uint32_t nevals = 0, nfull = 0; // pairs tested / pairs past the max-line test
+    // work counters: pairs tested / pairs past the max-line test (the hull
+    // sizes and wavefront evaluations of the same pairs are counted by the
+    // backward walk, where they cost less)
+    uint32_t nevals = 0, nfull = 0;
     for (;;) {
         const uint32_t item = next_item<FWD_CHUNK>(counters, total_tiles, q, tried, cnext, cend, &s_item);
         if (item == 0xFFFFFFFFu) break;
@@ -375,7 +424,9 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4)))
                 const uint8_t *rec = reinterpret_cast<const uint8_t *>(&lds[e * CH]);
                 PairEval<K> pe;
                 bool tested, full;
-                const bool hit = eval_pair<K>(rec, !done, u, y, pxf, pyf, ra.eps_alpha, pe, tested, full);
+                // all K line slots (slots past T hold null lines): a dispatch on
+                // T costs the forward more than the null lines it saves
+                const bool hit = eval_pair<K, K>(rec, !done, u, y, pxf, pyf, ra.eps_alpha, pe, tested, full);
                 nevals += tested;
                 nfull += full;
                 if (hit) {
@@ -402,22 +453,79 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4)))
             pixstate[vd.pix_off + pix] = make_uint2((uint32_t)nend, __float_as_uint(Tlast));
         }
     }
-    if (evalcount) { // the workgroup's sums, stored in its own slot
-        unsigned long long c = nevals, f = nfull;
+    if (evalcount) store_work_counts(evalcount, s_ev, nevals, nfull, 0u, 0u);
+}
+
+// Compact per-pair gradient values of a record with NL hull lines: a[NL]
+// b[NL] c[NL] (base-2 line coefficients), sigma', opacity, rgb[3], and
+// sum_j dL/dx2_j x2_j, padded with zeros to a multiple of 4 for the wave sums.
+template <int NL> constexpr int bwd_values() { return 3 * NL + 6; }
+template <int NL> constexpr int bwd_padded() { return (bwd_values<NL>() + 3) & ~3; }
+
+// Slot of compact value qv of a record with T lines in the accumulator row
+// a[K] b[K] c[K] sigma' opacity rgb[3] x2sum.
+template <int K> __device__ __forceinline__ int acc_slot(int qv, int T)
+{
+    return qv < T ? qv : qv < 2 * T ? K + (qv - T) : qv < 3 * T ? 2 * K + (qv - 2 * T) : 3 * K + (qv - 3 * T);
+}
+
+// Backward of one record for the wavefront's pixels: recompute the pair (the
+// forward's decisions, bit for bit), recover T_n, form the pixel's gradient
+// values, sum them over the wavefront and add the four row sums into the
+// record's LDS slot (compact layout, bwd_padded<K>() floats).
+template <int K, int NL>
+__device__ __forceinline__ void bwd_record(const uint8_t *rec, bool live, int u, int y, float pxf, float pyf,
+                                           float eps, float g0, float g1, float g2, float Tlast, float &Tcur,
+                                           bool &first, float &B0, float &B1, float &B2, float *slot, bool &full)
+{
+    constexpr int NP = bwd_padded<NL>();
+    constexpr int Q = NP / 4;
+    PairEval<K> pe;
+    bool tested;
+    const bool contrib = eval_pair<K, NL>(rec, live, u, y, pxf, pyf, eps, pe, tested, full);
+    if (__ballot(contrib) == 0ull) return; // wave-uniform
+    const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
+    // branch-free: a lane that does not contribute takes Tn = 0, which zeroes
+    // all of its values (every pe field is finite)
+    const float Tn = contrib ? (first ? Tlast : Tcur * __builtin_amdgcn_rcpf(pe.oma)) : 0.0f;
+    const float dLda = Tn * (g0 * (h.rgb[0] - B0) + g1 * (h.rgb[1] - B1) + g2 * (h.rgb[2] - B2));
+    const float ta = Tn * pe.alpha;
+    float val[NP];
+    val[3 * NL + 2] = g0 * ta;
+    val[3 * NL + 3] = g1 * ta;
+    val[3 * NL + 4] = g2 * ta;
+    val[3 * NL + 1] = dLda * pe.I;
+    const float dLdz = -dLda * h.opacity * pe.I * pe.omI; // I = Sigmoid(-z), z = sigma' phi
+    val[3 * NL] = dLdz * pe.phi2 * (float)LN2;
+    const float dLdphi2 = dLdz * h.sigma_p * (float)LN2;
+    const float gs = dLdphi2 * pe.inv_sum; // dL/dx2_j = gs e_j (softmax weights)
+    const float dxf = pxf - h.ox, dyf = pyf - h.oy;
+    float gdl = 0.0f;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            c += __shfl_xor(c, o, 64);
-            f += __shfl_xor(f, o, 64);
-        }
-        if ((threadIdx.x & 63) == 0) {
-            atomicAdd(&s_ev[0], c);
-            atomicAdd(&s_ev[1], f);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            evalcount[2 * blockIdx.x] = s_ev[0];
-            evalcount[2 * blockIdx.x + 1] = s_ev[1];
-        }
+    for (int j = 0; j < NL; ++j) {
+        const float gx = gs * pe.e[j];
+        val[j] = gx * dxf;
+        val[NL + j] = gx * dyf;
+        val[2 * NL + j] = gx;
+        gdl = fmaf(gx, pe.x2[j], gdl);
+    }
+    val[3 * NL + 5] = gdl;
+#pragma unroll
+    for (int qv = bwd_values<NL>(); qv < NP; ++qv) val[qv] = 0.0f;
+    if (contrib) {
+        first = false;
+        Tcur = Tn;
+        B0 = fmaf(pe.alpha, h.rgb[0], pe.oma * B0);
+        B1 = fmaf(pe.alpha, h.rgb[1], pe.oma * B1);
+        B2 = fmaf(pe.alpha, h.rgb[2], pe.oma * B2);
+    }
+    // whole-wave sums even when few lanes contribute: lane-by-lane LDS atomics
+    // serialise badly when a record covers the square
+    wave_sums<NP>(val);
+    if ((threadIdx.x & 15) == 0) { // one lane per row adds its quarter of the wave's sums
+        float *dst = slot + ((threadIdx.x & 63) >> 4) * Q;
+#pragma unroll
+        for (int qv = 0; qv < Q; ++qv) atomicAdd(dst + qv, val[qv]);
     }
 }
 
@@ -426,14 +534,12 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
     const FrameHeader *__restrict__ frame, const uint32_t *__restrict__ order, uint32_t *__restrict__ counters,
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ ids,
     const uint8_t *__restrict__ records, RenderArgs ra, const uint2 *__restrict__ pixstate,
-    float *__restrict__ acc)
+    float *__restrict__ acc, unsigned long long *__restrict__ evalcount)
 {
     constexpr int NT = TILE * TILE;
     constexpr int CH = rec_stride(K) / 16;
-    constexpr int NV = acc_values(K); // a[K] b[K] c[K] sigma' o rgb[3] x2-weighted sum
     constexpr int AS = acc_stride(K);
-    constexpr int NP = (NV + 3) & ~3; // padded for the wave sums
-    constexpr int Q = NP / 4;
+    constexpr int NP = bwd_padded<K>(); // LDS slot per batch entry (compact values of the largest hull)
     static_assert(BATCH <= NT, "one id per thread");
     static_assert(BATCH <= 64, "one ballot bit per batch entry");
     __shared__ uint4 lds[BATCH * CH];
@@ -442,13 +548,16 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
     __shared__ float s_acc[BATCH * NP];
     __shared__ int s_maxn;
     __shared__ uint32_t s_item;
+    __shared__ unsigned long long s_ev[EVAL_FIELDS];
     for (int c = threadIdx.x; c < BATCH * NP; c += NT) s_acc[c] = 0.0f;
+    if (threadIdx.x < EVAL_FIELDS) s_ev[threadIdx.x] = 0ull;
     const ViewDesc *views = reinterpret_cast<const ViewDesc *>(frame + 1);
     const int nviews = (int)frame->nviews;
     const uint32_t total_tiles = frame->total_tiles;
     const int lane = threadIdx.x & 63, wbit = threadIdx.x >> 6;
     int q = blockIdx.x % NUM_QUEUES, tried = 0;
     uint32_t cnext = 0, cend = 0;
+    uint32_t nfull = 0, nsumT = 0, nwave = 0;
     for (;;) {
         const uint32_t item = next_item<1>(counters, total_tiles, q, tried, cnext, cend, &s_item);
         if (item == 0xFFFFFFFFu) break;
@@ -495,82 +604,45 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
         for (int hi = maxn; hi > 0; hi -= BATCH) {
             const int lo = max(hi - BATCH, 0);
             const int cnt = hi - lo;
-            uint32_t *cur_ids = s_ids;
             __syncthreads();
-            if ((int)threadIdx.x < cnt) cur_ids[threadIdx.x] = ids[start + lo + threadIdx.x];
+            if ((int)threadIdx.x < cnt) s_ids[threadIdx.x] = ids[start + lo + threadIdx.x];
             __syncthreads();
-            load_records_direct<K, NT>(lds, cur_ids, records, cnt);
+            load_records_direct<K, NT>(lds, s_ids, records, cnt);
             __syncthreads();
             // the wave's records of this batch before its last contributor, back to front
-            const bool meets = lane < min(cnt, wmaxn - lo) &&
-                               square_meets<K>(reinterpret_cast<const uint8_t *>(&lds[min(lane, BATCH - 1) * CH]), su, sv);
+            const uint8_t *mine = reinterpret_cast<const uint8_t *>(&lds[min(lane, BATCH - 1) * CH]);
+            const bool meets = lane < min(cnt, wmaxn - lo) && square_meets<K>(mine, su, sv);
+            const int myT = reinterpret_cast<const RecHeader *>(mine)->T; // lane e: hull size of entry e
             uint64_t M = __ballot(meets);
             while (M) {
                 const int e = 63 - __builtin_clzll(M);
                 M &= ~(1ull << e);
-                const int pos = lo + e;
                 const uint8_t *rec = reinterpret_cast<const uint8_t *>(&lds[e * CH]);
-                PairEval<K> pe;
-                bool tested, full;
-                const bool contrib = eval_pair<K>(rec, pos < nend, u, y, pxf, pyf, ra.eps_alpha, pe, tested, full);
-                if (__ballot(contrib) == 0ull) continue; // wave-uniform
-                const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
-                // branch-free: a lane that does not contribute takes Tn = 0,
-                // which zeroes all of its values (every pe field is finite)
-                const float Tn = contrib ? (first ? Tlast : Tcur * __builtin_amdgcn_rcpf(pe.oma)) : 0.0f;
-                const float dLda = Tn * (g0 * (h.rgb[0] - B0) + g1 * (h.rgb[1] - B1) + g2 * (h.rgb[2] - B2));
-                const float ta = Tn * pe.alpha;
-                float val[NP];
-                val[3 * K + 2] = g0 * ta;
-                val[3 * K + 3] = g1 * ta;
-                val[3 * K + 4] = g2 * ta;
-                val[3 * K + 1] = dLda * pe.I;
-                const float dLdz = -dLda * h.opacity * pe.I * pe.omI; // I = Sigmoid(-z), z = sigma' phi
-                val[3 * K] = dLdz * pe.phi2 * (float)LN2;
-                const float dLdphi2 = dLdz * h.sigma_p * (float)LN2;
-                const float gs = dLdphi2 * pe.inv_sum; // dL/dx2_j = gs e_j (softmax weights)
-                const float dxf = pxf - h.ox, dyf = pyf - h.oy;
-                float gdl = 0.0f;
-#pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    const float gx = gs * pe.e[j];
-                    val[j] = gx * dxf;
-                    val[K + j] = gx * dyf;
-                    val[2 * K + j] = gx;
-                    gdl = fmaf(gx, pe.x2[j], gdl);
-                }
-                val[3 * K + 5] = gdl;
-#pragma unroll
-                for (int qv = NV; qv < NP; ++qv) val[qv] = 0.0f;
-                if (contrib) {
-                    first = false;
-                    Tcur = Tn;
-                    B0 = fmaf(pe.alpha, h.rgb[0], pe.oma * B0);
-                    B1 = fmaf(pe.alpha, h.rgb[1], pe.oma * B1);
-                    B2 = fmaf(pe.alpha, h.rgb[2], pe.oma * B2);
-                }
-                // whole-wave sums even when few lanes contribute: lane-by-lane
-                // LDS atomics serialise badly when a record covers the square
-                wave_sums<NP>(val);
-                if ((lane & 15) == 0) { // one lane per row adds its quarter of the wave's sums
-                    float *dst = &s_acc[e * NP + (lane >> 4) * Q];
-#pragma unroll
-                    for (int qv = 0; qv < Q; ++qv) atomicAdd(dst + qv, val[qv]);
-                }
+                const int Tr = __builtin_amdgcn_readlane(myT, e);
+                const bool live = lo + e < nend;
+                bool full = false;
+                CS_DISPATCH_NL(K, Tr, bwd_record<K, NLL>(rec, live, u, y, pxf, pyf, ra.eps_alpha, g0, g1, g2, Tlast, Tcur,
+                                                         first, B0, B1, B2, &s_acc[e * NP], full));
+                nfull += full;
+                nsumT += full ? (uint32_t)Tr : 0u;
+                nwave += __any(full) ? 1u : 0u;
             }
-            // one global atomic per (entry, value) for the whole workgroup
+            // one global atomic per (entry, value) for the whole workgroup; the
+            // compact values of entry e go to the slots of its hull size
             __syncthreads();
-            for (int c = threadIdx.x; c < cnt * NV; c += NT) {
-                const int e = c / NV, qv = c - e * NV;
-                float *src = &s_acc[e * NP + qv];
+            for (int c = threadIdx.x; c < cnt * NP; c += NT) {
+                const int e = c / NP, qv = c - e * NP;
+                float *src = &s_acc[c];
                 const float a = *src;
                 if (a != 0.0f) {
-                    unsafeAtomicAdd(&acc[(size_t)cur_ids[e] * AS + qv], a);
+                    const int T = reinterpret_cast<const RecHeader *>(&lds[e * CH])->T;
+                    unsafeAtomicAdd(&acc[(size_t)s_ids[e] * AS + acc_slot<K>(qv, T)], a);
                     *src = 0.0f;
                 }
             }
         }
     }
+    if (evalcount) store_work_counts(evalcount, s_ev, 0u, nfull, nsumT, nwave);
 }
 
 // ------------------------------------------------------------- launchers ---
@@ -632,17 +704,22 @@ int launch_render_fwd(hipStream_t st, int K, int tile, const FrameHeader *frame,
     return used;
 }
 
-void launch_render_bwd(hipStream_t st, int K, int tile, const FrameHeader *frame, const uint32_t *order,
-                       uint32_t max_items, uint32_t *counters, const uint2 *ranges, const uint32_t *ids,
-                       const uint8_t *records, const RenderArgs &ra, const uint2 *pixstate, float *acc)
+// Returns the grid size (the number of evalcount slots written).
+int launch_render_bwd(hipStream_t st, int K, int tile, const FrameHeader *frame, const uint32_t *order,
+                      uint32_t max_items, uint32_t *counters, const uint2 *ranges, const uint32_t *ids,
+                      const uint8_t *records, const RenderArgs &ra, const uint2 *pixstate, float *acc,
+                      unsigned long long *evalcount)
 {
-    if (max_items == 0) return;
+    if (max_items == 0) return 0;
+    int used = 0;
     CS_DISPATCH_K(K, CS_DISPATCH_TILE(tile, {
         auto kern = render_bwd_kernel<KK, TT, BBW>;
-        const int grid = std::min<int>(persistent_grid(kern, TT * TT), (int)max_items);
+        const int grid = std::min({persistent_grid(kern, TT * TT), (int)max_items, EVAL_SLOTS});
         hipLaunchKernelGGL(kern, dim3(grid), dim3(TT * TT), 0, st, frame, order, counters, ranges, ids, records, ra,
-                           pixstate, acc);
+                           pixstate, acc, evalcount);
+        used = grid;
     }));
+    return used;
 }
 
 // ------------------------------------------------------------ L1 loss ----

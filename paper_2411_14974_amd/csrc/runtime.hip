@@ -39,8 +39,9 @@ void launch_tile_ranges(hipStream_t, const uint32_t *, uint32_t, const uint32_t 
 int launch_render_fwd(hipStream_t, int, int, const FrameHeader *, const uint32_t *, uint32_t, uint32_t *,
                        const uint2 *, const uint32_t *, const uint8_t *, const RenderArgs &, uint2 *,
                        unsigned long long *);
-void launch_render_bwd(hipStream_t, int, int, const FrameHeader *, const uint32_t *, uint32_t, uint32_t *,
-                       const uint2 *, const uint32_t *, const uint8_t *, const RenderArgs &, const uint2 *, float *);
+int launch_render_bwd(hipStream_t, int, int, const FrameHeader *, const uint32_t *, uint32_t, uint32_t *,
+                      const uint2 *, const uint32_t *, const uint8_t *, const RenderArgs &, const uint2 *, float *,
+                      unsigned long long *);
 hipError_t launch_l1_grad(hipStream_t, const float *, const float *, size_t, float *, float *);
 } // namespace cs
 
@@ -163,13 +164,14 @@ static size_t capacity_class(size_t x)
     return (x + q - 1) / q * q;
 }
 
-int Frame::init(int n_, int K_, int deg_, int V_, size_t tiles, size_t pix, hipStream_t s, HostRing *r)
+int Frame::init(int n_, int K_, int deg_, int V_, size_t tiles, size_t pix, hipStream_t s, HostRing *r,
+                size_t min_inst)
 {
     n = n_; K = K_; deg = deg_; V = V_; st = s; ring = r;
     if (hipEventCreateWithFlags(&mcount_ev, hipEventDisableTiming) != hipSuccess)
         return fail(CS_EHIP, "event creation failed");
     ninst = (size_t)n * V;
-    cap_inst = capacity_class(ninst);
+    cap_inst = capacity_class(std::max(ninst, min_inst));
     cap_tiles = capacity_class(std::max<size_t>(tiles, 1));
     cap_pix = capacity_class(std::max<size_t>(pix, 1));
     const uint32_t ui = (uint32_t)cap_inst;
@@ -193,7 +195,7 @@ int Frame::init(int n_, int K_, int deg_, int V_, size_t tiles, size_t pix, hipS
     CS_A(pixstate, cap_pix * 8);
     counter_words = CNT_STATUS + scan_status_words((uint32_t)cap_inst);
     CS_A(counters, counter_words * 4);
-    CS_A(evalcount, (size_t)EVAL_SLOTS * 16);
+    CS_A(evalcount, (size_t)2 * EVAL_SLOTS * EVAL_FIELDS * 8);
 #undef CS_A
     return CS_OK;
 }
@@ -269,7 +271,7 @@ int Frame::bind(uint8_t *base, size_t bytes, int n_, int K_, int deg_, size_t ti
     ord_v_alt = (uint32_t *)carve(cap_tiles * 4);
     pixstate = (uint2 *)carve(cap_pix * 8);
     counters = (uint32_t *)carve(counter_words * 4);
-    evalcount = (unsigned long long *)carve((size_t)EVAL_SLOTS * 16);
+    evalcount = (unsigned long long *)carve((size_t)2 * EVAL_SLOTS * EVAL_FIELDS * 8);
     acc = nullptr;
     // pairs: four arrays of cap_pairs words, then the sort temporaries
     const int tile_bits = std::max(1, ilog2_ceil(cap_tiles));
@@ -589,8 +591,9 @@ int enqueue_backward(Frame &F, const cs_scene *sc, const cs_grads *g, const Rend
     launch_zero_ranges(st, reinterpret_cast<uint32_t *>(F.acc), F.ninst * acc_stride(F.K), F.counters + CNT_QUEUE,
                        QUEUE_WORDS, nullptr, 0);
     tm.begin();
-    launch_render_bwd(st, F.K, F.tile, F.d_frame, F.order, (uint32_t)F.cap_tiles, F.counters, F.ranges, F.sorted_ids,
-                      F.records, ra, F.pixstate, F.acc);
+    F.eval_slots_bwd = launch_render_bwd(st, F.K, F.tile, F.d_frame, F.order, (uint32_t)F.cap_tiles, F.counters,
+                                         F.ranges, F.sorted_ids, F.records, ra, F.pixstate, F.acc,
+                                         F.evalcount + (size_t)EVAL_SLOTS * EVAL_FIELDS);
     tm.end(CS_STAGE_RENDER_BWD);
     tm.begin();
     launch_preprocess_bwd(st, sc->n, F.V, F.K, F.deg, sc->dtype, sc->points, sc->delta, sc->sigma, sc->sh, F.d_frame,
@@ -1140,27 +1143,55 @@ int cs_autotune(cs_ctx *ctx, const cs_scene *sc, int32_t n_views, const cs_camer
     return CS_OK;
 }
 
+namespace {
+// Sums of the work counters of a frame's last forward and backward passes.
+int read_work_counters(Frame *F, cs_work_counters *w)
+{
+    std::vector<unsigned long long> ev(2 * (size_t)EVAL_SLOTS * EVAL_FIELDS, 0ull);
+    uint32_t cnt[CNT_WORDS];
+    if (F->eval_slots > 0)
+        CS_HIP(hipMemcpyAsync(ev.data(), F->evalcount, (size_t)EVAL_FIELDS * 8 * F->eval_slots,
+                              hipMemcpyDeviceToHost, F->st));
+    if (F->eval_slots_bwd > 0)
+        CS_HIP(hipMemcpyAsync(ev.data() + (size_t)EVAL_SLOTS * EVAL_FIELDS, F->evalcount + (size_t)EVAL_SLOTS * EVAL_FIELDS,
+                              (size_t)EVAL_FIELDS * 8 * F->eval_slots_bwd, hipMemcpyDeviceToHost, F->st));
+    CS_HIP(hipMemcpyAsync(cnt, F->counters, sizeof(cnt), hipMemcpyDeviceToHost, F->st));
+    CS_HIP(hipStreamSynchronize(F->st));
+    if (cnt[CNT_SORT_ERR]) return fail(CS_EHIP, "radix sort: a look-back wait exceeded its bound");
+    std::memset(w, 0, sizeof(*w));
+    w->pairs = cnt[CNT_PAIRS];
+    for (int g = 0; g < F->eval_slots; ++g) {
+        const unsigned long long *e = &ev[(size_t)EVAL_FIELDS * g];
+        w->tested += (int64_t)e[EV_TESTED];
+        w->full += (int64_t)e[EV_FULL];
+    }
+    for (int g = 0; g < F->eval_slots_bwd; ++g) {
+        const unsigned long long *e = &ev[(size_t)EVAL_SLOTS * EVAL_FIELDS + (size_t)EVAL_FIELDS * g];
+        w->full_bwd += (int64_t)e[EV_FULL];
+        w->sum_T_full += (int64_t)e[EV_SUM_T];
+        w->wave_evals += (int64_t)e[EV_WAVES];
+    }
+    return CS_OK;
+}
+} // namespace
+
 int cs_state_stats(cs_ctx *ctx, const cs_fwd_state *s, int64_t *n_pairs, int64_t *n_evaluated, int64_t *n_full)
 {
     if (!ctx || !s || !s->frame) return fail(CS_EINVAL, "ctx or state is NULL");
     CS_HIP(hipSetDevice(ctx->device));
-    Frame *F = s->frame;
-    std::vector<unsigned long long> ev(2 * (size_t)F->eval_slots + 2, 0ull);
-    uint32_t cnt[CNT_WORDS];
-    if (F->eval_slots > 0)
-        CS_HIP(hipMemcpyAsync(ev.data(), F->evalcount, 16 * (size_t)F->eval_slots, hipMemcpyDeviceToHost, F->st));
-    CS_HIP(hipMemcpyAsync(cnt, F->counters, sizeof(cnt), hipMemcpyDeviceToHost, F->st));
-    CS_HIP(hipStreamSynchronize(F->st));
-    if (cnt[CNT_SORT_ERR]) return fail(CS_EHIP, "radix sort: a look-back wait exceeded its bound");
-    unsigned long long tested = 0, full = 0;
-    for (int g = 0; g < F->eval_slots; ++g) {
-        tested += ev[2 * g];
-        full += ev[2 * g + 1];
-    }
-    if (n_pairs) *n_pairs = cnt[CNT_PAIRS];
-    if (n_evaluated) *n_evaluated = (int64_t)tested;
-    if (n_full) *n_full = (int64_t)full;
+    cs_work_counters w;
+    CS_TRY(read_work_counters(s->frame, &w));
+    if (n_pairs) *n_pairs = w.pairs;
+    if (n_evaluated) *n_evaluated = w.tested;
+    if (n_full) *n_full = w.full;
     return CS_OK;
+}
+
+int cs_state_counters(cs_ctx *ctx, const cs_fwd_state *s, cs_work_counters *out)
+{
+    if (!ctx || !s || !s->frame || !out) return fail(CS_EINVAL, "ctx, state or out is NULL");
+    CS_HIP(hipSetDevice(ctx->device));
+    return read_work_counters(s->frame, out);
 }
 
 int cs_timing_read(cs_ctx *ctx, double *ms, int64_t *count, int reset)
@@ -1249,3 +1280,56 @@ int cs_l1_loss_grad(cs_ctx *ctx, const float *rgb, const float *target, int32_t 
 }
 
 } // extern "C"
+
+namespace cs {
+
+int forward_batch_on(cs_ctx *ctx, Frame **Fp, const cs_scene *sc, int n_views, const cs_camera *cams,
+                     const cs_params *prm, float *const *out_rgb, hipStream_t st, bool *created)
+{
+    *created = false;
+    if (!ctx || !Fp) return fail(CS_EINVAL, "ctx or frame slot is NULL");
+    CS_TRY(check_scene(sc));
+    if (n_views < 1 || n_views > MAX_VIEWS) return fail(CS_EINVAL, "n_views = %d outside [1, %d]", n_views, MAX_VIEWS);
+    if (!cams || !out_rgb) return fail(CS_EINVAL, "cameras or outputs are NULL");
+    RenderArgs ra;
+    Knobs kn;
+    CS_TRY(render_args(prm, ra, kn));
+    CS_HIP(hipSetDevice(ctx->device));
+    ViewPlan vp;
+    CS_TRY(plan_views(n_views, cams, kn.tile, out_rgb, nullptr, vp));
+    const size_t inst = (size_t)sc->n * n_views, tiles = vp.hdr.total_tiles, pix = (size_t)vp.hdr.total_pix;
+    Frame *F = *Fp;
+    if (F && F->K == sc->k && F->deg == sc->sh_degree && F->cap_inst >= inst && F->cap_tiles >= tiles &&
+        F->cap_pix >= pix) {
+        F->st = st;
+        F->n = sc->n;
+        F->V = n_views;
+        F->ninst = inst;
+    } else { // re-create, at least as large as the frame it replaces
+        size_t min_inst = 0, min_tiles = tiles, min_pix = pix;
+        if (F) {
+            if (F->K == sc->k && F->deg == sc->sh_degree) {
+                min_inst = F->cap_inst;
+                min_tiles = std::max(min_tiles, F->cap_tiles);
+                min_pix = std::max(min_pix, F->cap_pix);
+            }
+            F->st = nullptr; // idle: its buffers go back on the null stream
+            delete F;
+            *Fp = nullptr;
+        }
+        F = new Frame;
+        int r = F->init(sc->n, sc->k, sc->sh_degree, n_views, min_tiles, min_pix, st, &ctx->ring, min_inst);
+        if (r) {
+            delete F;
+            return r;
+        }
+        *Fp = F;
+        *created = true;
+    }
+    F->ring = &ctx->ring;
+    CS_TRY(F->upload_views(vp.hdr, vp.views.data()));
+    StageTimer tm(ctx, st, false);
+    return enqueue_forward(ctx, *F, sc, ra, kn, false, 1.3, tm);
+}
+
+} // namespace cs

@@ -53,8 +53,10 @@ struct Frame {
     float *acc = nullptr;
     uint32_t *counters = nullptr; // CNT_WORDS counters, then the pair-offset scan's look-back status
     size_t counter_words = 0;
-    unsigned long long *evalcount = nullptr; // EVAL_SLOTS x (tested, full) of the last forward's workgroups
-    int eval_slots = 0;                      // slots that launch wrote
+    // work counters of the last passes' workgroups: EVAL_SLOTS slots of
+    // EVAL_FIELDS words for the forward, then as many for the backward
+    unsigned long long *evalcount = nullptr;
+    int eval_slots = 0, eval_slots_bwd = 0; // slots that the launches wrote
     uint32_t *h_counters = nullptr; // pinned read-back of the counters
     hipEvent_t counters_ev = nullptr;
     hipEvent_t mcount_ev = nullptr; // after the pair count's read-back (reused frames)
@@ -73,7 +75,9 @@ struct Frame {
 
     bool fixed = false; // buffers carved from caller memory (bind): nothing is allocated or freed
 
-    int init(int n, int K, int deg, int V, size_t tiles, size_t pix, hipStream_t st, HostRing *ring);
+    // min_inst: a floor for the instance capacity (a frame re-created larger)
+    int init(int n, int K, int deg, int V, size_t tiles, size_t pix, hipStream_t st, HostRing *ring,
+             size_t min_inst = 0);
     int bind(uint8_t *base, size_t bytes, int n, int K, int deg, size_t tiles, size_t pix, hipStream_t st);
     int init_async_readback();
     int alloc(void **p, size_t bytes);
@@ -85,6 +89,14 @@ struct Frame {
 };
 
 struct Server;
+
+// Batched eager forward of n_views views on a frame owned by the caller (the
+// serving loop).  *F (nullable) is used when the batch fits its capacities,
+// else replaced by a new frame at least as large as it (*created set); its
+// pair buffers grow inside the pass.  The frame is idle again once the
+// stream's work completes.
+int forward_batch_on(cs_ctx *ctx, Frame **F, const cs_scene *sc, int n_views, const cs_camera *cams,
+                     const cs_params *prm, float *const *out_rgb, hipStream_t st, bool *created);
 
 } // namespace cs
 

@@ -1,7 +1,11 @@
 // Request loop of the renderer: resident scenes, a host queue of view
 // requests, and worker threads that turn the queued requests of one scene into
-// one batched forward pass on their own stream (continuous batching), admitted
-// by an estimate of the batch's device memory against a budget.
+// one batched forward pass on their own stream (continuous batching).  The
+// device buffers of the passes are frames owned by the server and shared by
+// its workers: a batch takes an idle frame of its scene (grown when the batch
+// exceeds it), so the steady state allocates nothing, and every frame, idle
+// or in use, counts against the HBM budget.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -25,20 +29,21 @@ struct Request {
     int32_t scene = 0;
     cs_camera cam{};
     float *out = nullptr;
-    double t_submit = 0.0, t_done = 0.0;
-    size_t bytes = 0;
+    double t_submit = 0.0, t_start = 0.0, t_done = 0.0;
     int status = 0;
     bool done = false;
 };
 
-// Device memory of a batched forward pass: per (view, convex) instance the
-// record and 44 bytes of keys, ids, counts, offsets, rectangle and hull; an
-// allowance of 16 (tile, instance) pairs x 16 bytes (two ping-pong pairs of
-// 4-byte arrays); 8 bytes of per-pixel state; and a fixed 1 MiB.
+// Device memory of a batched forward pass (to admit a batch whose frame must
+// be created or grown): per (view, convex) instance the record and 60 bytes of
+// keys, ids, counts, offsets, binning records and hull, a quarter more for the
+// capacity rounding of frames; an allowance of 16 (tile, instance) pairs x 16
+// bytes (two ping-pong pairs of 4-byte arrays); 8 bytes of per-pixel state;
+// and a fixed 2 MiB (view table, counters, work-counter slots).
 size_t estimate_bytes(const cs_scene &s, int64_t views, int64_t pixels)
 {
     const int64_t inst = (int64_t)s.n * views;
-    return (size_t)(inst * (rec_stride(s.k) + 44) + inst * 16 * 16 + pixels * 8 + (1 << 20));
+    return (size_t)((double)(inst * (rec_stride(s.k) + 60)) * 1.25) + (size_t)(inst * 16 * 16 + pixels * 8 + (2 << 20));
 }
 
 } // namespace
@@ -55,18 +60,28 @@ struct Server {
     int32_t next_scene = 1;
     uint64_t next_id = 1;
     bool stop = false, paused = false;
-    size_t in_flight = 0, peak = 0;
-    int64_t submitted = 0, completed = 0, failed = 0, batches = 0, batch_reqs = 0, running = 0;
+    // frames: idle ones by scene (and last use), the bytes of all of them
+    struct Idle {
+        Frame *F;
+        int32_t scene;
+        uint64_t tick;
+    };
+    std::vector<Idle> idle;
+    size_t held = 0, peak = 0;
+    uint64_t tick = 0;
+    int64_t submitted = 0, completed = 0, failed = 0, batches = 0, batch_reqs = 0, running = 0, frames_created = 0;
+    double sum_queue_ms = 0.0, sum_run_ms = 0.0;
     std::vector<std::thread> workers;
 
-    bool fits(size_t bytes) const { return budget == 0 || in_flight == 0 || in_flight + bytes <= budget; }
-
-    // Under the lock: requests of the oldest request's scene, in arrival order,
-    // as many as max_batch and the budget allow.
-    bool take(std::vector<uint64_t> &ids, size_t &bytes)
+    // Under the lock: the requests of the oldest request's scene, in arrival
+    // order, up to max_batch, with an idle frame of that scene (or none), when
+    // the device memory the batch may add fits the budget after idle frames of
+    // other scenes are dropped (into `drop`, to be freed outside the lock).
+    // A batch always runs when nothing else does.
+    bool take(std::vector<uint64_t> &ids, Frame *&frame, std::vector<Frame *> &drop)
     {
         ids.clear();
-        bytes = 0;
+        frame = nullptr;
         if (queue.empty() || paused) return false;
         const Request &first = reqs[queue.front()];
         auto sit = scenes.find(first.scene);
@@ -87,14 +102,36 @@ struct Server {
             if ((int)pick.size() >= cfg.max_batch) break;
             const Request &r = reqs[id];
             if (r.scene != first.scene) continue;
-            const int64_t p = (int64_t)r.cam.width * r.cam.height;
-            const size_t b = estimate_bytes(sc, (int64_t)pick.size() + 1, pix + p);
-            if (!pick.empty() && budget && in_flight + b > budget) break;
             pick.push_back(id);
-            pix += p;
-            bytes = b;
+            pix += (int64_t)r.cam.width * r.cam.height;
         }
-        if (pick.empty() || !fits(bytes)) return false;
+        // the idle frame of this scene most recently used, if any
+        int best = -1;
+        for (size_t i = 0; i < idle.size(); ++i)
+            if (idle[i].scene == first.scene && (best < 0 || idle[i].tick > idle[best].tick)) best = (int)i;
+        const size_t have = best >= 0 ? idle[best].F->bytes_held : 0;
+        const size_t need = estimate_bytes(sc, (int64_t)pick.size(), pix);
+        const size_t grow = need > have ? need - have : 0;
+        if (budget) {
+            // drop idle frames of other scenes, least recently used first, while short
+            while (held + grow > budget) {
+                int lru = -1;
+                for (size_t i = 0; i < idle.size(); ++i)
+                    if ((int)i != best && (lru < 0 || idle[i].tick < idle[lru].tick)) lru = (int)i;
+                if (lru < 0) {
+                    if (running > 0) return false; // wait for running batches
+                    break;                         // alone: run anyway
+                }
+                held -= idle[lru].F->bytes_held;
+                drop.push_back(idle[lru].F);
+                idle.erase(idle.begin() + lru);
+                if (best > lru) --best;
+            }
+        }
+        if (best >= 0) {
+            frame = idle[best].F;
+            idle.erase(idle.begin() + best);
+        }
         for (uint64_t id : pick) {
             for (auto it = queue.begin(); it != queue.end(); ++it)
                 if (*it == id) {
@@ -111,50 +148,84 @@ struct Server {
         (void)hipSetDevice(device);
         cs_ctx *ctx = nullptr;
         hipStream_t st = nullptr;
+        hipEvent_t done_ev = nullptr;
         int init = cs_create(device, 0, &ctx);
         if (init == CS_OK && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) init = CS_EHIP;
+        if (init == CS_OK && hipEventCreateWithFlags(&done_ev, hipEventDisableTiming) != hipSuccess) init = CS_EHIP;
         cs_params prm = cfg.params;
         prm.flags &= ~(CS_FLAG_GRAPH | CS_FLAG_AUTOTUNE | CS_FLAG_TIMING);
         std::vector<uint64_t> ids;
         std::vector<cs_camera> cams;
         std::vector<float *> outs;
+        std::vector<Frame *> drop;
         for (;;) {
-            size_t bytes = 0;
+            Frame *F = nullptr;
             cs_scene sc{};
+            int32_t scene_id = 0;
+            drop.clear();
             {
                 std::unique_lock<std::mutex> lk(mu);
                 cv_work.wait(lk, [&] { return stop || (!paused && !queue.empty()); });
                 if (stop) break;
-                if (!take(ids, bytes)) {
-                    cv_work.wait_for(lk, std::chrono::microseconds(200));
+                if (!take(ids, F, drop)) {
+                    lk.unlock();
+                    release_idle(drop);
+                    lk.lock();
+                    // waiting for memory held by running batches: woken when one ends
+                    cv_work.wait_for(lk, std::chrono::milliseconds(5));
                     continue;
                 }
-                sc = scenes[reqs[ids[0]].scene];
+                scene_id = reqs[ids[0]].scene;
+                sc = scenes[scene_id];
                 cams.clear();
                 outs.clear();
+                const double t = now_ms();
                 for (uint64_t id : ids) {
-                    cams.push_back(reqs[id].cam);
-                    outs.push_back(reqs[id].out);
+                    Request &r = reqs[id];
+                    r.t_start = t;
+                    cams.push_back(r.cam);
+                    outs.push_back(r.out);
                 }
-                in_flight += bytes;
-                peak = std::max(peak, in_flight);
                 running += (int64_t)ids.size();
             }
+            release_idle(drop);
+            const size_t before = F ? F->bytes_held : 0;
+            bool created = false;
             int rc = init;
             if (rc == CS_OK)
-                rc = cs_render_forward_batch(ctx, &sc, (int32_t)ids.size(), cams.data(), &prm, outs.data(), nullptr,
-                                             st);
-            if (rc == CS_OK && hipStreamSynchronize(st) != hipSuccess) rc = CS_EHIP;
+                rc = forward_batch_on(ctx, &F, &sc, (int32_t)ids.size(), cams.data(), &prm, outs.data(), st, &created);
+            // completion by polling an event: a blocking wait wakes up late
+            if (rc == CS_OK && hipEventRecord(done_ev, st) != hipSuccess) rc = CS_EHIP;
+            if (rc == CS_OK) {
+                hipError_t e;
+                while ((e = hipEventQuery(done_ev)) == hipErrorNotReady) std::this_thread::yield();
+                if (e != hipSuccess) rc = CS_EHIP;
+            } else if (st) {
+                (void)hipStreamSynchronize(st);
+            }
             const double t = now_ms();
             {
                 std::lock_guard<std::mutex> lk(mu);
+                held -= before;
+                if (F) {
+                    if (rc == CS_OK) {
+                        held += F->bytes_held;
+                        idle.push_back({F, scene_id, ++tick});
+                    } else {
+                        F->st = nullptr;
+                        delete F;
+                    }
+                }
+                peak = std::max(peak, held);
+                frames_created += created ? 1 : 0;
                 for (uint64_t id : ids) {
                     Request &r = reqs[id];
                     r.status = rc;
                     r.t_done = t;
                     r.done = true;
+                    sum_queue_ms += r.t_start - r.t_submit;
+                    sum_run_ms += t - r.t_start;
                 }
-                in_flight -= bytes;
                 running -= (int64_t)ids.size();
                 ++batches;
                 batch_reqs += (int64_t)ids.size();
@@ -163,9 +234,31 @@ struct Server {
             cv_done.notify_all();
             cv_work.notify_all();
         }
-        // the context's cached frames were last used on st: free them before st goes
+        if (done_ev) (void)hipEventDestroy(done_ev);
         if (ctx) cs_destroy(ctx);
         if (st) (void)hipStreamDestroy(st);
+    }
+
+    // Idle frames leave: their buffers go back on the null stream (their last
+    // stream may belong to another worker).
+    static void release_idle(std::vector<Frame *> &frames)
+    {
+        for (Frame *d : frames) {
+            d->st = nullptr;
+            delete d;
+        }
+        frames.clear();
+    }
+
+    // After the workers have joined: free the idle frames.
+    void free_frames()
+    {
+        (void)hipDeviceSynchronize();
+        std::vector<Frame *> all;
+        for (Idle &i : idle) all.push_back(i.F);
+        idle.clear();
+        release_idle(all);
+        held = 0;
     }
 };
 
@@ -215,6 +308,7 @@ int cs_serve_stop(cs_ctx *ctx)
     }
     S->cv_work.notify_all();
     for (auto &t : S->workers) t.join();
+    S->free_frames();
     {
         std::lock_guard<std::mutex> lk(S->mu);
         for (uint64_t id : S->queue) {
@@ -273,7 +367,6 @@ int cs_serve_submit(cs_ctx *ctx, int32_t scene_id, const cs_camera *cam, float *
         r.scene = scene_id;
         r.cam = *cam;
         r.out = out_rgb;
-        r.bytes = b;
         r.t_submit = now_ms();
         S->queue.push_back(id);
         ++S->submitted;
@@ -311,6 +404,11 @@ int cs_serve_get_stats(cs_ctx *ctx, cs_serve_stats *out)
     out->peak_bytes = S->peak;
     out->queued = (int64_t)S->queue.size();
     out->running = S->running;
+    out->frames_created = S->frames_created;
+    out->frame_bytes = S->held;
+    const int64_t fin = S->completed + S->failed;
+    out->mean_queue_ms = fin ? S->sum_queue_ms / (double)fin : 0.0;
+    out->mean_run_ms = fin ? S->sum_run_ms / (double)fin : 0.0;
     return CS_OK;
 }
 

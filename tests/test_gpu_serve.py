@@ -114,3 +114,63 @@ def test_admission_and_queue_limits(R):
     assert (rc1, rc2, rc3) == (0, 0, CS_EBUSY)
     assert R.serve_stats()["queued"] == 2
     R.serve_stop()
+
+
+def estimate_bytes(n, k, views, pixels):
+    """The server's admission estimate of a batch (per instance the record
+    and 60 bytes of keys and binning, a quarter more for capacity rounding,
+    16 pairs of 16 bytes; 8 bytes per pixel; 2 MiB)."""
+    rec = (48 + 24 * k + 15) & ~15
+    inst = n * views
+    return int(inst * (rec + 60) * 1.25) + inst * 16 * 16 + pixels * 8 + (2 << 20)
+
+
+def test_frames_count_against_the_budget_and_are_reused(R):
+    """Frames (idle or running) never hold more device memory than the budget
+    when every batch fits it alone; with no budget, a second round of the same
+    request mix allocates no frame."""
+    from paper_2411_14974_amd.binding import DeviceScene
+    sizes = (20000, 40000, 60000)
+    ds = []
+    for i, n in enumerate(sizes):
+        rng = np.random.default_rng(5100 + i)
+        ds.append(DeviceScene.from_scene(scenes.convexes_around(rng, scenes.gmm_centres(rng, n), 6, 3), "cuda:0"))
+    W, H = 320, 180
+    budget = int(2.5 * estimate_bytes(max(sizes), 6, 2, 2 * W * H))
+
+    def round_of(sids, rng, count, resume=False):
+        outs = [torch.empty((H, W, 3), device="cuda:0") for _ in range(count)]
+        ids = [R.serve_submit(sids[int(rng.integers(0, len(sids)))], scenes.orbit_camera(rng, W, H), o)
+               for o in outs]
+        if resume:
+            R.serve_resume()
+        for rid in ids:
+            R.serve_wait(rid)
+        return outs
+
+    R.serve_start(workers=2, max_batch=2, hbm_budget_bytes=budget)
+    try:
+        sids = [R.scene_register(d) for d in ds]
+        round_of(sids, np.random.default_rng(61), 60)
+        st = R.serve_stats()
+        print(f"[serve-budget] budget {budget}, stats {st}", flush=True)
+        assert st["completed"] == 60 and st["failed"] == 0
+        assert st["peak_bytes"] <= budget, (st["peak_bytes"], budget)
+        assert st["frame_bytes"] <= budget
+    finally:
+        R.serve_stop()
+    # one worker, round 1 queued before it starts: every scene's frame meets a
+    # two-view batch in round 1, so round 2 fits the frames it left
+    R.serve_start(workers=1, max_batch=2, start_paused=True)
+    try:
+        sids = [R.scene_register(d) for d in ds]
+        round_of(sids, np.random.default_rng(62), 60, resume=True)
+        made = R.serve_stats()["frames_created"]
+        assert made == len(sizes)
+        round_of(sids, np.random.default_rng(63), 60)
+        st = R.serve_stats()
+        print(f"[serve-reuse] frames after round 1: {made}, after round 2: {st['frames_created']}; {st}", flush=True)
+        assert st["frames_created"] == made
+        assert st["completed"] == 120 and st["failed"] == 0
+    finally:
+        R.serve_stop()
