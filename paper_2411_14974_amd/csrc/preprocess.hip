@@ -48,6 +48,30 @@ template <typename P> __device__ __forceinline__ float4 ld4(const P *p, int q)
     }
 }
 
+// 1/x and 1/sqrt(x) in FP64: the hardware estimate and two Newton steps (each
+// doubles the correct bits), to within an ulp or two of the rounded result for
+// the finite, nonzero, normal arguments they get here (depths beyond the near
+// plane, squared edge lengths of distinct hull vertices, polygon-corner
+// denominators, nonzero line slopes); the correctly rounded division is an
+// eleven-instruction sequence.
+__device__ __forceinline__ double rcp64(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    double t = fma(-h * y, y, 0.5); // y <- y (1.5 - x y^2 / 2)
+    y = fma(y, t, y);
+    t = fma(-h * y, y, 0.5);
+    return fma(y, t, y);
+}
+
 // Inclusive pixel range [lo, hi] whose centres (u + 0.5) fall in [a, b], clamped to [0, n).
 __device__ __forceinline__ void pixel_span(double a, double b, int n, int &lo, int &hi)
 {
@@ -111,9 +135,11 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
     stage_rows<PF_BLOCK, 3 * K>(s_pts, points + (size_t)base * 3 * K, cnt, 3 * K, PS);
     __syncthreads();
     // one (view, convex) instance per thread; all outputs are indexed by the
-    // instance (threads past n compute on the last convex and store nothing)
+    // instance (threads past n compute on the last convex, whose row they read,
+    // and store nothing)
     const bool active = base + (int)threadIdx.x < n;
     const int i = active ? base + (int)threadIdx.x : n - 1;
+    const int srow = active ? (int)threadIdx.x : cnt - 1;
     const CamArgs cam = reinterpret_cast<const ViewDesc *>(frame + 1)[blockIdx.y].cam;
     const size_t inst = (size_t)blockIdx.y * n + i;
     if (active) ids[inst] = (uint32_t)inst;
@@ -121,9 +147,9 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
     float px[K], py[K], pz[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        px[k] = s_pts[threadIdx.x * PS + 3 * k];
-        py[k] = s_pts[threadIdx.x * PS + 3 * k + 1];
-        pz[k] = s_pts[threadIdx.x * PS + 3 * k + 2];
+        px[k] = s_pts[srow * PS + 3 * k];
+        py[k] = s_pts[srow * PS + 3 * k + 1];
+        pz[k] = s_pts[srow * PS + 3 * k + 2];
     }
     __syncthreads(); // the LDS now takes the records
     // point centroid (for the SH view direction), taken now so the points can retire early
@@ -166,7 +192,9 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
             X[k] = r0 * x + r1 * y + r2 * z + (double)cam.t[0];
             Y[k] = r3 * x + r4 * y + r5 * z + (double)cam.t[1];
             Z[k] = r6 * x + r7 * y + r8 * z + (double)cam.t[2];
-            // the projection's own arithmetic (the hull's orientation tests read it bit for bit)
+            // the projection with true divisions: the hull's orientation tests
+            // and the edge normals read it bit for bit, and a one-ulp change of
+            // a point moves the normal of a short edge by far more than an ulp
             qx[k] = (double)cam.fx * X[k] / Z[k] + (double)cam.cx;
             qy[k] = (double)cam.fy * Y[k] / Z[k] + (double)cam.cy;
             zs += Z[k];
@@ -192,10 +220,13 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
         double2 *lines2 = reinterpret_cast<double2 *>(rec + REC_HEADER);
         double carry = 0.0;
 
-        // cut-off radius: outside { L_j <= r for all j } alpha < eps_alpha
+        // cut-off radius: outside { L_j <= r for all j } alpha < eps_alpha.  The
+        // logarithm in float32 (the radius is a sub-pixel length bounded with a
+        // 1e-3 pixel margin; the skip threshold below is stored as a float)
         const double eps = (double)ra.eps_alpha;
         const bool faint = !(o > eps);
-        const double r = faint ? 0.0 : log(o / eps - 1.0) / (sp * dp);
+        const float lg2 = faint ? 0.0f : __log2f((float)(o / eps - 1.0));
+        const double r = faint ? 0.0 : (double)lg2 * LN2 * rcp64(sp * dp);
         double bx0 = 1e300, by0 = 1e300, bx1 = -1e300, by1 = -1e300;
         bool unbounded = false;
 
@@ -224,7 +255,7 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
             }
             // edge cur -> nxt: outward unit normal (e_y, -e_x)/|e|
             const double ex = nxp - cxp, ey = nyp - cyp;
-            const double il = 1.0 / sqrt(ex * ex + ey * ey);
+            const double il = rsq64(ex * ex + ey * ey);
             const double A = ey * il, B = -ex * il;
             const double Cabs = -(A * cxp + B * cyp);
             const double Crel = -(A * (cxp - ox) + B * (cyp - oy));
@@ -246,8 +277,8 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
                 firstA = A; firstB = B; firstC = Cabs;
             } else {
                 const double den = 1.0 + prevA * A + prevB * B;
-                if (den < 1e-6) unbounded = true;
-                const double rd = r / den;
+                if (den < 1e-6) unbounded = true; // (then the box is unbounded, whatever rd is)
+                const double rd = r * rcp64(den);
                 const double mx = cxp + rd * (prevA + A), my = cyp + rd * (prevB + B);
                 bx0 = fmin(bx0, fmin(mx, cxp)); bx1 = fmax(bx1, fmax(mx, cxp));
                 by0 = fmin(by0, fmin(my, cyp)); by1 = fmax(by1, fmax(my, cyp));
@@ -271,7 +302,7 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
         if (closed && T >= 3) {
             const double den = 1.0 + prevA * firstA + prevB * firstB;
             if (den < 1e-6) unbounded = true;
-            const double rd = r / den;
+            const double rd = r * rcp64(den);
             const double mx = sx + rd * (prevA + firstA), my = sy + rd * (prevB + firstB);
             bx0 = fmin(bx0, fmin(mx, sx)); bx1 = fmax(bx1, fmax(mx, sx));
             by0 = fmin(by0, fmin(my, sy)); by1 = fmax(by1, fmax(my, sy));
@@ -317,7 +348,7 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
             h.oy = (float)oy;
             h.sigma_p = (float)sp;
             // skip when max_j x2_j > log2(o/eps - 1) / sigma'  (LogSumExp >= its max)
-            h.thr2 = faint ? -INFINITY : (float)(log2(o / eps - 1.0) / sp);
+            h.thr2 = faint ? -INFINITY : (float)((double)lg2 * rcp64(sp));
             h.opacity = (float)o;
             h.rgb[0] = rgb[0]; h.rgb[1] = rgb[1]; h.rgb[2] = rgb[2];
             h.T = T;
@@ -377,7 +408,7 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
                         // each row keeps one interval of tiles (cost per row, not per tile)
                         double inv[K];
 #pragma unroll
-                        for (int j = 0; j < K; ++j) inv[j] = la[j] != 0.0 ? 1.0 / la[j] : 0.0;
+                        for (int j = 0; j < K; ++j) inv[j] = la[j] != 0.0 ? rcp64(la[j]) : 0.0;
                         uint64_t m = 0;
                         for (int ty = ty0; ty <= ty1; ++ty) {
                             const double c0 = (double)max(ty * ra.tile, v0) + 0.5 - oy;

@@ -694,15 +694,42 @@ __global__ void fill_u32_kernel(uint32_t *__restrict__ p, size_t n, uint32_t v)
         p[i] = v;
 }
 
-__global__ void tile_ranges_kernel(const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ n_dev,
-                                   uint32_t n_host, uint2 *__restrict__ ranges)
+// [start, end) of every tile's run in the sorted tile ids.  Each thread takes
+// RANGE_ITEMS consecutive ids in 16-byte loads (the sorted ids are 16-byte
+// aligned) plus the id before them, and marks the run boundaries among them.
+constexpr int RANGE_ITEMS = 8;
+
+__global__ __launch_bounds__(256) void tile_ranges_kernel(const uint32_t *__restrict__ tiles,
+                                                          const uint32_t *__restrict__ n_dev, uint32_t n_host,
+                                                          uint2 *__restrict__ ranges)
 {
     const uint32_t n = n_dev ? *n_dev : n_host;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t t = tiles[i];
-    if (i == 0 || tiles[i - 1] != t) ranges[t].x = i;
-    if (i == n - 1 || tiles[i + 1] != t) ranges[t].y = i + 1;
+    const size_t i0 = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * RANGE_ITEMS;
+    if (i0 >= n) return;
+    uint32_t t[RANGE_ITEMS];
+    if (i0 + RANGE_ITEMS <= n) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(tiles + i0);
+#pragma unroll
+        for (int q = 0; q < RANGE_ITEMS / 4; ++q) {
+            const uint4 w = src[q];
+            t[4 * q] = w.x; t[4 * q + 1] = w.y; t[4 * q + 2] = w.z; t[4 * q + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < RANGE_ITEMS; ++k) t[k] = i0 + k < n ? tiles[i0 + k] : 0u;
+    }
+    uint32_t prev = i0 > 0 ? tiles[i0 - 1] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int k = 0; k < RANGE_ITEMS; ++k) {
+        const size_t i = i0 + k;
+        if (i >= n) break;
+        if (t[k] != prev) { // a run starts at i and the previous one ends there
+            ranges[t[k]].x = (uint32_t)i;
+            if (i > 0) ranges[prev].y = (uint32_t)i;
+        }
+        prev = t[k];
+    }
+    if (i0 + RANGE_ITEMS >= n) ranges[prev].y = n; // the last run
 }
 
 void launch_fill_u32(hipStream_t st, uint32_t *p, size_t n, uint32_t v)
@@ -749,8 +776,9 @@ void launch_tile_ranges(hipStream_t st, const uint32_t *tiles, uint32_t n_host, 
                         uint32_t n_capacity, uint2 *ranges)
 {
     if (n_capacity == 0) return;
-    hipLaunchKernelGGL(tile_ranges_kernel, dim3((n_capacity + 255) / 256), dim3(256), 0, st, tiles, n_dev, n_host,
-                       ranges);
+    const size_t threads = ((size_t)n_capacity + RANGE_ITEMS - 1) / RANGE_ITEMS;
+    hipLaunchKernelGGL(tile_ranges_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, tiles, n_dev,
+                       n_host, ranges);
 }
 
 } // namespace cs

@@ -351,3 +351,29 @@ def test_autograd_matches_oracle_and_direct_call(R):
     for k in NAMES:
         torch.testing.assert_close(t[k].grad, g[k], rtol=1e-5, atol=1e-7)
     st.release()
+
+
+def test_work_counters_against_the_oracle(R):
+    """cs_state_counters: the pairs past the max-line test bound the pairs the
+    oracle composites (every pixel's contributors, matched mode) and are
+    bounded by the pairs tested; the backward walk (up to each pixel's last
+    contributor) sees a subset of the forward's (which walks on until T falls
+    below t_min); the mean hull size lies in [3, K]; lane utilisation in (0, 1]."""
+    import oracle
+    from paper_2411_14974_amd.binding import DeviceScene, make_params
+    scene, cam, _ = scenes.config3(n=40000, width=240, height=135)
+    ds = DeviceScene.from_scene(scene, "cuda:0")
+    rgb, st = R.forward(ds, cam, make_params(), want_state=True)
+    dl = torch.ones_like(rgb)
+    R.backward(st, dl)
+    torch.cuda.synchronize()
+    c = st.counters()
+    _, _, nref = oracle.render(scene, cam, mode=oracle.MODE_MATCHED)
+    contrib = int(nref.sum())
+    T_mean = c["sum_T_full"] / c["full_bwd"]
+    util = c["full_bwd"] / (64 * c["wave_evals"])
+    print(f"[counters] {c}; oracle contributors {contrib}; mean T {T_mean:.3f}; lane utilisation {util:.3f}", flush=True)
+    assert contrib <= c["full_bwd"] <= c["full"] <= c["tested"] <= 256 * c["pairs"]
+    assert 3.0 <= T_mean <= scene.k
+    assert 0.0 < util <= 1.0
+    st.release()
