@@ -48,6 +48,8 @@ size_t estimate_bytes(const cs_scene &s, int64_t views, int64_t pixels)
 
 } // namespace
 
+constexpr int MAX_IDLE_PER_SCENE = 8;
+
 struct Server {
     cs_ctx *owner = nullptr;
     cs_serve_config cfg{};
@@ -96,7 +98,8 @@ struct Server {
             return false;
         }
         const cs_scene &sc = sit->second;
-        int64_t pix = 0;
+        const int tile = cfg.params.tile > 0 ? cfg.params.tile : 16;
+        int64_t pix = 0, tiles = 0;
         std::vector<uint64_t> pick;
         for (uint64_t id : queue) {
             if ((int)pick.size() >= cfg.max_batch) break;
@@ -104,11 +107,20 @@ struct Server {
             if (r.scene != first.scene) continue;
             pick.push_back(id);
             pix += (int64_t)r.cam.width * r.cam.height;
+            tiles += (int64_t)((r.cam.width + tile - 1) / tile) * ((r.cam.height + tile - 1) / tile);
         }
-        // the idle frame of this scene most recently used, if any
+        // the smallest idle frame of this scene that fits the batch and is at
+        // most 4x its size (a much larger one would run its capacity-sized sort
+        // grids for nothing); none: a new frame of the batch's size
+        const size_t inst = (size_t)sc.n * pick.size();
         int best = -1;
-        for (size_t i = 0; i < idle.size(); ++i)
-            if (idle[i].scene == first.scene && (best < 0 || idle[i].tick > idle[best].tick)) best = (int)i;
+        for (size_t i = 0; i < idle.size(); ++i) {
+            const Frame *f = idle[i].F;
+            if (idle[i].scene != first.scene || f->cap_inst < inst || f->cap_inst > 4 * inst + 4096 ||
+                f->cap_tiles < (size_t)tiles || f->cap_pix < (size_t)pix)
+                continue;
+            if (best < 0 || f->cap_inst < idle[best].F->cap_inst) best = (int)i;
+        }
         const size_t have = best >= 0 ? idle[best].F->bytes_held : 0;
         const size_t need = estimate_bytes(sc, (int64_t)pick.size(), pix);
         const size_t grow = need > have ? need - have : 0;
@@ -211,6 +223,19 @@ struct Server {
                     if (rc == CS_OK) {
                         held += F->bytes_held;
                         idle.push_back({F, scene_id, ++tick});
+                        // at most MAX_IDLE_PER_SCENE idle frames of a scene (sizes of
+                        // the batches it meets): the least recently used goes
+                        int count = 0, lru = -1;
+                        for (size_t i = 0; i < idle.size(); ++i)
+                            if (idle[i].scene == scene_id) {
+                                ++count;
+                                if (lru < 0 || idle[i].tick < idle[lru].tick) lru = (int)i;
+                            }
+                        if (count > MAX_IDLE_PER_SCENE) {
+                            held -= idle[lru].F->bytes_held;
+                            drop.push_back(idle[lru].F);
+                            idle.erase(idle.begin() + lru);
+                        }
                     } else {
                         F->st = nullptr;
                         delete F;
@@ -233,6 +258,7 @@ struct Server {
             }
             cv_done.notify_all();
             cv_work.notify_all();
+            release_idle(drop);
         }
         if (done_ev) (void)hipEventDestroy(done_ev);
         if (ctx) cs_destroy(ctx);
