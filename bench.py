@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # VALU issue: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-operations/s for
-# full-rate ops (FP32 and FP64 FMA alike on this chip); a transcendental costs 4.
+# full-rate ops (FP32 and FP64 FMA alike on this chip); a transcendental costs TRANS_SLOTS.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
@@ -43,14 +43,20 @@ def workload(name):
     return scene, cam, target, desc
 
 
+# Issue slots of one float32 transcendental (v_exp_f32, v_log_f32, v_rcp_f32) in
+# full-rate VALU operations: measured on the MI355X with chains of exp2 against
+# chains of FMA (half rate), where an earlier estimate assumed quarter rate.
+TRANS_SLOTS = 2
+
+
 def pair_cost(stage, T):
     """VALU lane-operations of one full (pixel, convex) pair evaluation with T
-    hull lines, a transcendental counted as 4 full-rate operations:
+    hull lines, a transcendental counted as TRANS_SLOTS full-rate operations:
     forward (T + 3) transcendentals, 2T FP64 FMA, 3T + 12 FP32 operations;
     backward (T + 4) transcendentals, 2T FP64 FMA, 12T + 30 FP32 operations."""
     if stage == "render_fwd":
-        return 4 * (T + 3) + 2 * T + (3 * T + 12)
-    return 4 * (T + 4) + 2 * T + (12 * T + 30)
+        return TRANS_SLOTS * (T + 3) + 2 * T + (3 * T + 12)
+    return TRANS_SLOTS * (T + 4) + 2 * T + (12 * T + 30)
 
 
 def stage_work(stage, n, m, K, deg, cnt):
