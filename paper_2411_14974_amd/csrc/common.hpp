@@ -96,20 +96,69 @@ enum : int { EV_TESTED = 0, EV_FULL = 1, EV_SUM_T = 2, EV_WAVES = 3, EVAL_FIELDS
 
 // Device counters of one frame (u32 words).
 // Per-instance binning record (16 bytes): the tile rectangle, tx0 | ty0 << 16
-// and tx1 | ty1 << 16 (empty when tx0 > tx1), and the mask of kept tiles of a
-// rectangle of at most 64 tiles (bit (ty - ty0) * width + (tx - tx0)); larger
-// rectangles keep every tile.
+// and tx1 | ty1 << 16 (empty when tx0 > tx1), and 64 bits of kept tiles:
+//  - a rectangle of at most 64 tiles: the mask of kept tiles (bit
+//    (ty - ty0) * width + (tx - tx0));
+//  - a larger one: its rows are grouped into at most BIG_BANDS bands of
+//    ceil(th / BIG_BANDS) tile rows and its columns into at most 2^BIG_BITS
+//    blocks of ceil(tw / 2^BIG_BITS) tiles; field r (2 BIG_BITS bits) holds
+//    band r's kept blocks as the interval bx0 | bx1 << BIG_BITS (empty when
+//    bx0 > bx1), and the band keeps every tile of those blocks.
 __host__ __device__ inline uint4 make_bin(int tx0, int ty0, int tx1, int ty1, uint64_t mask)
 {
     return make_uint4((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16), (uint32_t)mask,
                       (uint32_t)(mask >> 32));
 }
+#ifndef CS_BIG_BANDS
+#define CS_BIG_BANDS 4
+#endif
+constexpr int BIG_BANDS = CS_BIG_BANDS;
+constexpr int BIG_BITS = 32 / BIG_BANDS;
+constexpr uint64_t BIG_FIELD = (1ull << (2 * BIG_BITS)) - 1ull;
+constexpr uint64_t big_empty()
+{
+    uint64_t m = 0;
+    for (int r = 0; r < BIG_BANDS; ++r) m |= ((1ull << BIG_BITS) - 1ull) << (2 * BIG_BITS * r);
+    return m;
+}
+constexpr uint64_t BIG_EMPTY = big_empty(); // every band of a large rectangle empty
+__host__ __device__ inline int big_bw(int tw) { return (tw + (1 << BIG_BITS) - 1) >> BIG_BITS; }
+__host__ __device__ inline int big_bh(int th) { return (th + BIG_BANDS - 1) / BIG_BANDS; }
+__host__ __device__ inline uint64_t big_field(int bx0, int bx1, int r)
+{
+    return ((uint64_t)bx0 | ((uint64_t)bx1 << BIG_BITS)) << (2 * BIG_BITS * r);
+}
+// Band r of a large rectangle: its first tile row (rectangle-relative) *row0,
+// its tile rows *nrow, first kept tile column *col0 and kept columns *ncol
+// (both 0 when the band is empty).
+__host__ __device__ inline void big_band(uint64_t mask, int tw, int th, int r, int *row0, int *nrow, int *col0,
+                                         int *ncol)
+{
+    const int bw = big_bw(tw), bh = big_bh(th);
+    const uint32_t f = (uint32_t)(mask >> (2 * BIG_BITS * r)) & (uint32_t)BIG_FIELD;
+    const int bx0 = (int)(f & ((1u << BIG_BITS) - 1u)), bx1 = (int)(f >> BIG_BITS);
+    *row0 = r * bh;
+    *nrow = th - r * bh < bh ? th - r * bh : bh;
+    const int cend = (bx1 + 1) * bw < tw ? (bx1 + 1) * bw : tw;
+    *col0 = bx0 * bw;
+    *ncol = (bx0 <= bx1 && *nrow > 0) ? cend - bx0 * bw : 0;
+    if (*ncol == 0) *nrow = 0;
+}
 __device__ inline uint32_t bin_count(uint4 b)
 {
     const int tx0 = (int)(b.x & 0xFFFFu), ty0 = (int)(b.x >> 16), tx1 = (int)(b.y & 0xFFFFu), ty1 = (int)(b.y >> 16);
     if (tx0 > tx1 || ty0 > ty1) return 0u;
-    const uint32_t area = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-    return area <= 64u ? (uint32_t)(__popc(b.z) + __popc(b.w)) : area;
+    const int tw = tx1 - tx0 + 1, th = ty1 - ty0 + 1;
+    const uint64_t mask = (uint64_t)b.z | ((uint64_t)b.w << 32);
+    if (tw * th <= 64) return (uint32_t)(__popc(b.z) + __popc(b.w));
+    uint32_t c = 0;
+#pragma unroll
+    for (int r = 0; r < BIG_BANDS; ++r) {
+        int row0, nrow, col0, ncol;
+        big_band(mask, tw, th, r, &row0, &nrow, &col0, &ncol);
+        c += (uint32_t)(nrow * ncol);
+    }
+    return c;
 }
 
 // Layout of a frame's counter buffer (32-bit words):

@@ -172,7 +172,7 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
     uint32_t packed = 0;
     int T = 0;
     int tx0 = 1, tx1 = 0, ty0 = 1, ty1 = 0;
-    uint64_t tmask = 0;  // tiles of a rectangle of <= 64 tiles that keep the convex (row-major)
+    uint64_t tmask = 0;  // kept tiles of the rectangle (binning record encoding)
     double dd = 0.0, dp = 0.0, sp = 0.0;
     float rgb[3] = {0.f, 0.f, 0.f};
     int clampmask = 0;
@@ -387,11 +387,14 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
                     // (max_j x2_j > thr2), so the pair is not emitted.  The minimum
                     // of a line over the rectangle is at a corner; the margin covers
                     // the rounding of both evaluations.
-                    // A rectangle one tile wide or high keeps every tile: the
-                    // polygon is connected and its bounding box spans the strip.
+                    // A small rectangle one tile wide or high keeps every tile:
+                    // the polygon is connected and its bounding box spans the
+                    // strip.  A rectangle of more than 64 tiles is culled the
+                    // same way per band of rows, in blocks of columns.
                     const int tw = tx1 - tx0 + 1, th = ty1 - ty0 + 1;
+                    const bool big = tw * th > 64;
                     tmask = (tw * th < 64) ? ((1ull << (tw * th)) - 1ull) : ~0ull;
-                    if (tw >= 2 && th >= 2 && tw * th <= 64) {
+                    if (big || (tw >= 2 && th >= 2)) {
                         // the lines as stored, into registers once (slots past T unused)
                         const double *ln = reinterpret_cast<const double *>(rec + REC_HEADER);
                         double la[K], lb[K], lc[K];
@@ -409,10 +412,13 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
                         double inv[K];
 #pragma unroll
                         for (int j = 0; j < K; ++j) inv[j] = la[j] != 0.0 ? rcp64(la[j]) : 0.0;
-                        uint64_t m = 0;
-                        for (int ty = ty0; ty <= ty1; ++ty) {
+                        // small: one tile row per step; big: one band of bh rows
+                        const int bh = big ? big_bh(th) : 1, bw = big ? big_bw(tw) : 1;
+                        uint64_t m = big ? BIG_EMPTY : 0ull;
+                        for (int ty = ty0, r = 0; ty <= ty1; ty += bh, ++r) {
+                            const int tyb = min(ty + bh - 1, ty1);
                             const double c0 = (double)max(ty * ra.tile, v0) + 0.5 - oy;
-                            const double c1 = (double)min(ty * ra.tile + ra.tile - 1, v1) + 0.5 - oy;
+                            const double c1 = (double)min(tyb * ra.tile + ra.tile - 1, v1) + 0.5 - oy;
                             double xlo = -INFINITY, xhi = INFINITY; // kept pixel centres, origin-relative
                             bool none = false;
 #pragma unroll
@@ -428,8 +434,12 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
                             const double uhi = fmin(floor(xhi + ox - 0.5), (double)u1);
                             if (none || !(ulo <= uhi)) continue;
                             const int kx0 = (int)ulo / ra.tile - tx0, kx1 = (int)uhi / ra.tile - tx0;
-                            const int nk = kx1 - kx0 + 1;
-                            m |= ((nk == 64) ? ~0ull : ((1ull << nk) - 1ull)) << ((ty - ty0) * tw + kx0);
+                            if (big) {
+                                m = (m & ~(BIG_FIELD << (2 * BIG_BITS * r))) | big_field(kx0 / bw, kx1 / bw, r);
+                            } else {
+                                const int nk = kx1 - kx0 + 1;
+                                m |= ((nk == 64) ? ~0ull : ((1ull << nk) - 1ull)) << ((ty - ty0) * tw + kx0);
+                            }
                         }
                         tmask = m;
                     }

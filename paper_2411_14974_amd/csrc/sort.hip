@@ -549,8 +549,10 @@ __global__ __launch_bounds__(EMIT_BLOCK) void emit_pairs_kernel(
     __shared__ uint32_t s_x0w[EMIT_BLOCK];  // tx0 | rect width << 16
     __shared__ uint32_t s_base[EMIT_BLOCK]; // global tile of the rectangle's first row start: toff + ty0 * tiles_x
     __shared__ uint32_t s_tx[EMIT_BLOCK];   // the view's tiles_x
-    __shared__ uint64_t s_mask[EMIT_BLOCK]; // kept tiles of a rectangle of <= 64 tiles (else unused)
+    __shared__ uint64_t s_mask[EMIT_BLOCK]; // kept tiles (binning record encoding)
     __shared__ uint32_t s_small[EMIT_BLOCK];
+    __shared__ uint32_t s_th[EMIT_BLOCK];    // rect height
+    __shared__ uint32_t s_bend[EMIT_BLOCK][BIG_BANDS]; // large rectangles: pairs up to the end of each band
     __shared__ float s_rw[EMIT_BLOCK];       // 1 / rect width
     __shared__ uint32_t s_own[EMIT_CHUNK];  // owner (block-local convex) of each pair of the chunk
     __shared__ uint32_t s_wmax[EMIT_BLOCK / 64];
@@ -565,7 +567,7 @@ __global__ __launch_bounds__(EMIT_BLOCK) void emit_pairs_kernel(
         const uint32_t off = offsets[r];
         s_off[tid] = off;
         s_id[tid] = id;
-        uint32_t x0w = 0, base = 0, tx = 1, small = 0;
+        uint32_t x0w = 0, base = 0, tx = 1, small = 0, th = 0;
         uint64_t mask = 0;
         if (counts_sorted[r] > 0) {
             const uint4 b = bins_sorted[r];
@@ -574,7 +576,8 @@ __global__ __launch_bounds__(EMIT_BLOCK) void emit_pairs_kernel(
             tx = (uint32_t)vd.tiles_x;
             x0w = tx0 | ((tx1 - tx0 + 1) << 16);
             base = (uint32_t)vd.tile_off + ty0 * tx;
-            small = (tx1 - tx0 + 1) * (ty1 - ty0 + 1) <= 64u;
+            th = ty1 - ty0 + 1;
+            small = (tx1 - tx0 + 1) * th <= 64u;
             mask = (uint64_t)b.z | ((uint64_t)b.w << 32);
         }
         s_x0w[tid] = x0w;
@@ -582,6 +585,17 @@ __global__ __launch_bounds__(EMIT_BLOCK) void emit_pairs_kernel(
         s_tx[tid] = tx;
         s_mask[tid] = mask;
         s_small[tid] = small;
+        s_th[tid] = th;
+        if (!small && th > 0) {
+            uint32_t acc = 0;
+#pragma unroll
+            for (int r = 0; r < BIG_BANDS; ++r) {
+                int row0, nrow, col0, ncol;
+                big_band(mask, (int)(x0w >> 16), (int)th, r, &row0, &nrow, &col0, &ncol);
+                acc += (uint32_t)(nrow * ncol);
+                s_bend[tid][r] = acc;
+            }
+        }
         s_rw[tid] = 1.0f / (float)max(x0w >> 16, 1u);
         if (tid == cnt - 1) s_end = off + counts_sorted[r];
     }
@@ -635,13 +649,32 @@ __global__ __launch_bounds__(EMIT_BLOCK) void emit_pairs_kernel(
             const uint32_t p = c0 + j;
             const int lo = (int)s_own[j];
             uint32_t q = p - s_off[lo];
-            if (s_small[lo]) q = nth_set_bit(s_mask[lo], q); // the q-th kept tile of the rectangle
             const uint32_t x0w = s_x0w[lo], w = x0w >> 16;
-            // q / w through the reciprocal (q < 2^24), corrected by one step
-            uint32_t row = (uint32_t)((float)q * s_rw[lo]);
-            if (row * w > q) --row;
-            else if ((row + 1) * w <= q) ++row;
-            const uint32_t col = q - row * w;
+            uint32_t row, col;
+            if (s_small[lo]) {
+                q = nth_set_bit(s_mask[lo], q); // the q-th kept tile of the rectangle
+                // q / w through the reciprocal (q < 2^24), corrected by one step
+                row = (uint32_t)((float)q * s_rw[lo]);
+                if (row * w > q) --row;
+                else if ((row + 1) * w <= q) ++row;
+                col = q - row * w;
+            } else { // the q-th tile of the kept bands, band by band, row-major in each
+                int r = 0;
+                uint32_t before = 0;
+#pragma unroll
+                for (int k = 0; k < BIG_BANDS - 1; ++k) {
+                    const uint32_t e = s_bend[lo][k];
+                    if (q >= e) { r = k + 1; before = e; }
+                }
+                int row0, nrow, col0, ncol;
+                big_band(s_mask[lo], (int)w, (int)s_th[lo], r, &row0, &nrow, &col0, &ncol);
+                const uint32_t qb = q - before, nc = (uint32_t)max(ncol, 1);
+                uint32_t rr = (uint32_t)((float)qb / (float)nc); // qb < 2^24, corrected by one step
+                if (rr * nc > qb) --rr;
+                else if ((rr + 1) * nc <= qb) ++rr;
+                row = (uint32_t)row0 + rr;
+                col = (uint32_t)col0 + (qb - rr * nc);
+            }
             pair_tiles[p] = s_base[lo] + row * s_tx[lo] + (x0w & 0xFFFFu) + col;
             pair_ids[p] = s_id[lo];
         }

@@ -150,6 +150,64 @@ def test_tile_lists_hold_oracle_candidates_in_depth_order(R):
     st.release()
 
 
+def big_convex_scene(n=160, width=1280, height=960, seed=5):
+    """Convexes stretched to 3-10x their size along a random direction (and
+    2-4x across it), so that many tile rectangles exceed 64 tiles and their
+    polygons fill a small part of them."""
+    rng = np.random.default_rng(seed)
+    sc = scenes.convexes_around(rng, scenes.uniform_centres(rng, n, (-0.6,) * 3, (0.6,) * 3), 6, 1)
+    c = sc.points.astype(np.float64).mean(axis=1, keepdims=True)
+    d = rng.normal(size=(n, 1, 3))
+    d /= np.linalg.norm(d, axis=2, keepdims=True)
+    off = sc.points - c
+    along = (off * d).sum(axis=2, keepdims=True)
+    stretch = rng.uniform(3.0, 10.0, (n, 1, 1)) * along * d + rng.uniform(2.0, 4.0, (n, 1, 1)) * (off - along * d)
+    pts = np.ascontiguousarray(c + stretch, dtype=np.float32)
+    scene = Scene(pts, sc.delta, sc.sigma, sc.opacity, sc.sh)
+    return scene, scenes.orbit_camera(rng, width, height, radius=3.0)
+
+
+def test_large_rectangles_are_culled_and_keep_every_candidate(R):
+    """Rectangles of more than 64 tiles drop the bands of blocks that no pixel
+    centre can reach (alpha < eps_alpha there): every tile's list still holds
+    the oracle's candidates, in depth order, and the image matches the
+    oracle."""
+    import oracle
+    scene, cam = big_convex_scene()
+    ds, rgb, st = render_gpu(R, scene, cam, want_state=True)
+    ranges, ids = st.tile_lists()
+    pre = oracle.preprocess(scene, cam)
+    keys = np.array([c.key for c in pre], np.uint64)
+    tx_n = (cam.width + 15) // 16
+    area = np.zeros(scene.n, np.int64)
+    for i, c in enumerate(pre):
+        if (c.status & 0xFF) != 0:
+            continue
+        x0, y0, x1, y1 = c.rect
+        u0, u1 = max(int(np.ceil(x0 - 0.5)), 0), min(int(np.floor(x1 - 0.5)), cam.width - 1)
+        v0, v1 = max(int(np.ceil(y0 - 0.5)), 0), min(int(np.floor(y1 - 0.5)), cam.height - 1)
+        if u0 <= u1 and v0 <= v1:
+            area[i] = (u1 // 16 - u0 // 16 + 1) * (v1 // 16 - v0 // 16 + 1)
+    big = area > 64
+    per = np.bincount(ids, minlength=scene.n)
+    say(f"[big rects] {int(big.sum())} rectangles over 64 tiles: {int(per[big].sum())} pairs kept of "
+        f"{int(area[big].sum())} rectangle tiles")
+    assert big.sum() >= 10
+    assert per[big].sum() < 0.9 * area[big].sum(), "large rectangles were not culled"
+    for t in range(ranges.shape[0]):
+        s0, e0 = ranges[t]
+        lst = ids[s0:e0]
+        assert len(set(lst.tolist())) == len(lst)
+        assert np.all(np.lexsort((lst, keys[lst])) == np.arange(len(lst))), t
+        cand = oracle.tile_candidates(scene, cam, 16, int(t % tx_n), int(t // tx_n))
+        assert set(cand.tolist()) <= set(lst.tolist()), (t, sorted(set(cand) - set(lst)))
+    ref, _, _ = oracle.render(scene, cam)
+    err = float(np.abs(rgb.cpu().numpy().astype(np.float64) - ref).max())
+    say(f"[big rects] {ranges.shape[0]} tiles hold their candidates; image max |gpu - oracle| {err:.2e}")
+    assert err <= PIX_TOL
+    st.release()
+
+
 # --------------------------------------------------------------- forward ----
 
 def forward_parity(R, scene, cam, label, bg=(0.0, 0.0, 0.0)):
