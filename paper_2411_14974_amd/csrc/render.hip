@@ -349,7 +349,7 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4)))
     const FrameHeader *__restrict__ frame, const uint32_t *__restrict__ order, uint32_t *__restrict__ counters,
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ ids,
     const uint8_t *__restrict__ records, RenderArgs ra, uint2 *__restrict__ pixstate,
-    unsigned long long *__restrict__ evalcount)
+    unsigned long long *__restrict__ evalcount, u32x4 *__restrict__ zero_acc, uint32_t zero_n4)
 {
     constexpr int NT = TILE * TILE;
     constexpr int CH = rec_stride(K) / 16;
@@ -373,9 +373,16 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(4)))
     // sizes and wavefront evaluations of the same pairs are counted by the
     // backward walk, where they cost less)
     uint32_t nevals = 0, nfull = 0;
+    // the backward's accumulators (zero_n4 16-byte words, or none) are cleared
+    // here, one slice per tile item, by stores that overlap the compositing
+    const uint32_t zper = total_tiles ? (zero_n4 + total_tiles - 1) / total_tiles : 0u;
     for (;;) {
         const uint32_t item = next_item<FWD_CHUNK>(counters, total_tiles, q, tried, cnext, cend, &s_item);
         if (item == 0xFFFFFFFFu) break;
+        if (zper) {
+            const uint32_t z0 = min(item * zper, zero_n4), z1 = min(z0 + zper, zero_n4);
+            for (uint32_t z = z0 + threadIdx.x; z < z1; z += NT) zero_acc[z] = u32x4{0u, 0u, 0u, 0u};
+        }
         const int gt = order ? (int)order[item] : (int)item;
         const int v = find_view(views, nviews, gt);
         const ViewDesc &vd = views[v];
@@ -690,15 +697,19 @@ template <class F> int persistent_grid(F kernel, int threads)
 // Returns the grid size (the number of evalcount slots written).
 int launch_render_fwd(hipStream_t st, int K, int tile, const FrameHeader *frame, const uint32_t *order,
                       uint32_t max_items, uint32_t *counters, const uint2 *ranges, const uint32_t *ids,
-                      const uint8_t *records, const RenderArgs &ra, uint2 *pixstate, unsigned long long *evalcount)
+                      const uint8_t *records, const RenderArgs &ra, uint2 *pixstate, unsigned long long *evalcount,
+                      float *zero_acc, size_t zero_floats)
 {
+    // the accumulator rows are whole 16-byte words (acc_stride is a multiple of 4)
+    u32x4 *z4 = reinterpret_cast<u32x4 *>(zero_acc);
+    const uint32_t n4 = zero_acc ? (uint32_t)(zero_floats / 4) : 0u;
     if (max_items == 0) return 0;
     int used = 0;
     CS_DISPATCH_K(K, CS_DISPATCH_TILE(tile, {
         auto kern = render_fwd_kernel<KK, TT, BF>;
         const int grid = std::min({persistent_grid(kern, TT * TT), (int)max_items, EVAL_SLOTS});
         hipLaunchKernelGGL(kern, dim3(grid), dim3(TT * TT), 0, st, frame, order, counters, ranges, ids, records, ra,
-                           pixstate, evalcount);
+                           pixstate, evalcount, z4, n4);
         used = grid;
     }));
     return used;

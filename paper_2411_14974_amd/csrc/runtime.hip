@@ -38,7 +38,7 @@ void launch_tile_length_keys(hipStream_t, uint32_t, const uint2 *, uint32_t *, u
 void launch_tile_ranges(hipStream_t, const uint32_t *, uint32_t, const uint32_t *, uint32_t, uint2 *);
 int launch_render_fwd(hipStream_t, int, int, const FrameHeader *, const uint32_t *, uint32_t, uint32_t *,
                        const uint2 *, const uint32_t *, const uint8_t *, const RenderArgs &, uint2 *,
-                       unsigned long long *);
+                       unsigned long long *, float *, size_t);
 int launch_render_bwd(hipStream_t, int, int, const FrameHeader *, const uint32_t *, uint32_t, uint32_t *,
                       const uint2 *, const uint32_t *, const uint8_t *, const RenderArgs &, const uint2 *, float *,
                       unsigned long long *);
@@ -489,6 +489,12 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
     tm.end(CS_STAGE_PREPROCESS);
 
     uint32_t *keys = F.keys, *ids = F.ids, *keys_alt = F.keys_alt, *ids_alt = F.ids_alt;
+    // A frame that holds backward accumulators (from an earlier backward) has
+    // them cleared by the compositing kernel, which leaves HBM mostly idle, so
+    // that the backward that follows skips its clearing pass.  Not under graph
+    // capture: a captured backward clears its accumulators itself.
+    const bool zero_acc = !device_count && F.acc != nullptr;
+    F.acc_zeroed = false;
     // Everything after the pair count: emission, tile sort, ranges, tile order,
     // compositing.  m_dev: the device-side pair count clamped to the buffers, or
     // NULL when the count (M_host) is known here.
@@ -523,7 +529,8 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
         }
         tm.begin();
         F.eval_slots = launch_render_fwd(st, F.K, kn.tile, F.d_frame, F.order, (uint32_t)F.cap_tiles, F.counters, F.ranges,
-                          F.sorted_ids, F.records, ra, F.pixstate, F.evalcount);
+                          F.sorted_ids, F.records, ra, F.pixstate, F.evalcount, zero_acc ? F.acc : nullptr,
+                          zero_acc ? F.ninst * acc_stride(F.K) : 0);
         tm.end(CS_STAGE_RENDER_FWD);
     };
 
@@ -580,16 +587,24 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(CS_EHIP, "kernel launch: %s", hipGetErrorString(e));
+    F.acc_zeroed = zero_acc;
     return CS_OK;
 }
 
-int enqueue_backward(Frame &F, const cs_scene *sc, const cs_grads *g, const RenderArgs &ra, StageTimer &tm)
+// capture: the work is being captured into a graph (which then always clears
+// the accumulators itself).
+int enqueue_backward(Frame &F, const cs_scene *sc, const cs_grads *g, const RenderArgs &ra, StageTimer &tm,
+                     bool capture = false)
 {
     hipStream_t st = F.st;
     int r = F.ensure_acc();
     if (r) return r;
-    launch_zero_ranges(st, reinterpret_cast<uint32_t *>(F.acc), F.ninst * acc_stride(F.K), F.counters + CNT_QUEUE,
-                       QUEUE_WORDS, nullptr, 0);
+    if (F.acc_zeroed && !capture) // cleared by the forward compositing kernel
+        launch_zero_ranges(st, F.counters + CNT_QUEUE, QUEUE_WORDS, nullptr, 0, nullptr, 0);
+    else
+        launch_zero_ranges(st, reinterpret_cast<uint32_t *>(F.acc), F.ninst * acc_stride(F.K), F.counters + CNT_QUEUE,
+                           QUEUE_WORDS, nullptr, 0);
+    F.acc_zeroed = false; // a second backward of the same forward clears them again
     tm.begin();
     F.eval_slots_bwd = launch_render_bwd(st, F.K, F.tile, F.d_frame, F.order, (uint32_t)F.cap_tiles, F.counters,
                                          F.ranges, F.sorted_ids, F.records, ra, F.pixstate, F.acc,
@@ -1047,12 +1062,13 @@ int cs_render_backward_batch(cs_ctx *ctx, const cs_scene *sc, int32_t n_views, c
         if (F->gbwd) { (void)hipGraphExecDestroy(F->gbwd); F->gbwd = nullptr; }
         CS_TRY(F->ensure_acc());
         StageTimer off(ctx, st, false);
-        CS_TRY(capture_graph(ctx, *F, &F->gbwd, [&] { return enqueue_backward(*F, sc, g, ra, off); }));
+        CS_TRY(capture_graph(ctx, *F, &F->gbwd, [&] { return enqueue_backward(*F, sc, g, ra, off, true); }));
         F->kbwd = key;
     }
     StageTimer tm(ctx, st, timing);
     tm.begin();
     CS_HIP(hipGraphLaunch(F->gbwd, st));
+    F->acc_zeroed = false; // the graph's backward has used them
     tm.end(CS_STAGE_GRAPH_BWD);
     return CS_OK;
 }

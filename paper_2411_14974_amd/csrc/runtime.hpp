@@ -51,6 +51,7 @@ struct Frame {
     uint32_t *ord_k = nullptr, *ord_v = nullptr, *ord_k_alt = nullptr, *ord_v_alt = nullptr;
     uint2 *pixstate = nullptr;
     float *acc = nullptr;
+    bool acc_zeroed = false; // acc was cleared by the last forward compositing launch
     uint32_t *counters = nullptr; // CNT_WORDS counters, then the pair-offset scan's look-back status
     size_t counter_words = 0;
     // work counters of the last passes' workgroups: EVAL_SLOTS slots of

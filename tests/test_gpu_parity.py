@@ -150,6 +150,34 @@ def test_tile_lists_hold_oracle_candidates_in_depth_order(R):
     st.release()
 
 
+def test_accumulators_cleared_for_every_backward(R):
+    """The backward's per-convex accumulators are cleared by the forward
+    compositing kernel once the frame holds them: a second backward of the
+    same forward, and the backward of later forwards on reused frames, give
+    the first backward's gradients (up to the order of the float atomics)."""
+    from paper_2411_14974_amd.binding import make_params
+    scene, cam, _ = scenes.config2(n=3000, width=160, height=120)
+    ds = dev(scene)
+    dl = torch.from_numpy(np.random.default_rng(3).normal(size=(cam.height, cam.width, 3)).astype(np.float32)).cuda()
+
+    def rel(a, b):
+        return max(float((a[k].double() - b[k].double()).norm() / b[k].double().norm()) for k in NAMES)
+
+    out, st = R.forward(ds, cam, make_params(), want_state=True)
+    g1 = {k: v.clone() for k, v in R.backward(st, dl).items()}
+    g2 = R.backward(st, dl)
+    torch.cuda.synchronize()
+    worst = rel(g2, g1)
+    st.release()
+    for _ in range(3):
+        out, st = R.forward(ds, cam, make_params(), want_state=True)
+        worst = max(worst, rel(R.backward(st, dl), g1))
+        torch.cuda.synchronize()
+        st.release()
+    say(f"[acc] repeated backwards within {worst:.1e} of the first")
+    assert worst <= 1e-5
+
+
 def big_convex_scene(n=160, width=1280, height=960, seed=5):
     """Convexes stretched to 3-10x their size along a random direction (and
     2-4x across it), so that many tile rectangles exceed 64 tiles and their
