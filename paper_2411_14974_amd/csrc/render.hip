@@ -60,6 +60,36 @@ template <int K> struct PairEval {
         CS_NL_CASE(6, K, __VA_ARGS__) CS_NL_CASE(7, K, __VA_ARGS__) CS_NL_CASE(8, K, __VA_ARGS__) default: break; \
     }
 
+// The FP32 part of a pair evaluation from the line values x (m: their
+// maximum, full: the pair passed the max-line test): softmax weights,
+// LogSumExp, indicator and alpha.  Returns whether the pair contributes.
+template <int K, int NL>
+__device__ __forceinline__ bool finish_pair(const RecHeader &h, const double *x, double m, bool full, float eps,
+                                            PairEval<K> &pe)
+{
+    const float mf = (float)m;
+    float s = 0.0f;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+        const float xf = (float)x[j];
+        const float e = __builtin_amdgcn_exp2f(xf - mf);
+        pe.e[j] = e;
+        pe.x2[j] = xf;
+        s += e;
+    }
+    pe.inv_sum = __builtin_amdgcn_rcpf(s);
+    const float phi2 = mf + __builtin_amdgcn_logf(s);
+    const float z = h.sigma_p * phi2; // I = 1 / (1 + 2^z)
+    const float ez = __builtin_amdgcn_exp2f(-fabsf(z));
+    const float r = __builtin_amdgcn_rcpf(1.0f + ez);
+    pe.I = z > 0.0f ? ez * r : r;
+    pe.omI = z > 0.0f ? r : ez * r;
+    pe.alpha = h.opacity * pe.I;
+    pe.oma = (1.0f - h.opacity) + h.opacity * pe.omI;
+    pe.phi2 = phi2;
+    return full && !(pe.alpha < eps);
+}
+
 // The one evaluation of a (pixel, convex) pair shared by both passes, called
 // by every lane of the wavefront (live: the pixel still takes convexes).
 // Returns whether the pair contributes: the pixel lies in the record's pixel
@@ -105,27 +135,7 @@ __device__ __forceinline__ bool eval_pair(const uint8_t *rec, bool live, int u, 
     // LogSumExp >= its largest term: past thr2 alpha < eps for certain
     full = tested && (m <= (double)h.thr2);
     if (!__any(full)) return false;
-    const float mf = (float)m;
-    float s = 0.0f;
-#pragma unroll
-    for (int j = 0; j < NL; ++j) {
-        const float xf = (float)x[j];
-        const float e = __builtin_amdgcn_exp2f(xf - mf);
-        pe.e[j] = e;
-        pe.x2[j] = xf;
-        s += e;
-    }
-    pe.inv_sum = __builtin_amdgcn_rcpf(s);
-    const float phi2 = mf + __builtin_amdgcn_logf(s);
-    const float z = h.sigma_p * phi2; // I = 1 / (1 + 2^z)
-    const float ez = __builtin_amdgcn_exp2f(-fabsf(z));
-    const float r = __builtin_amdgcn_rcpf(1.0f + ez);
-    pe.I = z > 0.0f ? ez * r : r;
-    pe.omI = z > 0.0f ? r : ez * r;
-    pe.alpha = h.opacity * pe.I;
-    pe.oma = (1.0f - h.opacity) + h.opacity * pe.omI;
-    pe.phi2 = phi2;
-    return full && !(pe.alpha < eps);
+    return finish_pair<K, NL>(h, x, m, full, eps, pe);
 }
 
 // Row sums: after it every lane of each 16-lane row holds that row's sum of
@@ -178,13 +188,13 @@ template <int TILE> __device__ __forceinline__ void tile_pixel(int &dx, int &dy)
 }
 
 
-// Can a record reach alpha >= eps_alpha at a pixel centre of the 8x8 square
-// [su, su + 7] x [sv, sv + 7]?  Its pixel box must meet the square, and no
+// Can a record reach alpha >= eps_alpha at a pixel centre of the RW x RH
+// rectangle [su, su + RW - 1] x [sv, sv + RH - 1] (a wavefront's pixels)?  Its pixel box must meet the square, and no
 // hull line may keep x2 above the skip threshold over all pixel centres of
 // the square's part of the box (then the pair evaluation skips every one of
 // them).  A line's minimum over a rectangle is at a corner; the margin covers
 // the rounding of this test and of the pair evaluation.
-template <int K> __device__ __forceinline__ bool square_meets(const uint8_t *rec, int su, int sv)
+template <int K, int RW = 8, int RH = 8> __device__ __forceinline__ bool square_meets(const uint8_t *rec, int su, int sv)
 {
     const RecHeader h = *reinterpret_cast<const RecHeader *>(rec);
     double L[3 * K + 1];
@@ -195,8 +205,8 @@ template <int K> __device__ __forceinline__ bool square_meets(const uint8_t *rec
         L[2 * q] = w.x;
         L[2 * q + 1] = w.y;
     }
-    const int u0 = max(su, (int)(h.box_u & 0xFFFFu)), u1 = min(su + 7, (int)(h.box_u >> 16));
-    const int v0 = max(sv, (int)(h.box_v & 0xFFFFu)), v1 = min(sv + 7, (int)(h.box_v >> 16));
+    const int u0 = max(su, (int)(h.box_u & 0xFFFFu)), u1 = min(su + RW - 1, (int)(h.box_u >> 16));
+    const int v0 = max(sv, (int)(h.box_v & 0xFFFFu)), v1 = min(sv + RH - 1, (int)(h.box_v >> 16));
     if (u0 > u1 || v0 > v1) return false;
     const double a0 = (double)u0 + 0.5 - (double)h.ox, a1 = (double)u1 + 0.5 - (double)h.ox;
     const double c0 = (double)v0 + 0.5 - (double)h.oy, c1 = (double)v1 + 0.5 - (double)h.oy;
@@ -480,10 +490,59 @@ template <int K> __device__ __forceinline__ int acc_slot(int qv, int T)
 // forward's decisions, bit for bit), recover T_n, form the pixel's gradient
 // values, sum them over the wavefront and add the four row sums into the
 // record's LDS slot (compact layout, bwd_padded<K>() floats).
+// A pixel's state in the back-to-front walk: dL/dC, the transmittance after
+// its last contributor, the transmittance before the pair being walked (T_n,
+// recovered by division), and the colour composited behind it.
+struct BwdPixel {
+    float g0, g1, g2, Tlast, Tcur, B0, B1, B2;
+    bool first;
+};
+
+// A pixel's compact gradient values of one record (see bwd_values), stored
+// into val (ADD: added to it), and the pixel's walk advanced past the record.
+template <int K, int NL, bool ADD>
+__device__ __forceinline__ void pixel_values(const RecHeader &h, const PairEval<K> &pe, bool contrib, BwdPixel &P,
+                                             float pxf, float pyf, float *val)
+{
+    // branch-free: a lane that does not contribute takes Tn = 0, which zeroes
+    // all of its values (every pe field is finite)
+    const float Tn = contrib ? (P.first ? P.Tlast : P.Tcur * __builtin_amdgcn_rcpf(pe.oma)) : 0.0f;
+    const float dLda = Tn * (P.g0 * (h.rgb[0] - P.B0) + P.g1 * (h.rgb[1] - P.B1) + P.g2 * (h.rgb[2] - P.B2));
+    const float ta = Tn * pe.alpha;
+    float v[bwd_values<NL>()];
+    v[3 * NL + 2] = P.g0 * ta;
+    v[3 * NL + 3] = P.g1 * ta;
+    v[3 * NL + 4] = P.g2 * ta;
+    v[3 * NL + 1] = dLda * pe.I;
+    const float dLdz = -dLda * h.opacity * pe.I * pe.omI; // I = Sigmoid(-z), z = sigma' phi
+    v[3 * NL] = dLdz * pe.phi2 * (float)LN2;
+    const float dLdphi2 = dLdz * h.sigma_p * (float)LN2;
+    const float gs = dLdphi2 * pe.inv_sum; // dL/dx2_j = gs e_j (softmax weights)
+    const float dxf = pxf - h.ox, dyf = pyf - h.oy;
+    float gdl = 0.0f;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+        const float gx = gs * pe.e[j];
+        v[j] = gx * dxf;
+        v[NL + j] = gx * dyf;
+        v[2 * NL + j] = gx;
+        gdl = fmaf(gx, pe.x2[j], gdl);
+    }
+    v[3 * NL + 5] = gdl;
+#pragma unroll
+    for (int qv = 0; qv < bwd_values<NL>(); ++qv) val[qv] = ADD ? val[qv] + v[qv] : v[qv];
+    if (contrib) {
+        P.first = false;
+        P.Tcur = Tn;
+        P.B0 = fmaf(pe.alpha, h.rgb[0], pe.oma * P.B0);
+        P.B1 = fmaf(pe.alpha, h.rgb[1], pe.oma * P.B1);
+        P.B2 = fmaf(pe.alpha, h.rgb[2], pe.oma * P.B2);
+    }
+}
+
 template <int K, int NL>
 __device__ __forceinline__ void bwd_record(const uint8_t *rec, bool live, int u, int y, float pxf, float pyf,
-                                           float eps, float g0, float g1, float g2, float Tlast, float &Tcur,
-                                           bool &first, float &B0, float &B1, float &B2, float *slot, bool &full)
+                                           float eps, BwdPixel &P, float *slot, bool &full)
 {
     constexpr int NP = bwd_padded<NL>();
     constexpr int Q = NP / 4;
@@ -492,40 +551,10 @@ __device__ __forceinline__ void bwd_record(const uint8_t *rec, bool live, int u,
     const bool contrib = eval_pair<K, NL>(rec, live, u, y, pxf, pyf, eps, pe, tested, full);
     if (__ballot(contrib) == 0ull) return; // wave-uniform
     const RecHeader &h = *reinterpret_cast<const RecHeader *>(rec);
-    // branch-free: a lane that does not contribute takes Tn = 0, which zeroes
-    // all of its values (every pe field is finite)
-    const float Tn = contrib ? (first ? Tlast : Tcur * __builtin_amdgcn_rcpf(pe.oma)) : 0.0f;
-    const float dLda = Tn * (g0 * (h.rgb[0] - B0) + g1 * (h.rgb[1] - B1) + g2 * (h.rgb[2] - B2));
-    const float ta = Tn * pe.alpha;
     float val[NP];
-    val[3 * NL + 2] = g0 * ta;
-    val[3 * NL + 3] = g1 * ta;
-    val[3 * NL + 4] = g2 * ta;
-    val[3 * NL + 1] = dLda * pe.I;
-    const float dLdz = -dLda * h.opacity * pe.I * pe.omI; // I = Sigmoid(-z), z = sigma' phi
-    val[3 * NL] = dLdz * pe.phi2 * (float)LN2;
-    const float dLdphi2 = dLdz * h.sigma_p * (float)LN2;
-    const float gs = dLdphi2 * pe.inv_sum; // dL/dx2_j = gs e_j (softmax weights)
-    const float dxf = pxf - h.ox, dyf = pyf - h.oy;
-    float gdl = 0.0f;
-#pragma unroll
-    for (int j = 0; j < NL; ++j) {
-        const float gx = gs * pe.e[j];
-        val[j] = gx * dxf;
-        val[NL + j] = gx * dyf;
-        val[2 * NL + j] = gx;
-        gdl = fmaf(gx, pe.x2[j], gdl);
-    }
-    val[3 * NL + 5] = gdl;
+    pixel_values<K, NL, false>(h, pe, contrib, P, pxf, pyf, val);
 #pragma unroll
     for (int qv = bwd_values<NL>(); qv < NP; ++qv) val[qv] = 0.0f;
-    if (contrib) {
-        first = false;
-        Tcur = Tn;
-        B0 = fmaf(pe.alpha, h.rgb[0], pe.oma * B0);
-        B1 = fmaf(pe.alpha, h.rgb[1], pe.oma * B1);
-        B2 = fmaf(pe.alpha, h.rgb[2], pe.oma * B2);
-    }
     // whole-wave sums even when few lanes contribute: lane-by-lane LDS atomics
     // serialise badly when a record covers the square
     wave_sums<NP>(val);
@@ -582,17 +611,18 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
         const float pxf = (float)u + 0.5f, pyf = (float)y + 0.5f;
         const int start = (int)ranges[gt].x;
 
-        float g0 = 0.f, g1 = 0.f, g2 = 0.f, Tlast = 1.f;
+        BwdPixel P{0.f, 0.f, 0.f, 1.f, 1.f, ra.bg[0], ra.bg[1], ra.bg[2], true};
         int nend = 0;
         if (inside) {
             const size_t pix = (size_t)y * W + u;
             const float *g = vd.dl_drgb + 3 * pix;
-            g0 = g[0];
-            g1 = g[1];
-            g2 = g[2];
+            P.g0 = g[0];
+            P.g1 = g[1];
+            P.g2 = g[2];
             const uint2 ps = pixstate[vd.pix_off + pix];
             nend = (int)ps.x;
-            Tlast = __uint_as_float(ps.y);
+            P.Tlast = __uint_as_float(ps.y);
+            P.Tcur = P.Tlast;
         }
         if (threadIdx.x == 0) s_maxn = 0;
         __syncthreads();
@@ -603,9 +633,6 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) wmaxn = max(wmaxn, __shfl_xor(wmaxn, o, 64));
 
-        float B0 = ra.bg[0], B1 = ra.bg[1], B2 = ra.bg[2];
-        float Tcur = Tlast;
-        bool first = true;
         // batches walk the list back to front (the walk is VALU-bound: plain loads,
         // no prefetch registers)
         for (int hi = maxn; hi > 0; hi -= BATCH) {
@@ -628,8 +655,7 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
                 const int Tr = __builtin_amdgcn_readlane(myT, e);
                 const bool live = lo + e < nend;
                 bool full = false;
-                CS_DISPATCH_NL(K, Tr, bwd_record<K, NLL>(rec, live, u, y, pxf, pyf, ra.eps_alpha, g0, g1, g2, Tlast, Tcur,
-                                                         first, B0, B1, B2, &s_acc[e * NP], full));
+                CS_DISPATCH_NL(K, Tr, bwd_record<K, NLL>(rec, live, u, y, pxf, pyf, ra.eps_alpha, P, &s_acc[e * NP], full));
                 nfull += full;
                 nsumT += full ? (uint32_t)Tr : 0u;
                 nwave += __any(full) ? 1u : 0u;
@@ -653,6 +679,7 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
 }
 
 // ------------------------------------------------------------- launchers ---
+
 
 #define CS_DISPATCH_K(K, ...)                                                                                      \
     switch (K) {                                                                                                   \
