@@ -235,6 +235,8 @@ def bench_serving(rates, duration, max_batch=4, workers=2):
                          "mean_queue_ms": window_mean(st0, st, "mean_queue_ms"),
                          "mean_run_ms": window_mean(st0, st, "mean_run_ms"),
                          "frame_gb": st["frame_bytes"] / 1e9})
+            print(f"[serve] {mode} {rate:g} req/s: {len(ids)} requests, p99 {rows[-1]['p99_ms']:.2f} ms",
+                  file=sys.stderr, flush=True)
         R.serve_stop()
         out["modes"][mode] = rows
     R.close()
