@@ -587,7 +587,7 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(CS_EHIP, "kernel launch: %s", hipGetErrorString(e));
-    F.acc_zeroed = zero_acc;
+    F.acc_zeroed = zero_acc && F.eval_slots > 0; // the compositing kernel ran (and cleared them)
     return CS_OK;
 }
 
