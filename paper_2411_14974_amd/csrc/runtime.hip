@@ -105,10 +105,18 @@ void Frame::release_buffer(void *p)
         }
 }
 
-Frame::~Frame()
+void Frame::drop_graphs()
 {
     if (gfwd) (void)hipGraphExecDestroy(gfwd);
     if (gbwd) (void)hipGraphExecDestroy(gbwd);
+    if (gbwd_nz) (void)hipGraphExecDestroy(gbwd_nz);
+    gfwd = gbwd = gbwd_nz = nullptr;
+    gfwd_zero = false;
+}
+
+Frame::~Frame()
+{
+    drop_graphs();
     for (void *p : allocs)
         if (p) (void)hipFreeAsync(p, st);
     if (counters_ev) (void)hipEventSynchronize(counters_ev), (void)hipEventDestroy(counters_ev);
@@ -491,9 +499,10 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
     uint32_t *keys = F.keys, *ids = F.ids, *keys_alt = F.keys_alt, *ids_alt = F.ids_alt;
     // A frame that holds backward accumulators (from an earlier backward) has
     // them cleared by the compositing kernel, which leaves HBM mostly idle, so
-    // that the backward that follows skips its clearing pass.  Not under graph
-    // capture: a captured backward clears its accumulators itself.
-    const bool zero_acc = !device_count && F.acc != nullptr;
+    // that the backward that follows skips its clearing pass (under graph
+    // capture too: the batched backward keeps a graph with and one without
+    // its clearing pass and replays the one that matches).
+    const bool zero_acc = F.acc != nullptr;
     F.acc_zeroed = false;
     // Everything after the pair count: emission, tile sort, ranges, tile order,
     // compositing.  m_dev: the device-side pair count clamped to the buffers, or
@@ -591,15 +600,15 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
     return CS_OK;
 }
 
-// capture: the work is being captured into a graph (which then always clears
-// the accumulators itself).
+// clear: clear the accumulators first (false when the forward compositing
+// kernel has cleared them since their last use).
 int enqueue_backward(Frame &F, const cs_scene *sc, const cs_grads *g, const RenderArgs &ra, StageTimer &tm,
-                     bool capture = false)
+                     bool clear)
 {
     hipStream_t st = F.st;
     int r = F.ensure_acc();
     if (r) return r;
-    if (F.acc_zeroed && !capture) // cleared by the forward compositing kernel
+    if (!clear)
         launch_zero_ranges(st, F.counters + CNT_QUEUE, QUEUE_WORDS, nullptr, 0, nullptr, 0);
     else
         launch_zero_ranges(st, reinterpret_cast<uint32_t *>(F.acc), F.ninst * acc_stride(F.K), F.counters + CNT_QUEUE,
@@ -972,12 +981,18 @@ int cs_render_forward_batch(cs_ctx *ctx, const cs_scene *sc, int32_t n_views, co
         ctx->batch_key = key;
     } else {
         CS_TRY(F->upload_views(vp.hdr, vp.views.data()));
+        if (F->gfwd && F->acc && !F->gfwd_zero) { // accumulators appeared: capture again with their clearing
+            (void)hipGraphExecDestroy(F->gfwd);
+            F->gfwd = nullptr;
+        }
         if (!F->gfwd) {
             StageTimer off(ctx, st, false);
             CS_TRY(capture_graph(ctx, *F, &F->gfwd, [&] { return enqueue_forward(ctx, *F, sc, ra, kn, true, 1.0, off); }));
+            F->gfwd_zero = F->acc != nullptr;
         }
         tm.begin();
         CS_HIP(hipGraphLaunch(F->gfwd, st));
+        F->acc_zeroed = F->gfwd_zero;
         tm.end(CS_STAGE_GRAPH_FWD);
     }
     F->epoch++;
@@ -1013,8 +1028,7 @@ int cs_batch_check(cs_ctx *ctx, const cs_fwd_state *s)
     if (F->h_counters[CNT_OVERFLOW]) {
         const size_t m = F->h_counters[CNT_PAIRS];
         CS_HIP(hipStreamSynchronize(F->st));
-        if (F->gfwd) { (void)hipGraphExecDestroy(F->gfwd); F->gfwd = nullptr; }
-        if (F->gbwd) { (void)hipGraphExecDestroy(F->gbwd); F->gbwd = nullptr; }
+        F->drop_graphs();
         int r = F->ensure_pairs((size_t)std::ceil(m * 1.3));
         if (r) return r;
         return fail(CS_EOVERFLOW, "frame needed %zu (convex, tile) pairs; buffers grown, render it again", m);
@@ -1052,22 +1066,28 @@ int cs_render_backward_batch(cs_ctx *ctx, const cs_scene *sc, int32_t n_views, c
     const bool timing = prm && (prm->flags & CS_FLAG_TIMING);
     if (state->owned || !(prm && (prm->flags & CS_FLAG_GRAPH))) {
         StageTimer tm(ctx, st, timing);
-        return enqueue_backward(*F, sc, g, ra, tm);
+        return enqueue_backward(*F, sc, g, ra, tm, !F->acc_zeroed);
     }
     uint64_t key = 1469598103934665603ull;
     for (uint64_t v : {(uint64_t)(uintptr_t)g->points, (uint64_t)(uintptr_t)g->delta, (uint64_t)(uintptr_t)g->sigma,
                        (uint64_t)(uintptr_t)g->opacity, (uint64_t)(uintptr_t)g->sh})
         key = mix(key, v);
-    if (!F->gbwd || F->kbwd != key) {
+    if (F->kbwd != key) { // other gradient buffers: both backward graphs are stale
         if (F->gbwd) { (void)hipGraphExecDestroy(F->gbwd); F->gbwd = nullptr; }
+        if (F->gbwd_nz) { (void)hipGraphExecDestroy(F->gbwd_nz); F->gbwd_nz = nullptr; }
+        F->kbwd = key;
+    }
+    // the graph without the clearing pass when the forward has cleared the accumulators
+    const bool cleared = F->acc_zeroed;
+    hipGraphExec_t &gx = cleared ? F->gbwd_nz : F->gbwd;
+    if (!gx) {
         CS_TRY(F->ensure_acc());
         StageTimer off(ctx, st, false);
-        CS_TRY(capture_graph(ctx, *F, &F->gbwd, [&] { return enqueue_backward(*F, sc, g, ra, off, true); }));
-        F->kbwd = key;
+        CS_TRY(capture_graph(ctx, *F, &gx, [&] { return enqueue_backward(*F, sc, g, ra, off, !cleared); }));
     }
     StageTimer tm(ctx, st, timing);
     tm.begin();
-    CS_HIP(hipGraphLaunch(F->gbwd, st));
+    CS_HIP(hipGraphLaunch(gx, st));
     F->acc_zeroed = false; // the graph's backward has used them
     tm.end(CS_STAGE_GRAPH_BWD);
     return CS_OK;

@@ -66,9 +66,12 @@ struct Frame {
     uint32_t *sorted_ids = nullptr;
     uint32_t *order = nullptr;
 
-    // captured graphs (batched path)
-    hipGraphExec_t gfwd = nullptr, gbwd = nullptr;
+    // captured graphs (batched path): the forward (gfwd_zero: it clears the
+    // backward's accumulators), the backward with and without its clearing pass
+    hipGraphExec_t gfwd = nullptr, gbwd = nullptr, gbwd_nz = nullptr;
+    bool gfwd_zero = false;
     uint64_t kbwd = 0;
+    void drop_graphs();
     uint64_t epoch = 0;
 
     HostRing *ring = nullptr;

@@ -206,6 +206,33 @@ def test_graph_replay_matches_eager_with_changing_cameras(R):
     say("[graph] 6 replays (2 camera sets) equal eager forward and backward")
 
 
+def test_graph_backward_twice_after_one_forward(R):
+    """The batched graphs clear the backward's accumulators in the forward's
+    compositing once the frame holds them; a second backward of the same
+    forward (the graph with its own clearing pass) gives the first's
+    gradients, and so does the backward of a later forward."""
+    from paper_2411_14974_amd.binding import FLAG_GRAPH, make_params
+    scene, cams = small_batch(n=15000, views=4, seed=4)
+    ds = dev(scene)
+    pg = make_params(flags=FLAG_GRAPH)
+    rng = np.random.default_rng(5)
+    dls = [torch.from_numpy(rng.normal(size=(c.height, c.width, 3)).astype(np.float32)).cuda() for c in cams]
+    ref = None
+    for rep in range(3):  # frame creation, capture with clearing, replay
+        outs, st = R.forward_batch(ds, cams, pg, want_state=True)
+        g1 = {k: v.clone() for k, v in R.backward_batch(st, dls).items()}
+        g2 = R.backward_batch(st, dls)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = g1
+        for k in NAMES:
+            assert grads_close(g2[k], g1[k]), (rep, k, grad_gap(g2[k], g1[k]))
+            assert grads_close(g1[k], ref[k]), (rep, k, grad_gap(g1[k], ref[k]))
+        assert R.batch_check(st) == 0
+        st.release()
+    say("[graph] repeated backwards of one forward and later forwards agree")
+
+
 def test_graph_overflow_is_reported_and_recovers(R):
     from paper_2411_14974_amd.binding import CS_EOVERFLOW, FLAG_GRAPH, Camera, make_camera, make_params
     scene, cams = small_batch(n=20000, views=2, seed=4, res=((256, 160),))
