@@ -28,7 +28,7 @@ void radix_sort(hipStream_t, uint32_t **, uint32_t **, uint32_t **, uint32_t **,
 size_t sort_temp_words(uint32_t, int, int);
 size_t scan_status_words(uint32_t);
 void launch_gather_scan(hipStream_t, uint32_t, const uint32_t *, const uint4 *, uint4 *, uint32_t *, uint32_t *,
-                        uint32_t *);
+                        uint32_t *, uint32_t *);
 void launch_fill_u32(hipStream_t, uint32_t *, size_t, uint32_t);
 void launch_emit_pairs(hipStream_t, uint32_t, uint32_t, const uint32_t *, const uint32_t *, const uint32_t *,
                        const uint4 *, const FrameHeader *, uint32_t, uint32_t *, uint32_t *);
@@ -135,8 +135,10 @@ int HostRing::init()
         if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess)
             return fail(CS_EHIP, "event creation failed");
     }
-    if (hipHostMalloc((void **)&h_word, 64, hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void **)&h_word, 64, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
         return fail(CS_ENOMEM, "pinned allocation failed");
+    if (hipHostGetDevicePointer((void **)&d_word, h_word, 0) != hipSuccess)
+        return fail(CS_EHIP, "pinned word has no device address");
     return CS_OK;
 }
 
@@ -185,6 +187,9 @@ int Frame::init(int n_, int K_, int deg_, int V_, size_t tiles, size_t pix, hipS
     const uint32_t ui = (uint32_t)cap_inst;
 #define CS_A(ptr, bytes) do { int r_ = alloc((void **)&(ptr), (bytes)); if (r_) return r_; } while (0)
     CS_A(d_frame, VIEW_TABLE_BYTES);
+    CS_A(d_frame_b, VIEW_TABLE_BYTES);
+    table_sent[0].clear();
+    table_sent[1].clear();
     CS_A(records, cap_inst * rec_stride(K));
     CS_A(keys, cap_inst * 4);
     CS_A(ids, cap_inst * 4);
@@ -262,6 +267,9 @@ int Frame::bind(uint8_t *base, size_t bytes, int n_, int K_, int deg_, size_t ti
         return (void *)p;
     };
     d_frame = (FrameHeader *)carve(VIEW_TABLE_BYTES);
+    d_frame_b = (FrameHeader *)carve(VIEW_TABLE_BYTES);
+    table_sent[0].clear();
+    table_sent[1].clear();
     records = (uint8_t *)carve(cap_inst * rec_stride(K));
     keys = (uint32_t *)carve(cap_inst * 4);
     ids = (uint32_t *)carve(cap_inst * 4);
@@ -312,8 +320,13 @@ int Frame::bind(uint8_t *base, size_t bytes, int n_, int K_, int deg_, size_t ti
 }
 
 // Upload the view table through the context's ring of pinned staging buffers.
-int Frame::upload_views(const FrameHeader &hdr, const ViewDesc *views)
+int Frame::upload_views(const FrameHeader &hdr, const ViewDesc *views, int table)
 {
+    const size_t bytes = sizeof(FrameHeader) + sizeof(ViewDesc) * hdr.nviews;
+    std::vector<char> &sent = table_sent[table];
+    if (table_stream[table] == st && sent.size() == bytes && std::memcmp(sent.data(), &hdr, sizeof(hdr)) == 0 &&
+        std::memcmp(sent.data() + sizeof(FrameHeader), views, bytes - sizeof(FrameHeader)) == 0)
+        return CS_OK; // the table on the device is this one (its upload is ordered before this stream's work)
     HostRing::Slot &sg = ring->slot[ring->next];
     ring->next = (ring->next + 1) % (int)(sizeof(ring->slot) / sizeof(ring->slot[0]));
     if (sg.used) {
@@ -322,11 +335,15 @@ int Frame::upload_views(const FrameHeader &hdr, const ViewDesc *views)
     }
     std::memcpy(sg.host, &hdr, sizeof(hdr));
     std::memcpy((char *)sg.host + sizeof(FrameHeader), views, sizeof(ViewDesc) * hdr.nviews);
-    const size_t bytes = sizeof(FrameHeader) + sizeof(ViewDesc) * hdr.nviews;
-    hipError_t e = hipMemcpyAsync(d_frame, sg.host, bytes, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return fail(CS_EHIP, "view table upload: %s", hipGetErrorString(e));
+    hipError_t e = hipMemcpyAsync(table ? d_frame_b : d_frame, sg.host, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+        sent.clear();
+        return fail(CS_EHIP, "view table upload: %s", hipGetErrorString(e));
+    }
     (void)hipEventRecord(sg.ev, st);
     sg.used = true;
+    sent.assign((const char *)sg.host, (const char *)sg.host + bytes);
+    table_stream[table] = st;
     return CS_OK;
 }
 
@@ -560,11 +577,12 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
         radix_sort(st, &keys, &ids, &keys_alt, &ids_alt, ninst, nullptr, ninst, 32, F.hist, 8, F.counters + CNT_SORT_ERR);
         tm.end(CS_STAGE_DEPTH_SORT);
         tm.begin();
-        launch_gather_scan(st, ninst, ids, F.bins, F.bins_sorted, F.counts_sorted, F.offsets, F.counters);
+        // the count also goes straight to pinned host memory (no copy in the stream)
+        launch_gather_scan(st, ninst, ids, F.bins, F.bins_sorted, F.counts_sorted, F.offsets, F.counters,
+                           device_count ? nullptr : F.ring->d_word);
         tm.end(CS_STAGE_BIN_SCAN);
         if (!device_count) {
-            hipError_t e = hipMemcpyAsync(hw, F.counters + CNT_PAIRS, 4, hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipEventRecord(F.mcount_ev, st);
+            hipError_t e = hipEventRecord(F.mcount_ev, st);
             // a new frame waits for its count here (polling: a blocking wait wakes up late and the GPU idles)
             if (e == hipSuccess && !speculative) e = spin_wait(F.mcount_ev);
             if (e != hipSuccess) return fail(CS_EHIP, "pair count read-back: %s", hipGetErrorString(e));
@@ -615,12 +633,12 @@ int enqueue_backward(Frame &F, const cs_scene *sc, const cs_grads *g, const Rend
                            QUEUE_WORDS, nullptr, 0);
     F.acc_zeroed = false; // a second backward of the same forward clears them again
     tm.begin();
-    F.eval_slots_bwd = launch_render_bwd(st, F.K, F.tile, F.d_frame, F.order, (uint32_t)F.cap_tiles, F.counters,
+    F.eval_slots_bwd = launch_render_bwd(st, F.K, F.tile, F.d_frame_b, F.order, (uint32_t)F.cap_tiles, F.counters,
                                          F.ranges, F.sorted_ids, F.records, ra, F.pixstate, F.acc,
                                          F.evalcount + (size_t)EVAL_SLOTS * EVAL_FIELDS);
     tm.end(CS_STAGE_RENDER_BWD);
     tm.begin();
-    launch_preprocess_bwd(st, sc->n, F.V, F.K, F.deg, sc->dtype, sc->points, sc->delta, sc->sigma, sc->sh, F.d_frame,
+    launch_preprocess_bwd(st, sc->n, F.V, F.K, F.deg, sc->dtype, sc->points, sc->delta, sc->sigma, sc->sh, F.d_frame_b,
                           F.hullpk, F.acc, g->points, g->delta, g->sigma, g->opacity, g->sh);
     tm.end(CS_STAGE_PREPROCESS_BWD);
     hipError_t e = hipGetLastError();
@@ -1062,7 +1080,7 @@ int cs_render_backward_batch(cs_ctx *ctx, const cs_scene *sc, int32_t n_views, c
     if (vp.hdr.total_tiles > F->cap_tiles || (size_t)vp.hdr.total_pix > F->cap_pix)
         return fail(CS_EINVAL, "cameras differ from the forward call");
     F->st = st;
-    CS_TRY(F->upload_views(vp.hdr, vp.views.data()));
+    CS_TRY(F->upload_views(vp.hdr, vp.views.data(), 1));
     const bool timing = prm && (prm->flags & CS_FLAG_TIMING);
     if (state->owned || !(prm && (prm->flags & CS_FLAG_GRAPH))) {
         StageTimer tm(ctx, st, timing);

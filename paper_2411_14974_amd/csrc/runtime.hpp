@@ -23,7 +23,8 @@ struct HostRing {
         bool used = false;
     } slot[8];
     int next = 0;
-    uint32_t *h_word = nullptr; // pinned words for synchronous read-backs
+    uint32_t *h_word = nullptr; // coherent pinned words for read-backs (kernels write them directly)
+    uint32_t *d_word = nullptr; // the device's address of h_word
     int init();
     ~HostRing();
 };
@@ -40,7 +41,12 @@ struct Frame {
     std::vector<void *> allocs;
     size_t bytes_held = 0;
 
-    FrameHeader *d_frame = nullptr; // header + ViewDesc[MAX_VIEWS]
+    FrameHeader *d_frame = nullptr;   // header + ViewDesc[MAX_VIEWS]: the forward's view table
+    FrameHeader *d_frame_b = nullptr; // the backward's (its views carry dL/dC instead of the output)
+    // the bytes last uploaded to each table and the stream of that upload: an
+    // identical table on the same stream is not sent again
+    std::vector<char> table_sent[2];
+    hipStream_t table_stream[2] = {nullptr, nullptr};
     uint8_t *records = nullptr;
     uint32_t *keys = nullptr, *ids = nullptr, *keys_alt = nullptr, *ids_alt = nullptr;
     uint32_t *counts_sorted = nullptr, *offsets = nullptr, *hullpk = nullptr;
@@ -88,7 +94,7 @@ struct Frame {
     void release_buffer(void *p);
     int ensure_pairs(size_t m);
     int ensure_acc();
-    int upload_views(const FrameHeader &hdr, const ViewDesc *views);
+    int upload_views(const FrameHeader &hdr, const ViewDesc *views, int table = 0);
     ~Frame();
 };
 

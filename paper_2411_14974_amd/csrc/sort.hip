@@ -78,10 +78,13 @@ __device__ __forceinline__ void ss_store(uint64_t *p, uint64_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// host_pairs (nullable): a word of coherent pinned host memory that also
+// receives the pair count (the host reads it after an event, with no copy in
+// the stream).
 __global__ __launch_bounds__(SCAN_BLOCK) void gather_scan_kernel(
     uint32_t n, const uint32_t *__restrict__ sorted_ids, const uint4 *__restrict__ bins,
     uint4 *__restrict__ bins_sorted, uint32_t *__restrict__ counts_sorted, uint32_t *__restrict__ offsets,
-    uint32_t *__restrict__ counters, uint64_t *__restrict__ status)
+    uint32_t *__restrict__ counters, uint64_t *__restrict__ status, uint32_t *__restrict__ host_pairs)
 {
     __shared__ uint32_t s[SCAN_TILE + SCAN_TILE / 32];
     __shared__ uint32_t s_wave[SCAN_BLOCK / 64];
@@ -139,7 +142,12 @@ __global__ __launch_bounds__(SCAN_BLOCK) void gather_scan_kernel(
         }
         if (tid == 0) {
             s_excl = excl;
-            if (base + SCAN_TILE >= n) counters[CNT_PAIRS] = (uint32_t)(excl + tile_total);
+            if (base + SCAN_TILE >= n) {
+                counters[CNT_PAIRS] = (uint32_t)(excl + tile_total);
+                if (host_pairs)
+                    __hip_atomic_store(host_pairs, (uint32_t)(excl + tile_total), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+            }
         }
     }
     __syncthreads();
@@ -158,12 +166,14 @@ size_t scan_status_words(uint32_t n) { return 2 * (((size_t)n + SCAN_TILE - 1) /
 // offsets = their exclusive scan, counters[CNT_PAIRS] = the total.  counters
 // must hold CNT_WORDS words, zeroed, followed by scan_status_words(n) zeroed words.
 void launch_gather_scan(hipStream_t st, uint32_t n, const uint32_t *sorted_ids, const uint4 *bins,
-                        uint4 *bins_sorted, uint32_t *counts_sorted, uint32_t *offsets, uint32_t *counters)
+                        uint4 *bins_sorted, uint32_t *counts_sorted, uint32_t *offsets, uint32_t *counters,
+                        uint32_t *host_pairs)
 {
     if (n == 0) return;
     const uint32_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     hipLaunchKernelGGL(gather_scan_kernel, dim3(tiles), dim3(SCAN_BLOCK), 0, st, n, sorted_ids, bins, bins_sorted,
-                       counts_sorted, offsets, counters, reinterpret_cast<uint64_t *>(counters + CNT_STATUS));
+                       counts_sorted, offsets, counters, reinterpret_cast<uint64_t *>(counters + CNT_STATUS),
+                       host_pairs);
 }
 
 // ----------------------------------------------------------- radix sort ----
