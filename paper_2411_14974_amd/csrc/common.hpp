@@ -165,16 +165,19 @@ __device__ inline uint32_t bin_count(uint4 b)
 //   [0, CNT_WORDS)            counters read back by the host:
 //     CNT_SORT_ERR: a radix-sort look-back wait ran out of its bound (never expected)
 //     CNT_SCAN_TILE: tile claims of the pair-offset scan
-//   [CNT_QUEUE, CNT_STATUS)   the compositing work queues' claim counters, one
-//                             per QUEUE_STRIDE words: device-scope atomics on
-//                             one memory block serialise, so each queue's
-//                             counter sits in a block of its own
+//   [CNT_QUEUE, CNT_QUEUE_B)  the forward compositing's work queues' claim
+//                             counters, one per QUEUE_STRIDE words: device-scope
+//                             atomics on one memory block serialise, so each
+//                             queue's counter sits in a block of its own
+//   [CNT_QUEUE_B, CNT_STATUS) the backward compositing's (cleared with the rest
+//                             when the forward starts)
 //   [CNT_STATUS, ...)         the pair-offset scan's look-back status (u64 per tile)
 enum : int { CNT_PAIRS = 0, CNT_PAIRS_EFF = 1, CNT_OVERFLOW = 2, CNT_SORT_ERR = 3, CNT_SCAN_TILE = 20, CNT_WORDS = 32 };
 constexpr int QUEUE_STRIDE = 1024; // 4 KiB
 constexpr int CNT_QUEUE = CNT_WORDS;
 constexpr int QUEUE_WORDS = NUM_QUEUES * QUEUE_STRIDE;
-constexpr int CNT_STATUS = CNT_QUEUE + QUEUE_WORDS;
+constexpr int CNT_QUEUE_B = CNT_QUEUE + QUEUE_WORDS;
+constexpr int CNT_STATUS = CNT_QUEUE_B + QUEUE_WORDS;
 
 // Host-visible debug record (mirrors cs_debug_convex of the public header).
 struct DebugConvex {

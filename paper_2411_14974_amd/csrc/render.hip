@@ -280,7 +280,7 @@ __device__ __forceinline__ void pipe_store_records(const u32x4 (&pre)[NL], uint4
 // CHUNK items are claimed per atomic (the workgroup keeps the rest of its
 // run in cnext..cend).
 template <uint32_t CHUNK>
-__device__ __forceinline__ uint32_t next_item(uint32_t *counters, uint32_t total, int &q, int &tried,
+__device__ __forceinline__ uint32_t next_item(uint32_t *queues, uint32_t total, int &q, int &tried,
                                               uint32_t &cnext, uint32_t &cend, uint32_t *s_item)
 {
     if (threadIdx.x == 0) {
@@ -292,7 +292,7 @@ __device__ __forceinline__ uint32_t next_item(uint32_t *counters, uint32_t total
             while (tried < NUM_QUEUES) {
                 const uint32_t lo = q * per, hi = min(total, lo + per);
                 if (lo < hi) {
-                    const uint32_t k = atomicAdd(&counters[CNT_QUEUE + QUEUE_STRIDE * q], CHUNK);
+                    const uint32_t k = atomicAdd(&queues[QUEUE_STRIDE * q], CHUNK);
                     if (lo + k < hi) {
                         item = lo + k;
                         cnext = item + 1;
@@ -359,7 +359,7 @@ constexpr uint32_t FWD_CHUNK = 2;
 // wavefronts and 106 VGPRs without spills).
 template <int K, int TILE, int BATCH>
 __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(5))) void render_fwd_kernel(
-    const FrameHeader *__restrict__ frame, const uint32_t *__restrict__ order, uint32_t *__restrict__ counters,
+    const FrameHeader *__restrict__ frame, const uint32_t *__restrict__ order, uint32_t *__restrict__ queues,
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ ids,
     const uint8_t *__restrict__ records, RenderArgs ra, uint2 *__restrict__ pixstate,
     unsigned long long *__restrict__ evalcount, u32x4 *__restrict__ zero_acc, uint32_t zero_n4)
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(5)))
     // here, one slice per tile item, by stores that overlap the compositing
     const uint32_t zper = total_tiles ? (zero_n4 + total_tiles - 1) / total_tiles : 0u;
     for (;;) {
-        const uint32_t item = next_item<FWD_CHUNK>(counters, total_tiles, q, tried, cnext, cend, &s_item);
+        const uint32_t item = next_item<FWD_CHUNK>(queues, total_tiles, q, tried, cnext, cend, &s_item);
         if (item == 0xFFFFFFFFu) break;
         if (zper) {
             const uint32_t z0 = min(item * zper, zero_n4), z1 = min(z0 + zper, zero_n4);
@@ -570,7 +570,7 @@ __device__ __forceinline__ void bwd_record(const uint8_t *rec, bool live, int u,
 
 template <int K, int TILE, int BATCH>
 __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
-    const FrameHeader *__restrict__ frame, const uint32_t *__restrict__ order, uint32_t *__restrict__ counters,
+    const FrameHeader *__restrict__ frame, const uint32_t *__restrict__ order, uint32_t *__restrict__ queues,
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ ids,
     const uint8_t *__restrict__ records, RenderArgs ra, const uint2 *__restrict__ pixstate,
     float *__restrict__ acc, unsigned long long *__restrict__ evalcount)
@@ -598,7 +598,7 @@ __global__ __launch_bounds__(TILE *TILE) void render_bwd_kernel(
     uint32_t cnext = 0, cend = 0;
     uint32_t nfull = 0, nsumT = 0, nwave = 0;
     for (;;) {
-        const uint32_t item = next_item<1>(counters, total_tiles, q, tried, cnext, cend, &s_item);
+        const uint32_t item = next_item<1>(queues, total_tiles, q, tried, cnext, cend, &s_item);
         if (item == 0xFFFFFFFFu) break;
         const int gt = order ? (int)order[item] : (int)item;
         const int v = find_view(views, nviews, gt);
@@ -726,7 +726,7 @@ template <class F> int persistent_grid(F kernel, int threads)
 // max_items bounds the grid (a persistent grid larger than the work only idles).
 // Returns the grid size (the number of evalcount slots written).
 int launch_render_fwd(hipStream_t st, int K, int tile, const FrameHeader *frame, const uint32_t *order,
-                      uint32_t max_items, uint32_t *counters, const uint2 *ranges, const uint32_t *ids,
+                      uint32_t max_items, uint32_t *queues, const uint2 *ranges, const uint32_t *ids,
                       const uint8_t *records, const RenderArgs &ra, uint2 *pixstate, unsigned long long *evalcount,
                       float *zero_acc, size_t zero_floats)
 {
@@ -738,7 +738,7 @@ int launch_render_fwd(hipStream_t st, int K, int tile, const FrameHeader *frame,
     CS_DISPATCH_K(K, CS_DISPATCH_TILE(tile, {
         auto kern = render_fwd_kernel<KK, TT, BF>;
         const int grid = std::min({persistent_grid(kern, TT * TT), (int)max_items, EVAL_SLOTS});
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(TT * TT), 0, st, frame, order, counters, ranges, ids, records, ra,
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(TT * TT), 0, st, frame, order, queues, ranges, ids, records, ra,
                            pixstate, evalcount, z4, n4);
         used = grid;
     }));
@@ -747,7 +747,7 @@ int launch_render_fwd(hipStream_t st, int K, int tile, const FrameHeader *frame,
 
 // Returns the grid size (the number of evalcount slots written).
 int launch_render_bwd(hipStream_t st, int K, int tile, const FrameHeader *frame, const uint32_t *order,
-                      uint32_t max_items, uint32_t *counters, const uint2 *ranges, const uint32_t *ids,
+                      uint32_t max_items, uint32_t *queues, const uint2 *ranges, const uint32_t *ids,
                       const uint8_t *records, const RenderArgs &ra, const uint2 *pixstate, float *acc,
                       unsigned long long *evalcount)
 {
@@ -756,7 +756,7 @@ int launch_render_bwd(hipStream_t st, int K, int tile, const FrameHeader *frame,
     CS_DISPATCH_K(K, CS_DISPATCH_TILE(tile, {
         auto kern = render_bwd_kernel<KK, TT, BBW>;
         const int grid = std::min({persistent_grid(kern, TT * TT), (int)max_items, EVAL_SLOTS});
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(TT * TT), 0, st, frame, order, counters, ranges, ids, records, ra,
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(TT * TT), 0, st, frame, order, queues, ranges, ids, records, ra,
                            pixstate, acc, evalcount);
         used = grid;
     }));

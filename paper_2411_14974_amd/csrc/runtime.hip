@@ -554,7 +554,7 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
             F.order = ov;
         }
         tm.begin();
-        F.eval_slots = launch_render_fwd(st, F.K, kn.tile, F.d_frame, F.order, (uint32_t)F.cap_tiles, F.counters, F.ranges,
+        F.eval_slots = launch_render_fwd(st, F.K, kn.tile, F.d_frame, F.order, (uint32_t)F.cap_tiles, F.counters + CNT_QUEUE, F.ranges,
                           F.sorted_ids, F.records, ra, F.pixstate, F.evalcount, zero_acc ? F.acc : nullptr,
                           zero_acc ? F.ninst * acc_stride(F.K) : 0);
         tm.end(CS_STAGE_RENDER_FWD);
@@ -626,14 +626,14 @@ int enqueue_backward(Frame &F, const cs_scene *sc, const cs_grads *g, const Rend
     hipStream_t st = F.st;
     int r = F.ensure_acc();
     if (r) return r;
-    if (!clear)
-        launch_zero_ranges(st, F.counters + CNT_QUEUE, QUEUE_WORDS, nullptr, 0, nullptr, 0);
-    else
-        launch_zero_ranges(st, reinterpret_cast<uint32_t *>(F.acc), F.ninst * acc_stride(F.K), F.counters + CNT_QUEUE,
+    // without clear the forward that just ran has cleared the accumulators and,
+    // with its counters, the backward's work queues
+    if (clear)
+        launch_zero_ranges(st, reinterpret_cast<uint32_t *>(F.acc), F.ninst * acc_stride(F.K), F.counters + CNT_QUEUE_B,
                            QUEUE_WORDS, nullptr, 0);
     F.acc_zeroed = false; // a second backward of the same forward clears them again
     tm.begin();
-    F.eval_slots_bwd = launch_render_bwd(st, F.K, F.tile, F.d_frame_b, F.order, (uint32_t)F.cap_tiles, F.counters,
+    F.eval_slots_bwd = launch_render_bwd(st, F.K, F.tile, F.d_frame_b, F.order, (uint32_t)F.cap_tiles, F.counters + CNT_QUEUE_B,
                                          F.ranges, F.sorted_ids, F.records, ra, F.pixstate, F.acc,
                                          F.evalcount + (size_t)EVAL_SLOTS * EVAL_FIELDS);
     tm.end(CS_STAGE_RENDER_BWD);
