@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <string>
@@ -28,14 +29,14 @@ void radix_sort(hipStream_t, uint32_t **, uint32_t **, uint32_t **, uint32_t **,
 size_t sort_temp_words(uint32_t, int, int);
 size_t scan_status_words(uint32_t);
 void launch_gather_scan(hipStream_t, uint32_t, const uint32_t *, const uint4 *, uint4 *, uint32_t *, uint32_t *,
-                        uint32_t *, uint32_t *);
+                        uint32_t *, unsigned long long *, uint32_t);
 void launch_fill_u32(hipStream_t, uint32_t *, size_t, uint32_t);
 void launch_emit_pairs(hipStream_t, uint32_t, uint32_t, const uint32_t *, const uint32_t *, const uint32_t *,
                        const uint4 *, const FrameHeader *, uint32_t, uint32_t *, uint32_t *);
 void launch_prepare_tail(hipStream_t, uint32_t *, uint32_t, uint32_t *, size_t);
 void launch_zero_ranges(hipStream_t, uint32_t *, size_t, uint32_t *, size_t, uint32_t *, size_t);
 void launch_tile_length_keys(hipStream_t, uint32_t, const uint2 *, uint32_t *, uint32_t *);
-void launch_tile_ranges(hipStream_t, const uint32_t *, uint32_t, const uint32_t *, uint32_t, uint2 *);
+void launch_tile_ranges(hipStream_t, const uint32_t *, uint32_t, const uint32_t *, uint32_t, uint2 *, uint32_t);
 int launch_render_fwd(hipStream_t, int, int, const FrameHeader *, const uint32_t *, uint32_t, uint32_t *,
                        const uint2 *, const uint32_t *, const uint8_t *, const RenderArgs &, uint2 *,
                        unsigned long long *, float *, size_t);
@@ -120,7 +121,6 @@ Frame::~Frame()
     for (void *p : allocs)
         if (p) (void)hipFreeAsync(p, st);
     if (counters_ev) (void)hipEventSynchronize(counters_ev), (void)hipEventDestroy(counters_ev);
-    if (mcount_ev) (void)hipEventSynchronize(mcount_ev), (void)hipEventDestroy(mcount_ev);
     if (h_counters) (void)hipHostFree(h_counters);
     if (ready) (void)hipEventDestroy(ready);
 }
@@ -137,6 +137,9 @@ int HostRing::init()
     }
     if (hipHostMalloc((void **)&h_word, 64, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
         return fail(CS_ENOMEM, "pinned allocation failed");
+    // pinned memory comes back with whatever it held (often an earlier ring's
+    // tagged count): zero it, so that no tag is found before a kernel writes it
+    std::memset(h_word, 0, 64);
     if (hipHostGetDevicePointer((void **)&d_word, h_word, 0) != hipSuccess)
         return fail(CS_EHIP, "pinned word has no device address");
     return CS_OK;
@@ -178,8 +181,6 @@ int Frame::init(int n_, int K_, int deg_, int V_, size_t tiles, size_t pix, hipS
                 size_t min_inst)
 {
     n = n_; K = K_; deg = deg_; V = V_; st = s; ring = r;
-    if (hipEventCreateWithFlags(&mcount_ev, hipEventDisableTiming) != hipSuccess)
-        return fail(CS_EHIP, "event creation failed");
     ninst = (size_t)n * V;
     cap_inst = capacity_class(std::max(ninst, min_inst));
     cap_tiles = capacity_class(std::max<size_t>(tiles, 1));
@@ -490,11 +491,41 @@ int plan_views(int nviews, const cs_camera *cams, int tile, float *const *out, c
 // (fixed capacities, graph capture); otherwise it is read back to size the
 // pair buffers exactly (plus `margin`).
 // Wait for an event by polling it.
-static hipError_t spin_wait(hipEvent_t ev)
+// Tags of the pair counts: unique in the process (never 0), so that a word
+// that still holds another call's or another ring's count never matches.
+static uint32_t next_count_tag()
 {
-    for (;;) {
-        const hipError_t e = hipEventQuery(ev);
-        if (e != hipErrorNotReady) return e;
+    static std::atomic<uint32_t> last{0};
+    uint32_t t;
+    do t = last.fetch_add(1, std::memory_order_relaxed) + 1;
+    while (t == 0);
+    return t;
+}
+
+// Waits for the pair count tagged `tag` in the pinned word (polling: a
+// blocking wait wakes up late and the GPU idles).  The stream is queried now
+// and then, so that a stream that finished or failed without writing it ends
+// the wait with an error.
+static int wait_pair_count(const HostRing &ring, uint32_t tag, hipStream_t st, uint32_t *count)
+{
+    const unsigned long long *w = reinterpret_cast<const unsigned long long *>(ring.h_word);
+    for (uint64_t spin = 1;; ++spin) {
+        const unsigned long long v = __atomic_load_n(w, __ATOMIC_ACQUIRE);
+        if ((uint32_t)(v >> 32) == tag) {
+            *count = (uint32_t)v;
+            return CS_OK;
+        }
+        if ((spin & 4095) == 0) {
+            const hipError_t q = hipStreamQuery(st);
+            if (q == hipErrorNotReady) continue;
+            const unsigned long long v2 = __atomic_load_n(w, __ATOMIC_ACQUIRE);
+            if (q == hipSuccess && (uint32_t)(v2 >> 32) == tag) {
+                *count = (uint32_t)v2;
+                return CS_OK;
+            }
+            return fail(CS_EHIP, "pair count read-back: %s", q == hipSuccess ? "the count was not written"
+                                                                          : hipGetErrorString(q));
+        }
     }
 }
 
@@ -539,7 +570,8 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
                        kn.digits, F.counters + CNT_SORT_ERR);
             tm.end(CS_STAGE_TILE_SORT);
             tm.begin();
-            launch_tile_ranges(st, pt, M_host, m_dev, m_dev ? (uint32_t)F.cap_pairs : M_host, F.ranges);
+            launch_tile_ranges(st, pt, M_host, m_dev, m_dev ? (uint32_t)F.cap_pairs : M_host, F.ranges,
+                               (uint32_t)F.cap_tiles);
             tm.end(CS_STAGE_RANGES);
         }
         F.sorted_ids = pi;
@@ -567,7 +599,7 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
     // count to size its buffers.
     const bool speculative = !device_count && ninst > 0 && F.pt != nullptr;
     uint32_t M = 0;
-    uint32_t *hw = F.ring->h_word;
+    const uint32_t tag = next_count_tag();
     if (ninst > 0) {
         if (!F.pt) { // first sizing: the sort temporaries come with the pair buffers
             int r = F.ensure_pairs(1);
@@ -579,16 +611,13 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
         tm.begin();
         // the count also goes straight to pinned host memory (no copy in the stream)
         launch_gather_scan(st, ninst, ids, F.bins, F.bins_sorted, F.counts_sorted, F.offsets, F.counters,
-                           device_count ? nullptr : F.ring->d_word);
+                           device_count ? nullptr : reinterpret_cast<unsigned long long *>(F.ring->d_word), tag);
         tm.end(CS_STAGE_BIN_SCAN);
         if (!device_count) {
-            hipError_t e = hipEventRecord(F.mcount_ev, st);
-            // a new frame waits for its count here (polling: a blocking wait wakes up late and the GPU idles)
-            if (e == hipSuccess && !speculative) e = spin_wait(F.mcount_ev);
-            if (e != hipSuccess) return fail(CS_EHIP, "pair count read-back: %s", hipGetErrorString(e));
-            if (!speculative) {
-                M = hw[0];
-                int r = F.ensure_pairs((size_t)std::ceil(M * margin));
+            if (!speculative) { // a new frame waits for its count here
+                int r = wait_pair_count(*F.ring, tag, st, &M);
+                if (r) return r;
+                r = F.ensure_pairs((size_t)std::ceil(M * margin));
                 if (r) return r;
                 F.npairs = M;
             }
@@ -600,9 +629,8 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
     }
     tail(M, (device_count || speculative) ? F.counters + CNT_PAIRS_EFF : nullptr);
     if (speculative) {
-        hipError_t e = hipEventSynchronize(F.mcount_ev);
-        if (e != hipSuccess) return fail(CS_EHIP, "pair count read-back: %s", hipGetErrorString(e));
-        M = hw[0];
+        int r = wait_pair_count(*F.ring, tag, st, &M);
+        if (r) return r;
         F.npairs = M;
         if (M > F.cap_pairs) { // did not fit: grow, reset the tile queues and counts, run the tail again
             int r = F.ensure_pairs((size_t)std::ceil(M * margin));
@@ -808,8 +836,6 @@ int cs_create(int device, size_t hbm_budget_bytes, cs_ctx **out)
     if (!r) {
         c->noalloc = new Frame;
         c->noalloc->ring = &c->ring;
-        if (hipEventCreateWithFlags(&c->noalloc->mcount_ev, hipEventDisableTiming) != hipSuccess)
-            r = fail(CS_EHIP, "event creation failed");
     }
     if (r) {
         delete c->noalloc;

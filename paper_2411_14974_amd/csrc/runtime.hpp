@@ -66,7 +66,6 @@ struct Frame {
     int eval_slots = 0, eval_slots_bwd = 0; // slots that the launches wrote
     uint32_t *h_counters = nullptr; // pinned read-back of the counters
     hipEvent_t counters_ev = nullptr;
-    hipEvent_t mcount_ev = nullptr; // after the pair count's read-back (reused frames)
 
     // results of the last forward pass (point into the buffers above)
     uint32_t *sorted_ids = nullptr;

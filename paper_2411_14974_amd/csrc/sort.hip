@@ -78,13 +78,14 @@ __device__ __forceinline__ void ss_store(uint64_t *p, uint64_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// host_pairs (nullable): a word of coherent pinned host memory that also
-// receives the pair count (the host reads it after an event, with no copy in
-// the stream).
+// host_word (nullable): a word of coherent pinned host memory that also
+// receives the pair count, as tag << 32 | count: the host waits for its tag
+// there, with no copy or event in the stream.
 __global__ __launch_bounds__(SCAN_BLOCK) void gather_scan_kernel(
     uint32_t n, const uint32_t *__restrict__ sorted_ids, const uint4 *__restrict__ bins,
     uint4 *__restrict__ bins_sorted, uint32_t *__restrict__ counts_sorted, uint32_t *__restrict__ offsets,
-    uint32_t *__restrict__ counters, uint64_t *__restrict__ status, uint32_t *__restrict__ host_pairs)
+    uint32_t *__restrict__ counters, uint64_t *__restrict__ status, unsigned long long *__restrict__ host_word,
+    uint32_t tag)
 {
     __shared__ uint32_t s[SCAN_TILE + SCAN_TILE / 32];
     __shared__ uint32_t s_wave[SCAN_BLOCK / 64];
@@ -144,9 +145,9 @@ __global__ __launch_bounds__(SCAN_BLOCK) void gather_scan_kernel(
             s_excl = excl;
             if (base + SCAN_TILE >= n) {
                 counters[CNT_PAIRS] = (uint32_t)(excl + tile_total);
-                if (host_pairs)
-                    __hip_atomic_store(host_pairs, (uint32_t)(excl + tile_total), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_SYSTEM);
+                if (host_word)
+                    __hip_atomic_store(host_word, ((unsigned long long)tag << 32) | (uint32_t)(excl + tile_total),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             }
         }
     }
@@ -167,13 +168,13 @@ size_t scan_status_words(uint32_t n) { return 2 * (((size_t)n + SCAN_TILE - 1) /
 // must hold CNT_WORDS words, zeroed, followed by scan_status_words(n) zeroed words.
 void launch_gather_scan(hipStream_t st, uint32_t n, const uint32_t *sorted_ids, const uint4 *bins,
                         uint4 *bins_sorted, uint32_t *counts_sorted, uint32_t *offsets, uint32_t *counters,
-                        uint32_t *host_pairs)
+                        unsigned long long *host_word, uint32_t tag)
 {
     if (n == 0) return;
     const uint32_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     hipLaunchKernelGGL(gather_scan_kernel, dim3(tiles), dim3(SCAN_BLOCK), 0, st, n, sorted_ids, bins, bins_sorted,
                        counts_sorted, offsets, counters, reinterpret_cast<uint64_t *>(counters + CNT_STATUS),
-                       host_pairs);
+                       host_word, tag);
 }
 
 // ----------------------------------------------------------- radix sort ----
@@ -742,9 +743,11 @@ __global__ void fill_u32_kernel(uint32_t *__restrict__ p, size_t n, uint32_t v)
 // aligned) plus the id before them, and marks the run boundaries among them.
 constexpr int RANGE_ITEMS = 8;
 
+// ntiles bounds the tile ids written (every id of a pair is below it; the
+// bound keeps a wrong count from writing past the ranges).
 __global__ __launch_bounds__(256) void tile_ranges_kernel(const uint32_t *__restrict__ tiles,
                                                           const uint32_t *__restrict__ n_dev, uint32_t n_host,
-                                                          uint2 *__restrict__ ranges)
+                                                          uint2 *__restrict__ ranges, uint32_t ntiles)
 {
     const uint32_t n = n_dev ? *n_dev : n_host;
     const size_t i0 = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * RANGE_ITEMS;
@@ -767,12 +770,12 @@ __global__ __launch_bounds__(256) void tile_ranges_kernel(const uint32_t *__rest
         const size_t i = i0 + k;
         if (i >= n) break;
         if (t[k] != prev) { // a run starts at i and the previous one ends there
-            ranges[t[k]].x = (uint32_t)i;
-            if (i > 0) ranges[prev].y = (uint32_t)i;
+            if (t[k] < ntiles) ranges[t[k]].x = (uint32_t)i;
+            if (i > 0 && prev < ntiles) ranges[prev].y = (uint32_t)i;
         }
         prev = t[k];
     }
-    if (i0 + RANGE_ITEMS >= n) ranges[prev].y = n; // the last run
+    if (i0 + RANGE_ITEMS >= n && prev < ntiles) ranges[prev].y = n; // the last run
 }
 
 void launch_fill_u32(hipStream_t st, uint32_t *p, size_t n, uint32_t v)
@@ -816,12 +819,12 @@ void launch_tile_length_keys(hipStream_t st, uint32_t ntiles, const uint2 *range
 }
 
 void launch_tile_ranges(hipStream_t st, const uint32_t *tiles, uint32_t n_host, const uint32_t *n_dev,
-                        uint32_t n_capacity, uint2 *ranges)
+                        uint32_t n_capacity, uint2 *ranges, uint32_t ntiles)
 {
     if (n_capacity == 0) return;
     const size_t threads = ((size_t)n_capacity + RANGE_ITEMS - 1) / RANGE_ITEMS;
     hipLaunchKernelGGL(tile_ranges_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, tiles, n_dev,
-                       n_host, ranges);
+                       n_host, ranges, ntiles);
 }
 
 } // namespace cs

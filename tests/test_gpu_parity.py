@@ -178,6 +178,31 @@ def test_accumulators_cleared_for_every_backward(R):
     assert worst <= 1e-5
 
 
+def test_first_forward_of_a_new_context_after_another_context():
+    """The pair count reaches the host through a tagged word of pinned memory;
+    a new context's word may come back holding the last context's count.  A
+    context that made one forward of a larger scene, closed, then a new
+    context's first forward of a smaller scene: the image matches the oracle
+    and the pair count is the small scene's."""
+    import oracle
+    from paper_2411_14974_amd.binding import Renderer
+    big, cam_b, _ = scenes.config2(n=20000, width=200, height=130)
+    small, cam_s, _ = scenes.config2(n=4000, width=128, height=96)
+    counts = []
+    for sc, cam in ((big, cam_b), (small, cam_s)):
+        r = Renderer(0)
+        ds, rgb, st = render_gpu(r, sc, cam, want_state=True)
+        counts.append(st.stats()["pairs"])
+        img = rgb.cpu().numpy()
+        st.release()
+        r.close()
+    ref, _, _ = oracle.render(small, cam_s)
+    err = float(np.abs(img.astype(np.float64) - ref).max())
+    say(f"[new context] pairs {counts}, image max |gpu - oracle| {err:.2e}")
+    assert counts[1] < counts[0]
+    assert err <= PIX_TOL
+
+
 def big_convex_scene(n=160, width=1280, height=960, seed=5):
     """Convexes stretched to 3-10x their size along a random direction (and
     2-4x across it), so that many tile rectangles exceed 64 tiles and their
