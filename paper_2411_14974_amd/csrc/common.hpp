@@ -161,6 +161,25 @@ __device__ inline uint32_t bin_count(uint4 b)
     return c;
 }
 
+// Up to two word ranges that a kernel clears on the side (each block its
+// share), in place of clearing launches of their own: the ranges' next users
+// run after the kernel in the stream.
+struct ZeroSpans {
+    uint32_t *p[2];
+    uint32_t n[2];
+};
+__device__ inline void zero_share(const ZeroSpans &z)
+{
+    const uint32_t nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (!z.p[k]) continue;
+        const uint32_t per = (z.n[k] + nb - 1) / nb;
+        const uint32_t lo = min(b * per, z.n[k]), hi = min(lo + per, z.n[k]);
+        for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) z.p[k][i] = 0u;
+    }
+}
+
 // Layout of a frame's counter buffer (32-bit words):
 //   [0, CNT_WORDS)            counters read back by the host:
 //     CNT_SORT_ERR: a radix-sort look-back wait ran out of its bound (never expected)

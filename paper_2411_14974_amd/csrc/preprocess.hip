@@ -120,8 +120,9 @@ __global__ __launch_bounds__(PF_BLOCK) void preprocess_fwd_kernel(
     const P *__restrict__ sigma, const P *__restrict__ opacity, const P *__restrict__ sh,
     const FrameHeader *__restrict__ frame, RenderArgs ra, uint8_t *__restrict__ records, uint32_t *__restrict__ keys,
     uint32_t *__restrict__ ids, uint4 *__restrict__ bins, uint32_t *__restrict__ hullpk,
-    DebugConvex *__restrict__ dbg)
+    DebugConvex *__restrict__ dbg, ZeroSpans zero)
 {
+    zero_share(zero); // the frame's counters and the depth sort's temporaries, when asked
     // The block's points arrive through LDS (coalesced loads; odd row stride);
     // once they are in registers the same LDS holds the block's records, which
     // leave in coalesced 16-byte stores (one contiguous run per block).
@@ -906,7 +907,7 @@ __global__ __launch_bounds__(PB_BLOCK) __attribute__((amdgpu_waves_per_eu(MV || 
 void launch_preprocess_fwd(hipStream_t st, int n, int nviews, int K, int deg, int dtype, const void *points,
                            const void *delta, const void *sigma, const void *opacity, const void *sh,
                            const FrameHeader *views, const RenderArgs &ra, uint8_t *records, uint32_t *keys,
-                           uint32_t *ids, uint4 *bins, uint32_t *hullpk, DebugConvex *dbg)
+                           uint32_t *ids, uint4 *bins, uint32_t *hullpk, DebugConvex *dbg, const ZeroSpans &zero)
 {
     if (n <= 0 || nviews <= 0) return;
     dim3 grid((n + PF_BLOCK - 1) / PF_BLOCK, nviews), block(PF_BLOCK);
@@ -914,12 +915,12 @@ void launch_preprocess_fwd(hipStream_t st, int n, int nviews, int K, int deg, in
         CS_DISPATCH_P(dtype, CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_fwd_kernel<KK, true, PP>), grid, block, 0, st, n,
                                                              deg, (const PP *)points, (const PP *)delta,
                                                              (const PP *)sigma, (const PP *)opacity, (const PP *)sh,
-                                                             views, ra, records, keys, ids, bins, hullpk, dbg)))
+                                                             views, ra, records, keys, ids, bins, hullpk, dbg, zero)))
     else
         CS_DISPATCH_P(dtype, CS_DISPATCH_K(K, hipLaunchKernelGGL((preprocess_fwd_kernel<KK, false, PP>), grid, block, 0, st,
                                                              n, deg, (const PP *)points, (const PP *)delta,
                                                              (const PP *)sigma, (const PP *)opacity, (const PP *)sh,
-                                                             views, ra, records, keys, ids, bins, hullpk, dbg)))
+                                                             views, ra, records, keys, ids, bins, hullpk, dbg, zero)))
 }
 
 void launch_preprocess_bwd(hipStream_t st, int n, int nviews, int K, int deg, int dtype, const void *points,

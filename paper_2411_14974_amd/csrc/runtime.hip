@@ -20,19 +20,20 @@
 namespace cs {
 void launch_preprocess_fwd(hipStream_t, int, int, int, int, int, const void *, const void *, const void *,
                            const void *, const void *, const FrameHeader *, const RenderArgs &, uint8_t *,
-                           uint32_t *, uint32_t *, uint4 *, uint32_t *, DebugConvex *);
+                           uint32_t *, uint32_t *, uint4 *, uint32_t *, DebugConvex *, const ZeroSpans &);
 void launch_preprocess_bwd(hipStream_t, int, int, int, int, int, const void *, const void *, const void *,
                            const void *, const FrameHeader *, const uint32_t *, const float *,
                            float *, float *, float *, float *, float *);
 void radix_sort(hipStream_t, uint32_t **, uint32_t **, uint32_t **, uint32_t **, uint32_t, const uint32_t *, uint32_t, int,
-                uint32_t *, int, uint32_t *);
+                uint32_t *, int, uint32_t *, bool);
+size_t radix_sort_words(uint32_t, bool, uint32_t, int, int);
 size_t sort_temp_words(uint32_t, int, int);
 size_t scan_status_words(uint32_t);
 void launch_gather_scan(hipStream_t, uint32_t, const uint32_t *, const uint4 *, uint4 *, uint32_t *, uint32_t *,
-                        uint32_t *, unsigned long long *, uint32_t);
+                        uint32_t *, unsigned long long *, uint32_t, uint32_t, uint32_t *, uint32_t);
 void launch_fill_u32(hipStream_t, uint32_t *, size_t, uint32_t);
 void launch_emit_pairs(hipStream_t, uint32_t, uint32_t, const uint32_t *, const uint32_t *, const uint32_t *,
-                       const uint4 *, const FrameHeader *, uint32_t, uint32_t *, uint32_t *);
+                       const uint4 *, const FrameHeader *, uint32_t, uint32_t *, uint32_t *, uint32_t *, uint32_t);
 void launch_prepare_tail(hipStream_t, uint32_t *, uint32_t, uint32_t *, size_t);
 void launch_zero_ranges(hipStream_t, uint32_t *, size_t, uint32_t *, size_t, uint32_t *, size_t);
 void launch_tile_length_keys(hipStream_t, uint32_t, const uint2 *, uint32_t *, uint32_t *);
@@ -538,10 +539,23 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
     F.tile = kn.tile;
     F.longest = kn.longest;
     F.digits = kn.digits;
-    launch_zero_ranges(st, F.counters, F.counter_words, nullptr, 0, nullptr, 0);
+    // The clearing of the frame's counters, the sort temporaries and the tile
+    // ranges rides on the kernels before their users (preprocess, pair scan,
+    // emission) instead of launches of their own, when those kernels run.
+    const bool fused = ninst > 0 && n > 0;
+    if (fused && !F.pt) { // first sizing: the sort temporaries come with the pair buffers
+        int r = F.ensure_pairs(1);
+        if (r) return r;
+    }
+    ZeroSpans zpre{{nullptr, nullptr}, {0u, 0u}};
+    if (fused)
+        zpre = ZeroSpans{{F.counters, F.hist},
+                         {(uint32_t)F.counter_words, (uint32_t)radix_sort_words(ninst, false, ninst, 32, 8)}};
+    else
+        launch_zero_ranges(st, F.counters, F.counter_words, nullptr, 0, nullptr, 0);
     tm.begin();
     launch_preprocess_fwd(st, n, F.V, F.K, F.deg, sc->dtype, sc->points, sc->delta, sc->sigma, sc->opacity, sc->sh, F.d_frame,
-                          ra, F.records, F.keys, F.ids, F.bins, F.hullpk, nullptr);
+                          ra, F.records, F.keys, F.ids, F.bins, F.hullpk, nullptr, zpre);
     tm.end(CS_STAGE_PREPROCESS);
 
     uint32_t *keys = F.keys, *ids = F.ids, *keys_alt = F.keys_alt, *ids_alt = F.ids_alt;
@@ -555,19 +569,26 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
     // Everything after the pair count: emission, tile sort, ranges, tile order,
     // compositing.  m_dev: the device-side pair count clamped to the buffers, or
     // NULL when the count (M_host) is known here.
+    // scan_prepared: the pair scan has set the clamped count and the overflow
+    // flag for the current buffers and cleared the tile ranges.
+    bool scan_prepared = false;
     auto tail = [&](uint32_t M_host, const uint32_t *m_dev) {
-        launch_prepare_tail(st, F.counters, (uint32_t)F.cap_pairs, reinterpret_cast<uint32_t *>(F.ranges),
-                            2 * F.cap_tiles);
+        if (!scan_prepared)
+            launch_prepare_tail(st, F.counters, (uint32_t)F.cap_pairs, reinterpret_cast<uint32_t *>(F.ranges),
+                                2 * F.cap_tiles);
+        scan_prepared = false;
         uint32_t *pt = F.pt, *pi = F.pi, *pt_alt = F.pt_alt, *pi_alt = F.pi_alt;
         if (ninst > 0) {
+            const int tile_bits = std::max(1, ilog2_ceil(F.cap_tiles));
+            // the emission clears the tile sort's temporaries
+            const size_t tw = radix_sort_words(M_host, m_dev != nullptr, (uint32_t)F.cap_pairs, tile_bits, kn.digits);
             tm.begin();
             launch_emit_pairs(st, ninst, (uint32_t)n, ids, F.offsets, F.counts_sorted, F.bins_sorted, F.d_frame,
-                              (uint32_t)F.cap_pairs, pt, pi);
+                              (uint32_t)F.cap_pairs, pt, pi, F.hist, (uint32_t)tw);
             tm.end(CS_STAGE_EMIT);
-            const int tile_bits = std::max(1, ilog2_ceil(F.cap_tiles));
             tm.begin();
             radix_sort(st, &pt, &pi, &pt_alt, &pi_alt, M_host, m_dev, (uint32_t)F.cap_pairs, tile_bits, F.hist,
-                       kn.digits, F.counters + CNT_SORT_ERR);
+                       kn.digits, F.counters + CNT_SORT_ERR, true);
             tm.end(CS_STAGE_TILE_SORT);
             tm.begin();
             launch_tile_ranges(st, pt, M_host, m_dev, m_dev ? (uint32_t)F.cap_pairs : M_host, F.ranges,
@@ -581,7 +602,7 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
             tm.begin();
             launch_tile_length_keys(st, (uint32_t)F.cap_tiles, F.ranges, ok, ov);
             radix_sort(st, &ok, &ov, &ok2, &ov2, (uint32_t)F.cap_tiles, nullptr, (uint32_t)F.cap_tiles, 16, F.hist,
-                       8, F.counters + CNT_SORT_ERR);
+                       8, F.counters + CNT_SORT_ERR, false);
             tm.end(CS_STAGE_ORDER);
             F.order = ov;
         }
@@ -606,12 +627,18 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
             if (r) return r;
         }
         tm.begin();
-        radix_sort(st, &keys, &ids, &keys_alt, &ids_alt, ninst, nullptr, ninst, 32, F.hist, 8, F.counters + CNT_SORT_ERR);
+        radix_sort(st, &keys, &ids, &keys_alt, &ids_alt, ninst, nullptr, ninst, 32, F.hist, 8, F.counters + CNT_SORT_ERR,
+                   fused);
         tm.end(CS_STAGE_DEPTH_SORT);
         tm.begin();
-        // the count also goes straight to pinned host memory (no copy in the stream)
+        // the count also goes straight to pinned host memory (no copy in the
+        // stream); with the pair buffers' size known (a reused frame, graph
+        // capture) the scan also prepares the pair pass
+        scan_prepared = device_count || speculative;
         launch_gather_scan(st, ninst, ids, F.bins, F.bins_sorted, F.counts_sorted, F.offsets, F.counters,
-                           device_count ? nullptr : reinterpret_cast<unsigned long long *>(F.ring->d_word), tag);
+                           device_count ? nullptr : reinterpret_cast<unsigned long long *>(F.ring->d_word), tag,
+                           scan_prepared ? (uint32_t)F.cap_pairs : 0u, reinterpret_cast<uint32_t *>(F.ranges),
+                           (uint32_t)(2 * F.cap_tiles));
         tm.end(CS_STAGE_BIN_SCAN);
         if (!device_count) {
             if (!speculative) { // a new frame waits for its count here
@@ -1317,7 +1344,8 @@ int cs_debug_preprocess(cs_ctx *ctx, const cs_scene *sc, const cs_camera *cam, c
     DebugConvex *dbg = nullptr;
     CS_TRY(F.alloc((void **)&dbg, sizeof(DebugConvex) * (size_t)sc->n));
     launch_preprocess_fwd(st, sc->n, 1, sc->k, sc->sh_degree, sc->dtype, sc->points, sc->delta, sc->sigma, sc->opacity, sc->sh,
-                          F.d_frame, ra, F.records, F.keys, F.ids, F.bins, F.hullpk, dbg);
+                          F.d_frame, ra, F.records, F.keys, F.ids, F.bins, F.hullpk, dbg,
+                          ZeroSpans{{nullptr, nullptr}, {0u, 0u}});
     CS_HIP(hipGetLastError());
     CS_HIP(hipMemcpyAsync(out, dbg, sizeof(DebugConvex) * (size_t)sc->n, hipMemcpyDeviceToHost, st));
     CS_HIP(hipStreamSynchronize(st));

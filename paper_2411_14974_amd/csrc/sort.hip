@@ -85,8 +85,9 @@ __global__ __launch_bounds__(SCAN_BLOCK) void gather_scan_kernel(
     uint32_t n, const uint32_t *__restrict__ sorted_ids, const uint4 *__restrict__ bins,
     uint4 *__restrict__ bins_sorted, uint32_t *__restrict__ counts_sorted, uint32_t *__restrict__ offsets,
     uint32_t *__restrict__ counters, uint64_t *__restrict__ status, unsigned long long *__restrict__ host_word,
-    uint32_t tag)
+    uint32_t tag, uint32_t capacity, ZeroSpans zero)
 {
+    zero_share(zero); // the tile ranges, when this scan also prepares the pair pass
     __shared__ uint32_t s[SCAN_TILE + SCAN_TILE / 32];
     __shared__ uint32_t s_wave[SCAN_BLOCK / 64];
     __shared__ uint32_t s_tile;
@@ -144,7 +145,12 @@ __global__ __launch_bounds__(SCAN_BLOCK) void gather_scan_kernel(
         if (tid == 0) {
             s_excl = excl;
             if (base + SCAN_TILE >= n) {
-                counters[CNT_PAIRS] = (uint32_t)(excl + tile_total);
+                const uint32_t m = (uint32_t)(excl + tile_total);
+                counters[CNT_PAIRS] = m;
+                if (capacity) { // the pair pass's count, clamped to the buffers, and the overflow flag
+                    counters[CNT_PAIRS_EFF] = m < capacity ? m : capacity;
+                    counters[CNT_OVERFLOW] = m > capacity ? 1u : 0u;
+                }
                 if (host_word)
                     __hip_atomic_store(host_word, ((unsigned long long)tag << 32) | (uint32_t)(excl + tile_total),
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -168,13 +174,15 @@ size_t scan_status_words(uint32_t n) { return 2 * (((size_t)n + SCAN_TILE - 1) /
 // must hold CNT_WORDS words, zeroed, followed by scan_status_words(n) zeroed words.
 void launch_gather_scan(hipStream_t st, uint32_t n, const uint32_t *sorted_ids, const uint4 *bins,
                         uint4 *bins_sorted, uint32_t *counts_sorted, uint32_t *offsets, uint32_t *counters,
-                        unsigned long long *host_word, uint32_t tag)
+                        unsigned long long *host_word, uint32_t tag, uint32_t capacity, uint32_t *ranges,
+                        uint32_t range_words)
 {
     if (n == 0) return;
     const uint32_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    const ZeroSpans z{{capacity ? ranges : nullptr, nullptr}, {capacity ? range_words : 0u, 0u}};
     hipLaunchKernelGGL(gather_scan_kernel, dim3(tiles), dim3(SCAN_BLOCK), 0, st, n, sorted_ids, bins, bins_sorted,
                        counts_sorted, offsets, counters, reinterpret_cast<uint64_t *>(counters + CNT_STATUS),
-                       host_word, tag);
+                       host_word, tag, capacity, z);
 }
 
 // ----------------------------------------------------------- radix sort ----
@@ -479,9 +487,22 @@ static void os_launch_scatter(hipStream_t st, const uint32_t *keys, const uint32
 // temp: sort_temp_words(n_capacity, end_bit, digit_bits) words.  *err (device)
 // gets bit 0 set if a look-back wait ran out of its bound.  The key arrays must
 // be 16-byte aligned (the histogram pass reads them in 16-byte loads).
+// Words of temp that radix_sort uses (and clears first, unless told that they
+// are clear) for these arguments.
+size_t radix_sort_words(uint32_t n_host, bool n_on_device, uint32_t n_capacity, int end_bit, int digit_bits)
+{
+    digit_bits = std::min(8, std::max(4, digit_bits));
+    const uint32_t n_grid = n_on_device ? n_capacity : n_host;
+    if (n_grid == 0 || end_bit <= 0) return 0;
+    const int P = os_passes(end_bit, digit_bits);
+    const int tile = n_grid <= (1u << 22) ? OS_TILE_MIN : 2 * OS_TILE_MIN;
+    const size_t tiles = ((size_t)n_grid + tile - 1) / tile;
+    return OS_STATUS + (size_t)P * tiles * OS_RADIX;
+}
+
 void radix_sort(hipStream_t st, uint32_t **keys, uint32_t **vals, uint32_t **keys_alt, uint32_t **vals_alt,
                 uint32_t n_host, const uint32_t *n_dev, uint32_t n_capacity, int end_bit, uint32_t *temp,
-                int digit_bits, uint32_t *err)
+                int digit_bits, uint32_t *err, bool temp_clear)
 {
     digit_bits = std::min(8, std::max(4, digit_bits));
     const uint32_t n_grid = n_dev ? n_capacity : n_host;
@@ -492,9 +513,11 @@ void radix_sort(hipStream_t st, uint32_t **keys, uint32_t **vals, uint32_t **key
     const bool small = n_grid <= (1u << 22);
     const int tile = small ? OS_TILE_MIN : 2 * OS_TILE_MIN;
     const int tiles = (int)((n_grid + tile - 1) / tile);
-    const size_t words = OS_STATUS + (size_t)P * tiles * OS_RADIX;
-    const size_t fb = std::min<size_t>((words + 255) / 256, 4096);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)fb), dim3(256), 0, st, temp, words, 0u);
+    const size_t words = radix_sort_words(n_host, n_dev != nullptr, n_capacity, end_bit, digit_bits);
+    if (!temp_clear) {
+        const size_t fb = std::min<size_t>((words + 255) / 256, 4096);
+        hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)fb), dim3(256), 0, st, temp, words, 0u);
+    }
     const int hb = std::max(1, std::min(tiles, 256)); // one workgroup per CU: fewer same-address global adds
     const int widest = os_width(end_bit, P, 0);
     if (small) {
@@ -553,8 +576,9 @@ __global__ __launch_bounds__(EMIT_BLOCK) void emit_pairs_kernel(
     uint32_t n, uint32_t n_convex, const uint32_t *__restrict__ sorted_ids, const uint32_t *__restrict__ offsets,
     const uint32_t *__restrict__ counts_sorted, const uint4 *__restrict__ bins_sorted,
     const FrameHeader *__restrict__ frame, uint32_t capacity, uint32_t *__restrict__ pair_tiles,
-    uint32_t *__restrict__ pair_ids)
+    uint32_t *__restrict__ pair_ids, ZeroSpans zero)
 {
+    zero_share(zero); // the tile sort's temporaries
     __shared__ uint32_t s_off[EMIT_BLOCK];
     __shared__ uint32_t s_id[EMIT_BLOCK];
     __shared__ uint32_t s_x0w[EMIT_BLOCK];  // tx0 | rect width << 16
@@ -787,12 +811,14 @@ void launch_fill_u32(hipStream_t st, uint32_t *p, size_t n, uint32_t v)
 
 void launch_emit_pairs(hipStream_t st, uint32_t n, uint32_t n_convex, const uint32_t *sorted_ids,
                        const uint32_t *offsets, const uint32_t *counts_sorted, const uint4 *bins_sorted,
-                       const FrameHeader *views, uint32_t capacity, uint32_t *pair_tiles, uint32_t *pair_ids)
+                       const FrameHeader *views, uint32_t capacity, uint32_t *pair_tiles, uint32_t *pair_ids,
+                       uint32_t *zero, uint32_t zero_words)
 {
     if (n == 0) return;
+    const ZeroSpans z{{zero, nullptr}, {zero ? zero_words : 0u, 0u}};
     hipLaunchKernelGGL(emit_pairs_kernel, dim3((n + EMIT_BLOCK - 1) / EMIT_BLOCK), dim3(EMIT_BLOCK), 0, st, n,
                        n_convex, sorted_ids, offsets, counts_sorted, bins_sorted, views, capacity, pair_tiles,
-                       pair_ids);
+                       pair_ids, z);
 }
 
 void launch_prepare_tail(hipStream_t st, uint32_t *counters, uint32_t capacity, uint32_t *ranges, size_t nwords)
