@@ -543,6 +543,12 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
     // ranges rides on the kernels before their users (preprocess, pair scan,
     // emission) instead of launches of their own, when those kernels run.
     const bool fused = ninst > 0 && n > 0;
+    // A frame that already holds pair buffers (a reused one) runs the tail at
+    // once on the device-side count; the host reads the count back while the
+    // GPU works and, in the rare case that it did not fit, grows the buffers
+    // and runs the tail again before returning.  A new frame waits for the
+    // count to size its buffers.
+    const bool speculative = !device_count && ninst > 0 && F.pt != nullptr;
     if (fused && !F.pt) { // first sizing: the sort temporaries come with the pair buffers
         int r = F.ensure_pairs(1);
         if (r) return r;
@@ -613,12 +619,6 @@ int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs 
         tm.end(CS_STAGE_RENDER_FWD);
     };
 
-    // A frame that already holds pair buffers (a reused one) runs the tail at
-    // once on the device-side count; the host reads the count back while the
-    // GPU works and, in the rare case that it did not fit, grows the buffers
-    // and runs the tail again before returning.  A new frame waits for the
-    // count to size its buffers.
-    const bool speculative = !device_count && ninst > 0 && F.pt != nullptr;
     uint32_t M = 0;
     const uint32_t tag = next_count_tag();
     if (ninst > 0) {
