@@ -488,10 +488,6 @@ int plan_views(int nviews, const cs_camera *cams, int tile, float *const *out, c
 
 // --------------------------------------------------------- launch sequence --
 
-// Forward pass on frame F.  device_count: the pair count stays on the device
-// (fixed capacities, graph capture); otherwise it is read back to size the
-// pair buffers exactly (plus `margin`).
-// Wait for an event by polling it.
 // Tags of the pair counts: unique in the process (never 0), so that a word
 // that still holds another call's or another ring's count never matches.
 static uint32_t next_count_tag()
@@ -530,6 +526,9 @@ static int wait_pair_count(const HostRing &ring, uint32_t tag, hipStream_t st, u
     }
 }
 
+// Forward pass on frame F.  device_count: the pair count stays on the device
+// (fixed capacities, graph capture); otherwise it is read back to size the
+// pair buffers exactly (plus `margin`).
 int enqueue_forward(cs_ctx *ctx, Frame &F, const cs_scene *sc, const RenderArgs &ra, const Knobs &kn,
                     bool device_count, double margin, StageTimer &tm)
 {
