@@ -138,29 +138,13 @@ __device__ __forceinline__ bool eval_pair(const uint8_t *rec, bool live, int u, 
     return finish_pair<K, NL>(h, x, m, full, eps, pe);
 }
 
-// Row sums: after it every lane of each 16-lane row holds that row's sum of
-// each of the NV values (DPP quad_perm, half-mirror, mirror; run across all
-// values at once so that independent chains hide the DPP hazards).
-template <int NV> __device__ __forceinline__ void row_sums(float *v)
-{
-#define CS_DPP_STEP(CTRL)                                                                                          \
-    _Pragma("unroll") for (int q = 0; q < NV; ++q) v[q] += __int_as_float(                                          \
-        __builtin_amdgcn_mov_dpp(__float_as_int(v[q]), CTRL, 0xF, 0xF, true));
-    CS_DPP_STEP(0xB1)  // quad_perm 1,0,3,2
-    CS_DPP_STEP(0x4E)  // quad_perm 2,3,0,1
-    CS_DPP_STEP(0x141) // row_half_mirror
-    CS_DPP_STEP(0x140) // row_mirror
-#undef CS_DPP_STEP
-}
-
-// Whole-wavefront sums of NP values (NP a multiple of 4) by transposition:
-// a 32-lane swap (v_permlane32_swap) pairs value j with value j + NP/2 so that
-// one add leaves the two half-wave sums of j in the lower half and of j + NP/2
-// in the upper half; a 16-lane swap (v_permlane16_swap) does the same between
-// rows; the 16-lane row sums finish.  On return every lane of row r holds in
-// v[j], j < NP/4, the wave's sum of value j + r NP/4: 3 NP/4 + NP adds and
-// swaps where plain row sums would take 4 NP and still leave 4 partial sums.
-template <int NP> __device__ __forceinline__ void wave_sums(float *v)
+// First half of a whole-wavefront sum of NP values (NP a multiple of 4), by
+// transposition: a 32-lane swap (v_permlane32_swap) pairs value j with value
+// j + NP/2 so that one add leaves the two half-wave sums of j in the lower
+// half and of j + NP/2 in the upper half; a 16-lane swap (v_permlane16_swap)
+// does the same between rows.  On return lane l of row r holds in v[j],
+// j < NP/4, a partial sum of value j + r NP/4 (the row reduction finishes it).
+template <int NP> __device__ __forceinline__ void wave_to_rows(float *v)
 {
     static_assert(NP % 4 == 0, "pad the values to a multiple of 4");
     constexpr int H = NP / 2, Q = NP / 4;
@@ -174,7 +158,94 @@ template <int NP> __device__ __forceinline__ void wave_sums(float *v)
         const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[j]), __float_as_uint(v[j + Q]), false, false);
         v[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
-    row_sums<Q>(v);
+}
+
+// Row totals of Q values over the 16 lanes of each row, transposed like the
+// swaps above: four DPP stages pair every lane with a partner (row mirror,
+// half-row mirror, quad swap of 2, of 1), and at each stage the registers are
+// taken in pairs: both values of a pair are added to the partner's, and the
+// lanes on one side of the stage keep the first sum, the others the second
+// (an unpaired last register is summed in place).  The register count halves
+// per stage, so Q values cost about 1.5 (Q + Q/2 + Q/4 + Q/8) instructions
+// where plain row sums take 4 Q; at the end lane i of a row holds the row
+// total of value rr_value(Q, i).
+__host__ __device__ constexpr bool rr_keeps_first(int stage, int i)
+{
+    return stage == 0 ? (i < 8) : stage == 1 ? ((i & 7) < 4) : stage == 2 ? ((i & 2) == 0) : ((i & 1) == 0);
+}
+__host__ __device__ constexpr int rr_value(int Q, int lane)
+{
+    int reg[16] = {};
+    int m = Q;
+    for (int k = 0; k < Q; ++k) reg[k] = k;
+    for (int s = 0; s < 4; ++s) {
+        const bool first = rr_keeps_first(s, lane);
+        int nm = 0;
+        for (int p = 0; p + 1 < m; p += 2) reg[nm++] = first ? reg[p] : reg[p + 1];
+        if (m & 1) reg[nm++] = reg[m - 1];
+        m = nm;
+    }
+    return reg[0];
+}
+// 4 bits per lane: the value whose total the lane holds
+__host__ __device__ constexpr uint64_t rr_map(int Q)
+{
+    uint64_t t = 0;
+    for (int i = 0; i < 16; ++i) t |= (uint64_t)rr_value(Q, i) << (4 * i);
+    return t;
+}
+// the lanes that hold a value no lower lane of the row holds
+__host__ __device__ constexpr uint32_t rr_first_lanes(int Q)
+{
+    uint32_t f = 0;
+    for (int i = 0; i < 16; ++i) {
+        bool first = true;
+        for (int j = 0; j < i; ++j) first = first && rr_value(Q, j) != rr_value(Q, i);
+        if (first) f |= 1u << i;
+    }
+    return f;
+}
+// every value's total reaches exactly one first lane
+__host__ __device__ constexpr bool rr_covers(int Q)
+{
+    const uint32_t f = rr_first_lanes(Q);
+    int holders[16] = {};
+    for (int i = 0; i < 16; ++i)
+        if ((f >> i) & 1u) ++holders[rr_value(Q, i)];
+    bool ok = true;
+    for (int q = 0; q < 16; ++q) ok = ok && holders[q] == (q < Q ? 1 : 0);
+    return ok;
+}
+static_assert(rr_covers(4) && rr_covers(5) && rr_covers(6) && rr_covers(7) && rr_covers(8),
+              "row reduction lane map");
+template <int S, int M> __device__ __forceinline__ void rr_stage(float *v, int li)
+{
+    constexpr int CTRL = S == 0 ? 0x140 : S == 1 ? 0x141 : S == 2 ? 0x4E : 0xB1; // DPP partner of the stage
+    const bool first = rr_keeps_first(S, li);
+#pragma unroll
+    for (int p = 0; p + 1 < M; p += 2) {
+        // the sums first, then the choice: a choice between the two array
+        // elements would become a per-lane index into the array
+        const float a = v[p], b = v[p + 1];
+        const float sa = a + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(a), CTRL, 0xF, 0xF, true));
+        const float sb = b + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(b), CTRL, 0xF, 0xF, true));
+        v[p / 2] = first ? sa : sb;
+    }
+    if constexpr ((M & 1) != 0) {
+        const float a = v[M - 1];
+        v[M / 2] = a + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(a), CTRL, 0xF, 0xF, true));
+    }
+}
+template <int Q> __device__ __forceinline__ float row_reduce(float *v)
+{
+    static_assert(Q >= 1 && Q <= 16, "at most 16 values per row");
+    const int li = threadIdx.x & 15;
+    constexpr int M1 = (Q + 1) / 2, M2 = (M1 + 1) / 2, M3 = (M2 + 1) / 2;
+    rr_stage<0, Q>(v, li);
+    rr_stage<1, M1>(v, li);
+    rr_stage<2, M2>(v, li);
+    rr_stage<3, M3>(v, li);
+    return v[0];
 }
 
 // Pixel of a thread within its tile: each wavefront covers an 8x8 square
@@ -560,11 +631,12 @@ __device__ __forceinline__ void bwd_record(const uint8_t *rec, bool live, int u,
     for (int qv = bwd_values<NL>(); qv < NP; ++qv) val[qv] = 0.0f;
     // whole-wave sums even when few lanes contribute: lane-by-lane LDS atomics
     // serialise badly when a record covers the square
-    wave_sums<NP>(val);
-    if ((threadIdx.x & 15) == 0) { // one lane per row adds its quarter of the wave's sums
-        float *dst = slot + ((threadIdx.x & 63) >> 4) * Q;
-#pragma unroll
-        for (int qv = 0; qv < Q; ++qv) atomicAdd(dst + qv, val[qv]);
+    wave_to_rows<NP>(val);
+    const float total = row_reduce<Q>(val);
+    const int li = threadIdx.x & 15;
+    if ((rr_first_lanes(Q) >> li) & 1u) { // one lane per (row, value) adds the wave's sum
+        const int qv = (int)((rr_map(Q) >> (4 * li)) & 15u);
+        atomicAdd(slot + ((threadIdx.x & 63) >> 4) * Q + qv, total);
     }
 }
 
